@@ -1,0 +1,260 @@
+/*
+ * alae.h -- C ABI of the MI355X exact local-alignment search library (libalae.so).
+ *
+ * Problem (Section 2.1, "Local alignment problem"; Algorithm 1): for a text T
+ * of n characters, a query P of m characters, a scoring scheme
+ * <s_a, s_b, s_g, s_s> and a threshold H, report every pair (query end j,
+ * text end i) whose best local alignment score
+ *
+ *     A(i,j) = max(0, max over x <= i, y <= j of sim(T[x..i], P[y..j]))
+ *
+ * reaches H, together with A(i,j).  sim is the best global alignment score:
+ * a substitution score per aligned column and a gap of r characters costing
+ * s_g + r*s_s (Section 2.1).
+ *
+ * Method (Sections 2.2-5): the text's suffix trie is walked through an
+ * FM-index of the reversed text (Section 5); each trie node X carries the
+ * sparse row of M_X/G_a (Section 2.2) that survives the zero floor, the length
+ * filter (Theorem 1), the score filter (Theorem 2), q-prefix seeding
+ * (Theorem 3) and the domination test (Section 3.2); hits are spread to every
+ * occurrence and the maximum per (j, i) is kept (Algorithm 1).
+ *
+ * Conventions for every entry point:
+ *  - Indices are 0-based and inclusive: query_end in [0, m), text_end in [0, n).
+ *  - Results are sorted ascending by (query_end, text_end), one record per pair.
+ *  - Every call returns an alae_status; on error nothing is written to the
+ *    caller's outputs and alae_last_error() describes the failure.
+ *  - Input buffers stay owned by the caller and are copied; they may be freed
+ *    as soon as the call returns.
+ *  - An index is immutable after it is built or loaded and may be shared by
+ *    threads; a workspace or a server must be used by one thread at a time.
+ *  - No C++ exception crosses this interface.
+ */
+#ifndef ALAE_H
+#define ALAE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    ALAE_OK = 0,
+    ALAE_E_ARG = 1,        /* null pointer, zero length, bad option value            */
+    ALAE_E_ALPHABET = 2,   /* a character outside the alphabet                        */
+    ALAE_E_SCORING = 3,    /* scoring scheme outside the model of Section 2.1         */
+    ALAE_E_TOO_LONG = 4,   /* n or m beyond the library's 32-bit index limits         */
+    ALAE_E_NOMEM = 5,      /* host or device allocation failed                        */
+    ALAE_E_DEVICE = 6,     /* no usable GPU, or a HIP runtime error                   */
+    ALAE_E_ADMISSION = 7,  /* a serving request does not fit the memory budget        */
+    ALAE_E_INTERNAL = 8,   /* an internal consistency check failed                    */
+    ALAE_E_IO = 9,         /* index file could not be read or written                 */
+    ALAE_E_NOT_FOUND = 10  /* unknown request id                                      */
+} alae_status;
+
+typedef enum {
+    ALAE_DNA = 0,     /* A C G T (case-insensitive)                         -> codes 0..3  */
+    ALAE_PROTEIN = 1  /* A R N D C Q E G H I L K M F P S T W Y V (case-ins.) -> codes 0..19 */
+} alae_alphabet;
+
+/*
+ * Scoring scheme (Section 2.1).  With use_matrix == 0 an identical pair
+ * scores sa (> 0) and any other pair sb (< 0).  With use_matrix != 0,
+ * matrix points to sigma*sigma int8 scores, row-major, [text char][query
+ * char]; it must be symmetric with a positive diagonal.  A gap of r
+ * characters costs sg + r*ss with sg <= 0 and ss < 0 (Theorem 1 divides by
+ * ss).  Example: the paper's default <1,-3,-5,-2> is
+ * {0, 1, -3, NULL, -5, -2}.
+ */
+typedef struct {
+    int32_t use_matrix;
+    int32_t sa;
+    int32_t sb;
+    const int8_t *matrix;
+    int32_t sg;
+    int32_t ss;
+} alae_scoring;
+
+/* A result set.  Arrays are allocated by the library; release with alae_hits_free. */
+typedef struct {
+    uint32_t *query_end;
+    uint64_t *text_end;
+    int32_t *score;
+    size_t count;
+} alae_hits;
+
+/* Counters of one search (all optional to read). */
+typedef struct {
+    uint64_t nodes;          /* trie nodes whose row was computed                      */
+    uint64_t entries;        /* DP entries computed (live entries of all rows)         */
+    uint64_t entries_diag;   /* entries fed only by the diagonal (no-gap region, Eq. 3) */
+    uint64_t entries_gap2;   /* entries with two contributing predecessors             */
+    uint64_t entries_gap3;   /* entries with three contributing predecessors           */
+    uint64_t dominated;      /* states removed by the domination test (Section 3.2)    */
+    uint64_t emitted;        /* hit records emitted before the max-merge               */
+    uint64_t hits;           /* distinct (query end, text end) pairs reported          */
+    uint64_t levels;         /* trie depths visited                                    */
+    uint64_t retries;        /* capacity or int16-saturation re-runs                    */
+    uint64_t max_depth;      /* deepest trie node with a live entry                    */
+    double device_ms;        /* device time of the search (events around the work)      */
+    /* traffic and time of the frontier-expansion kernel (roofline accounting) */
+    uint64_t occ_reads;      /* occurrence-block reads (64-byte granules)              */
+    uint64_t sa_reads;       /* suffix-array reads at nodes that become unique          */
+    uint64_t text_reads;     /* text reads of nodes walked along the text               */
+    uint64_t frontier_bytes; /* frontier nodes/entries read + written, hit records      */
+    uint64_t expand_launches;/* launches of the expansion kernel                        */
+    double expand_ms;        /* summed device time of those launches                    */
+    double merge_ms;         /* device time of the sort + max-merge of hit records      */
+} alae_stats;
+
+/* Search options; pass NULL for the defaults. */
+typedef struct {
+    int32_t score_bits;        /* 0 = automatic, 16 or 32                                  */
+    int32_t use_domination;    /* Section 3.2 domination test (default 1)                  */
+    int32_t use_score_filter;  /* Theorem 2 (default 1)                                     */
+    int32_t use_qprefix;       /* Theorem 3 q-prefix seeding (default 1)                    */
+    int32_t reserved0;
+    int32_t reserved1;
+    uint64_t entry_capacity;   /* frontier entries per level buffer, 0 = automatic          */
+    uint64_t hit_capacity;     /* emitted hit records, 0 = automatic                        */
+    alae_stats *stats;         /* filled when not NULL                                      */
+} alae_search_opts;
+
+/* Index options; pass NULL for the defaults. */
+typedef struct {
+    int32_t device;            /* HIP device ordinal used when the index goes to the GPU */
+    int32_t reserved;
+} alae_index_opts;
+
+typedef struct alae_index alae_index;
+typedef struct alae_workspace alae_workspace;
+typedef struct alae_server alae_server;
+
+/* Read-only description of an index. */
+typedef struct {
+    uint64_t n;                /* text length                                    */
+    int32_t sigma;             /* 4 (DNA) or 20 (protein)                        */
+    int32_t alphabet;          /* alae_alphabet                                  */
+    uint64_t C[21];            /* C[c] = 1 + #(text chars < c); C[sigma] = n + 1  */
+    uint64_t dollar_row;       /* BWT row holding the terminator                 */
+    uint64_t host_bytes;       /* bytes held on the host                         */
+    uint64_t device_bytes;     /* bytes held on the device (0 until uploaded)    */
+} alae_index_info;
+
+/*
+ * Build the FM-index of the reversed text with the terminator (Section 5:
+ * the compressed suffix array of T^-1$, positions of T kept).  text holds n
+ * characters of the given alphabet.  The suffix array stores, for every
+ * BWT row, the 0-based text position where that occurrence ends (Section 5,
+ * search (2): the start is the stored end minus |X| plus one); row 0 is the
+ * terminator.  The index lives on the host until a search first needs it on
+ * the device.  Errors: ALAE_E_ARG (null, n == 0), ALAE_E_ALPHABET,
+ * ALAE_E_TOO_LONG (n >= 2^31 - 1), ALAE_E_NOMEM.
+ */
+alae_status alae_index_build(const char *text, size_t n, alae_alphabet alphabet, const alae_index_opts *opts,
+                             alae_index **out);
+
+/* Same, from already encoded characters (codes 0..sigma-1). */
+alae_status alae_index_build_codes(const uint8_t *codes, size_t n, alae_alphabet alphabet,
+                                   const alae_index_opts *opts, alae_index **out);
+
+/* Write / read a versioned binary image of the index.  Errors: ALAE_E_IO, ALAE_E_NOMEM. */
+alae_status alae_index_save(const alae_index *index, const char *path);
+alae_status alae_index_load(const char *path, const alae_index_opts *opts, alae_index **out);
+
+/* Release an index and its device copy.  NULL is ignored. */
+void alae_index_free(alae_index *index);
+
+alae_status alae_index_get_info(const alae_index *index, alae_index_info *out);
+
+/* Copies of the host arrays, for inspection: sa_end has n+1 entries (row 0,
+ * the terminator, holds UINT32_MAX); bwt has n+1 codes (255 for the
+ * terminator). */
+alae_status alae_index_copy_sa(const alae_index *index, uint32_t *sa_end);
+alae_status alae_index_copy_bwt(const alae_index *index, uint8_t *bwt);
+
+/*
+ * Backward search on the host (Section 2.3 and Section 5, search (1)):
+ * the BWT rows [lo, hi] whose occurrences end with `pattern` read forward
+ * in T.  Empty when lo > hi.  Used by tests and by query preparation.
+ */
+alae_status alae_index_range(const alae_index *index, const uint8_t *pattern_codes, size_t len, uint64_t *lo,
+                             uint64_t *hi);
+
+/*
+ * One search of one query (host buffers in and out).  query holds m
+ * characters of the index's alphabet.  On success *out receives the sorted
+ * hit set (library-allocated; free with alae_hits_free).  The index is
+ * uploaded to the device on first use.  Errors: ALAE_E_ARG, ALAE_E_ALPHABET,
+ * ALAE_E_SCORING, ALAE_E_TOO_LONG, ALAE_E_NOMEM, ALAE_E_DEVICE.
+ */
+alae_status alae_search(const alae_index *index, const char *query, size_t m, const alae_scoring *scoring,
+                        int32_t H, const alae_search_opts *opts, alae_hits *out);
+
+/*
+ * k searches in one persistent device launch (the batched form).  outs
+ * receives k result sets, one per query, each exactly what alae_search
+ * would return for that query alone.
+ */
+alae_status alae_search_batch(const alae_index *index, const char *const *queries, const size_t *lens, size_t k,
+                              const alae_scoring *scoring, int32_t H, const alae_search_opts *opts,
+                              alae_hits *outs);
+
+void alae_hits_free(alae_hits *hits);
+
+/*
+ * Device-resident form.  A workspace owns the device buffers a search needs
+ * (frontier levels, hit records, sort buffers) and keeps them between
+ * searches.  alae_search_device takes the query as device memory holding
+ * codes 0..sigma-1 and leaves the sorted result on the device, where
+ * alae_workspace_result returns pointers into the workspace (valid until the
+ * next search on it): keys[k] = (query_end << 32) | text_end, scores[k].
+ * stream is a hipStream_t (NULL = the default stream); the call returns when
+ * the result is complete on that stream.
+ */
+alae_status alae_workspace_create(const alae_index *index, alae_workspace **out);
+void alae_workspace_free(alae_workspace *ws);
+alae_status alae_search_device(alae_workspace *ws, const uint8_t *d_query_codes, size_t m,
+                               const alae_scoring *scoring, int32_t H, const alae_search_opts *opts,
+                               void *stream, size_t *hit_count);
+alae_status alae_workspace_result(const alae_workspace *ws, const uint64_t **d_keys, const int32_t **d_scores,
+                                  size_t *count);
+/* Copy the workspace result into caller-owned device buffers of at least
+ * `count` elements (asynchronous on `stream`, a hipStream_t or NULL). */
+alae_status alae_workspace_copy_result(const alae_workspace *ws, uint64_t *d_keys, int32_t *d_scores, void *stream);
+
+/*
+ * Serving: a request loop that keeps the index resident, admits requests by
+ * the device memory their rows need, runs admitted requests together and
+ * retires each as soon as it is done.  submit copies the query and returns
+ * an id; poll returns ALAE_OK with the result once the request is complete
+ * (wait != 0 blocks), ALAE_E_BUSY-like ALAE_E_NOT_FOUND for an unknown id,
+ * and ALAE_E_ADMISSION if the request can never fit the budget.
+ */
+typedef struct {
+    uint64_t memory_budget;    /* device bytes for in-flight rows, 0 = automatic */
+    int32_t max_inflight;      /* requests on the device at once, 0 = automatic  */
+    int32_t reserved;
+} alae_server_opts;
+
+alae_status alae_server_create(const alae_index *index, const alae_server_opts *opts, alae_server **out);
+alae_status alae_server_submit(alae_server *srv, const char *query, size_t m, const alae_scoring *scoring,
+                               int32_t H, uint64_t *req_id);
+/* Returns ALAE_OK and fills *out when done; ALAE_E_BUSY is not used: a pending
+ * request with wait == 0 returns ALAE_OK with out->count == SIZE_MAX. */
+alae_status alae_server_poll(alae_server *srv, uint64_t req_id, int wait, alae_hits *out);
+void alae_server_destroy(alae_server *srv);
+
+/* Message for the last failing call on this thread. */
+const char *alae_last_error(void);
+
+/* Library version string. */
+const char *alae_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ALAE_H */

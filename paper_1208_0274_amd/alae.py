@@ -1,0 +1,346 @@
+"""ctypes binding of ``libalae.so`` (the C ABI in ``include/alae.h``).
+
+Argument marshalling only: every step of a search runs in the library's HIP
+kernels.  The library is loaded on import; a missing library raises
+immediately (there is no fallback of any kind).  PyTorch is used only for
+device buffers and streams in :meth:`Workspace.search_device`.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libalae.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1208_0274_amd.build`")
+
+# PyTorch-ROCm ships its own HIP runtime under a different file name.  Loading
+# torch first makes libalae bind to that same runtime (matching soname), so
+# device pointers and streams are shared and only one runtime owns the GPU.
+try:  # pragma: no cover - torch is part of the supported environment
+    import torch  # noqa: F401
+except ImportError:  # ctypes-only use (index building, validation) still works
+    torch = None
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+DNA, PROTEIN = 0, 1
+ALPHABETS = {"dna": DNA, "protein": PROTEIN}
+STATUS = {0: "ALAE_OK", 1: "ALAE_E_ARG", 2: "ALAE_E_ALPHABET", 3: "ALAE_E_SCORING", 4: "ALAE_E_TOO_LONG",
+          5: "ALAE_E_NOMEM", 6: "ALAE_E_DEVICE", 7: "ALAE_E_ADMISSION", 8: "ALAE_E_INTERNAL", 9: "ALAE_E_IO",
+          10: "ALAE_E_NOT_FOUND"}
+
+
+class AlaeError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        msg = _lib.alae_last_error().decode(errors="replace")
+        super().__init__(f"{where}: {STATUS.get(status, status)}: {msg}")
+
+
+class Scoring(ctypes.Structure):
+    _fields_ = [("use_matrix", ctypes.c_int32), ("sa", ctypes.c_int32), ("sb", ctypes.c_int32),
+                ("matrix", ctypes.POINTER(ctypes.c_int8)), ("sg", ctypes.c_int32), ("ss", ctypes.c_int32)]
+
+
+class Hits(ctypes.Structure):
+    _fields_ = [("query_end", ctypes.POINTER(ctypes.c_uint32)), ("text_end", ctypes.POINTER(ctypes.c_uint64)),
+                ("score", ctypes.POINTER(ctypes.c_int32)), ("count", ctypes.c_size_t)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("nodes", ctypes.c_uint64), ("entries", ctypes.c_uint64), ("entries_diag", ctypes.c_uint64),
+                ("entries_gap2", ctypes.c_uint64), ("entries_gap3", ctypes.c_uint64),
+                ("dominated", ctypes.c_uint64), ("emitted", ctypes.c_uint64), ("hits", ctypes.c_uint64),
+                ("levels", ctypes.c_uint64), ("retries", ctypes.c_uint64), ("max_depth", ctypes.c_uint64),
+                ("device_ms", ctypes.c_double), ("occ_reads", ctypes.c_uint64), ("sa_reads", ctypes.c_uint64),
+                ("text_reads", ctypes.c_uint64), ("frontier_bytes", ctypes.c_uint64),
+                ("expand_launches", ctypes.c_uint64), ("expand_ms", ctypes.c_double), ("merge_ms", ctypes.c_double)]
+
+    def expand_alg_bytes(self) -> int:
+        """Algorithmic bytes of the expansion kernel: one 64-byte granule per random
+        occ/SA/text read plus the frontier records it must read and write."""
+        return 64 * (self.occ_reads + self.sa_reads + self.text_reads) + self.frontier_bytes
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class SearchOpts(ctypes.Structure):
+    _fields_ = [("score_bits", ctypes.c_int32), ("use_domination", ctypes.c_int32),
+                ("use_score_filter", ctypes.c_int32), ("use_qprefix", ctypes.c_int32),
+                ("reserved0", ctypes.c_int32), ("reserved1", ctypes.c_int32),
+                ("entry_capacity", ctypes.c_uint64), ("hit_capacity", ctypes.c_uint64),
+                ("stats", ctypes.POINTER(Stats))]
+
+
+class IndexOpts(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class IndexInfo(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_uint64), ("sigma", ctypes.c_int32), ("alphabet", ctypes.c_int32),
+                ("C", ctypes.c_uint64 * 21), ("dollar_row", ctypes.c_uint64), ("host_bytes", ctypes.c_uint64),
+                ("device_bytes", ctypes.c_uint64)]
+
+
+_vp = ctypes.c_void_p
+_u8p = ctypes.POINTER(ctypes.c_uint8)
+_st = ctypes.c_int
+
+
+def _sig(name, res, *args):
+    f = getattr(_lib, name)
+    f.restype = res
+    f.argtypes = list(args)
+    return f
+
+
+_sig("alae_last_error", ctypes.c_char_p)
+_sig("alae_version", ctypes.c_char_p)
+_sig("alae_index_build", _st, ctypes.c_char_p, ctypes.c_size_t, ctypes.c_int, ctypes.POINTER(IndexOpts),
+     ctypes.POINTER(_vp))
+_sig("alae_index_build_codes", _st, _u8p, ctypes.c_size_t, ctypes.c_int, ctypes.POINTER(IndexOpts),
+     ctypes.POINTER(_vp))
+_sig("alae_index_save", _st, _vp, ctypes.c_char_p)
+_sig("alae_index_load", _st, ctypes.c_char_p, ctypes.POINTER(IndexOpts), ctypes.POINTER(_vp))
+_sig("alae_index_free", None, _vp)
+_sig("alae_index_get_info", _st, _vp, ctypes.POINTER(IndexInfo))
+_sig("alae_index_copy_sa", _st, _vp, ctypes.POINTER(ctypes.c_uint32))
+_sig("alae_index_copy_bwt", _st, _vp, _u8p)
+_sig("alae_index_range", _st, _vp, _u8p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_uint64),
+     ctypes.POINTER(ctypes.c_uint64))
+_sig("alae_search", _st, _vp, ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(Scoring), ctypes.c_int32,
+     ctypes.POINTER(SearchOpts), ctypes.POINTER(Hits))
+_sig("alae_search_batch", _st, _vp, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(ctypes.c_size_t),
+     ctypes.c_size_t, ctypes.POINTER(Scoring), ctypes.c_int32, ctypes.POINTER(SearchOpts), ctypes.POINTER(Hits))
+_sig("alae_hits_free", None, ctypes.POINTER(Hits))
+_sig("alae_workspace_create", _st, _vp, ctypes.POINTER(_vp))
+_sig("alae_workspace_free", None, _vp)
+_sig("alae_search_device", _st, _vp, _vp, ctypes.c_size_t, ctypes.POINTER(Scoring), ctypes.c_int32,
+     ctypes.POINTER(SearchOpts), _vp, ctypes.POINTER(ctypes.c_size_t))
+_sig("alae_workspace_result", _st, _vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(ctypes.c_size_t))
+_sig("alae_workspace_copy_result", _st, _vp, _vp, _vp, _vp)
+
+
+def _check(status, where):
+    if status != 0:
+        raise AlaeError(status, where)
+
+
+def version() -> str:
+    return _lib.alae_version().decode()
+
+
+def make_scoring(sa=1, sb=-3, sg=-5, ss=-2, matrix=None):
+    """Scoring of Section 2.1; `matrix` (sigma x sigma, symmetric) switches to matrix mode."""
+    sc = Scoring()
+    sc.sa, sc.sb, sc.sg, sc.ss = int(sa), int(sb), int(sg), int(ss)
+    if matrix is not None:
+        arr = np.ascontiguousarray(np.asarray(matrix, dtype=np.int8))
+        sc.use_matrix = 1
+        sc.matrix = arr.ctypes.data_as(ctypes.POINTER(ctypes.c_int8))
+        sc._keep = arr  # keep the buffer alive with the struct
+    else:
+        sc.use_matrix = 0
+        sc.matrix = None
+    return sc
+
+
+def make_opts(stats: Stats | None = None, use_domination=True, use_score_filter=True, use_qprefix=True,
+              entry_capacity=0, hit_capacity=0, score_bits=0):
+    o = SearchOpts()
+    o.score_bits = int(score_bits)
+    o.use_domination = 1 if use_domination else 0
+    o.use_score_filter = 1 if use_score_filter else 0
+    o.use_qprefix = 1 if use_qprefix else 0
+    o.entry_capacity = int(entry_capacity)
+    o.hit_capacity = int(hit_capacity)
+    o.stats = ctypes.pointer(stats) if stats is not None else None
+    return o
+
+
+def _alpha(alphabet) -> int:
+    if isinstance(alphabet, str):
+        return ALPHABETS[alphabet.lower()]
+    return int(alphabet)
+
+
+def _decode_letters(alphabet: int) -> bytes:
+    return b"ACGT" if alphabet == DNA else b"ARNDCQEGHILKMFPSTWYV"
+
+
+def codes_to_bytes(codes: np.ndarray, alphabet) -> bytes:
+    lut = np.frombuffer(_decode_letters(_alpha(alphabet)), dtype=np.uint8)
+    return lut[np.asarray(codes, dtype=np.uint8)].tobytes()
+
+
+class Index:
+    """The FM-index of the reversed text (Section 5)."""
+
+    def __init__(self, handle, alphabet: int):
+        self._h = _vp(handle)
+        self.alphabet = alphabet
+
+    @classmethod
+    def build(cls, text, alphabet="dna", device: int = 0):
+        """text: str/bytes of letters, or a uint8 array of codes."""
+        a = _alpha(alphabet)
+        opts = IndexOpts(device, 0)
+        h = _vp()
+        if isinstance(text, np.ndarray):
+            arr = np.ascontiguousarray(text, dtype=np.uint8)
+            _check(_lib.alae_index_build_codes(arr.ctypes.data_as(_u8p), arr.shape[0], a, ctypes.byref(opts),
+                                               ctypes.byref(h)), "alae_index_build_codes")
+        else:
+            b = text.encode() if isinstance(text, str) else bytes(text)
+            _check(_lib.alae_index_build(b, len(b), a, ctypes.byref(opts), ctypes.byref(h)), "alae_index_build")
+        return cls(h.value, a)
+
+    @classmethod
+    def load(cls, path: str, device: int = 0):
+        opts = IndexOpts(device, 0)
+        h = _vp()
+        _check(_lib.alae_index_load(path.encode(), ctypes.byref(opts), ctypes.byref(h)), "alae_index_load")
+        idx = cls(h.value, 0)
+        idx.alphabet = idx.info()["alphabet"]
+        return idx
+
+    def save(self, path: str):
+        _check(_lib.alae_index_save(self._h, path.encode()), "alae_index_save")
+
+    def info(self) -> dict:
+        inf = IndexInfo()
+        _check(_lib.alae_index_get_info(self._h, ctypes.byref(inf)), "alae_index_get_info")
+        return {"n": inf.n, "sigma": inf.sigma, "alphabet": inf.alphabet, "C": list(inf.C)[:inf.sigma + 1],
+                "dollar_row": inf.dollar_row, "host_bytes": inf.host_bytes, "device_bytes": inf.device_bytes}
+
+    def sa_end(self) -> np.ndarray:
+        n = self.info()["n"]
+        out = np.empty(n + 1, dtype=np.uint32)
+        _check(_lib.alae_index_copy_sa(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))),
+               "alae_index_copy_sa")
+        return out
+
+    def bwt(self) -> np.ndarray:
+        n = self.info()["n"]
+        out = np.empty(n + 1, dtype=np.uint8)
+        _check(_lib.alae_index_copy_bwt(self._h, out.ctypes.data_as(_u8p)), "alae_index_copy_bwt")
+        return out
+
+    def range(self, pattern_codes) -> tuple[int, int]:
+        arr = np.ascontiguousarray(np.asarray(pattern_codes, dtype=np.uint8))
+        lo, hi = ctypes.c_uint64(), ctypes.c_uint64()
+        _check(_lib.alae_index_range(self._h, arr.ctypes.data_as(_u8p), arr.shape[0], ctypes.byref(lo),
+                                     ctypes.byref(hi)), "alae_index_range")
+        return int(lo.value), int(hi.value)
+
+    def free(self):
+        if self._h:
+            _lib.alae_index_free(self._h)
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def _hits_to_numpy(h: Hits):
+    n = int(h.count)
+    if n == 0:
+        return (np.zeros(0, np.int64), np.zeros(0, np.int64), np.zeros(0, np.int64))
+    j = np.ctypeslib.as_array(h.query_end, shape=(n,)).astype(np.int64)
+    t = np.ctypeslib.as_array(h.text_end, shape=(n,)).astype(np.int64)
+    s = np.ctypeslib.as_array(h.score, shape=(n,)).astype(np.int64)
+    return j, t, s
+
+
+def _query_bytes(query, alphabet: int) -> bytes:
+    if isinstance(query, np.ndarray):
+        return codes_to_bytes(query, alphabet)
+    return query.encode() if isinstance(query, str) else bytes(query)
+
+
+def search(index: Index, query, H: int, scoring: Scoring | None = None, stats: Stats | None = None, **opt):
+    """One search; returns (query_end, text_end, score) int64 arrays sorted by (query_end, text_end)."""
+    sc = scoring if scoring is not None else make_scoring()
+    q = _query_bytes(query, index.alphabet)
+    opts = make_opts(stats=stats, **opt)
+    h = Hits()
+    _check(_lib.alae_search(index._h, q, len(q), ctypes.byref(sc), int(H), ctypes.byref(opts), ctypes.byref(h)),
+           "alae_search")
+    try:
+        return _hits_to_numpy(h)
+    finally:
+        _lib.alae_hits_free(ctypes.byref(h))
+
+
+def search_batch(index: Index, queries, H: int, scoring: Scoring | None = None, stats: Stats | None = None, **opt):
+    """k searches in one call; returns a list of (query_end, text_end, score) triples."""
+    sc = scoring if scoring is not None else make_scoring()
+    qs = [_query_bytes(q, index.alphabet) for q in queries]
+    k = len(qs)
+    arr = (ctypes.c_char_p * k)(*qs)
+    lens = (ctypes.c_size_t * k)(*[len(q) for q in qs])
+    outs = (Hits * k)()
+    opts = make_opts(stats=stats, **opt)
+    _check(_lib.alae_search_batch(index._h, arr, lens, k, ctypes.byref(sc), int(H), ctypes.byref(opts), outs),
+           "alae_search_batch")
+    res = []
+    for i in range(k):
+        res.append(_hits_to_numpy(outs[i]))
+        _lib.alae_hits_free(ctypes.byref(outs[i]))
+    return res
+
+
+class Workspace:
+    """Device buffers reused across searches; queries and results stay in device memory."""
+
+    def __init__(self, index: Index):
+        self.index = index
+        self._h = _vp()
+        _check(_lib.alae_workspace_create(index._h, ctypes.byref(self._h)), "alae_workspace_create")
+
+    def search_device(self, d_query, H: int, scoring: Scoring | None = None, stats: Stats | None = None,
+                      stream=None, **opt) -> int:
+        """d_query: a torch uint8 tensor of codes on the GPU.  Returns the hit count."""
+        sc = scoring if scoring is not None else make_scoring()
+        opts = make_opts(stats=stats, **opt)
+        cnt = ctypes.c_size_t()
+        sptr = _vp(stream.cuda_stream) if stream is not None else None
+        _check(_lib.alae_search_device(self._h, _vp(d_query.data_ptr()), int(d_query.numel()), ctypes.byref(sc),
+                                       int(H), ctypes.byref(opts), sptr, ctypes.byref(cnt)), "alae_search_device")
+        return int(cnt.value)
+
+    def result_torch(self, stream=None):
+        """Copies of the sorted result as torch tensors on the device: (keys int64, scores int32)."""
+        import torch
+
+        k, s, n = _vp(), _vp(), ctypes.c_size_t()
+        _check(_lib.alae_workspace_result(self._h, ctypes.byref(k), ctypes.byref(s), ctypes.byref(n)),
+               "alae_workspace_result")
+        cnt = int(n.value)
+        keys = torch.empty(cnt, dtype=torch.int64, device="cuda")
+        scores = torch.empty(cnt, dtype=torch.int32, device="cuda")
+        if cnt:
+            sptr = _vp(stream.cuda_stream) if stream is not None else None
+            _check(_lib.alae_workspace_copy_result(self._h, _vp(keys.data_ptr()), _vp(scores.data_ptr()), sptr),
+                   "alae_workspace_copy_result")
+        return keys, scores
+
+    def free(self):
+        if self._h:
+            _lib.alae_workspace_free(self._h)
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass

@@ -1,0 +1,32 @@
+// Host-callable device primitives written for this library: exclusive scan,
+// LSD radix sort of (64-bit key, 32-bit value) pairs, and the max-merge of
+// sorted hit records.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace alae {
+
+// Scratch needed by scan_exclusive_u32 for n elements (in uint32 words).
+uint64_t scan_scratch_words(uint64_t n);
+// out[i] = sum of in[0..i-1]; in and out may alias.  tmp holds scan_scratch_words(n) words.
+hipError_t scan_exclusive_u32(const uint32_t *in, uint32_t *out, uint64_t n, uint32_t *tmp, hipStream_t s);
+
+// Scratch (uint32 words) for radix_sort_pairs on n elements.
+uint64_t radix_scratch_words(uint64_t n);
+// Stable LSD radix sort by the low `bits` bits of the keys, 8 bits per pass.
+// (keys, vals) and (keys_alt, vals_alt) are ping-pong buffers of n elements;
+// on return *result_in_alt says which pair holds the sorted data.
+hipError_t radix_sort_pairs(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, uint32_t *vals_alt, uint64_t n,
+                            int bits, uint32_t *scratch, bool *result_in_alt, hipStream_t s);
+
+// Given hit records sorted by key, keep one record per key with the largest
+// score (Algorithm 1's "keep the larger score").  flags/pos hold n+1 words
+// each, tmp scan_scratch_words(n+1).  *count_dev receives the distinct count.
+hipError_t max_merge_sorted(const uint64_t *keys, const uint32_t *scores, uint64_t n, uint64_t *out_keys,
+                            uint32_t *out_scores, uint32_t *flags, uint32_t *pos, uint32_t *tmp,
+                            hipStream_t s);
+
+}  // namespace alae

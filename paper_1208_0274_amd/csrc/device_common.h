@@ -1,0 +1,127 @@
+// Device-side data formats and helpers of the search path (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "alae_internal.h"
+
+namespace alae {
+
+// "Dead" score for a state that does not exist (-infinity in Section 2.2).
+// Far enough from INT32_MIN that adding a few penalties never wraps.
+constexpr int32_t kNeg = -(1 << 29);
+
+// A trie node of the frontier.  While the node has several occurrences it is
+// the BWT row range [lo, hi] of its string (Section 5).  Once it has one
+// occurrence, lo holds kUniqueBit | e, where e is the 0-based text position
+// where that occurrence ends, and the subtree is walked along the text.
+constexpr uint32_t kUniqueBit = 0x80000000u;
+struct Node {
+    uint32_t lo;
+    uint32_t hi;
+    uint32_t off;  // first entry of the row in the level's entry buffer
+    uint32_t len;  // number of entries of the row
+};
+static_assert(sizeof(Node) == 16, "node record is 16 bytes");
+
+// One live entry of a sparse DP row (Section 2.2): query column (0-based end),
+// M_X and G_a at this column, and the start column y of the alignment that
+// gives each of the two values (used by the domination test, Section 3.2).
+struct Entry {
+    uint32_t col;
+    int32_t M;
+    int32_t Ga;
+    uint32_t yM;
+    uint32_t yGa;
+};
+static_assert(sizeof(Entry) == 20, "entry record is 20 bytes");
+
+// Everything a kernel needs about the index and the query.
+struct SearchArgs {
+    const uint8_t *occ;   // occurrence blocks
+    const uint32_t *sa;   // text end of every BWT row
+    const uint8_t *text;  // text codes
+    const int8_t *prof;   // query profile: prof[c*m + j] = s(c, P[j])
+    const int32_t *U;     // U[j]: largest total score the columns after j can add
+    uint32_t n;
+    uint32_t dollar_row;
+    uint32_t m;
+    int32_t sigma;
+    int32_t sg;
+    int32_t ss;
+    int32_t H;
+    int32_t smax;
+    int32_t lmax;         // Equation 1
+    int32_t use_score_filter;
+    int32_t use_domination;
+    int32_t dom_reach;    // longest left extension tried by the domination test
+    uint32_t C[21];
+};
+
+// occ(c, i) for the four DNA codes at once: counts of each code in BWT[0..i].
+// i may be -1 (all zero).  One 64-byte block read.
+__device__ inline void occ4_dna(const SearchArgs &a, int64_t i, uint32_t out[4]) {
+    if (i < 0) {
+        out[0] = out[1] = out[2] = out[3] = 0;
+        return;
+    }
+    const uint64_t b = (uint64_t)i / kDnaBlockChars;
+    const int k = (int)((uint64_t)i - b * kDnaBlockChars) + 1;  // chars of this block to count
+    const uint4 *p = reinterpret_cast<const uint4 *>(a.occ + b * 64);
+    uint4 q0 = p[0], q1 = p[1], q2 = p[2], q3 = p[3];
+    const uint32_t w[12] = {q1.x, q1.y, q1.z, q1.w, q2.x, q2.y, q2.z, q2.w, q3.x, q3.y, q3.z, q3.w};
+    uint32_t c1 = 0, c2 = 0, c3 = 0;
+    const int full = k >> 4;
+    const int rem = k & 15;
+#pragma unroll
+    for (int t = 0; t < 12; ++t) {
+        uint32_t mask;
+        if (t < full)
+            mask = 0x55555555u;
+        else if (t == full && rem)
+            mask = 0x55555555u & ((1u << (2 * rem)) - 1u);
+        else
+            mask = 0u;
+        const uint32_t lo = w[t] & mask;
+        const uint32_t hi = (w[t] >> 1) & mask;
+        c1 += __popc(lo & ~hi);
+        c2 += __popc(hi & ~lo);
+        c3 += __popc(lo & hi);
+    }
+    uint32_t c0 = (uint32_t)k - c1 - c2 - c3;
+    const uint64_t bstart = b * kDnaBlockChars;
+    if ((uint64_t)a.dollar_row >= bstart && (uint64_t)a.dollar_row <= (uint64_t)i) c0 -= 1;
+    out[0] = q0.x + c0;
+    out[1] = q0.y + c1;
+    out[2] = q0.z + c2;
+    out[3] = q0.w + c3;
+}
+
+// occ(c, i) for one code of a byte-per-character block (protein alphabet).
+__device__ inline uint32_t occ1_gen(const SearchArgs &a, int c, int64_t i) {
+    if (i < 0) return 0;
+    const uint64_t b = (uint64_t)i / kGenBlockChars;
+    const int k = (int)((uint64_t)i - b * kGenBlockChars) + 1;
+    const uint32_t *blk = reinterpret_cast<const uint32_t *>(a.occ + b * 128);
+    uint32_t cnt = blk[c];
+    const uint32_t pat = 0x01010101u * (uint32_t)c;
+#pragma unroll
+    for (int t = 0; t < 12; ++t) {
+        const int first = t * 4;
+        if (first >= k) break;
+        const uint32_t v = blk[20 + t] ^ pat;  // zero bytes where the char equals c
+        uint32_t z = (v & 0x7F7F7F7Fu) + 0x7F7F7F7Fu;
+        z = ~(z | v | 0x7F7F7F7Fu);  // 0x80 in each zero byte
+        const int take = k - first;
+        if (take < 4) z &= (1u << (8 * take)) - 1u;
+        cnt += __popc(z);
+    }
+    return cnt;
+}
+
+__device__ inline int32_t imax(int32_t a, int32_t b) { return a > b ? a : b; }
+__device__ inline int32_t imin(int32_t a, int32_t b) { return a < b ? a : b; }
+
+}  // namespace alae

@@ -1,0 +1,239 @@
+// Device primitives: exclusive scan, stable LSD radix sort, max-merge of hits.
+// Written for wave64 (gfx950): ballots are 64-bit and a 256-thread block holds
+// four waves.
+#include <hip/hip_runtime.h>
+
+#include "device_algos.h"
+
+namespace alae {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kItems = 8;
+constexpr int kTile = kThreads * kItems;  // elements per block
+constexpr int kWaves = kThreads / 64;
+
+__device__ inline uint32_t wave_inclusive_scan(uint32_t v) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        uint32_t o = __shfl_up(v, d, 64);
+        if (lane >= d) v += o;
+    }
+    return v;
+}
+
+// Exclusive scan of the 256 per-thread totals of a block; returns the prefix
+// for this thread and writes the block total to *total.
+__device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t *total) {
+    __shared__ uint32_t wsum[kWaves];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    uint32_t inc = wave_inclusive_scan(v);
+    if (lane == 63) wsum[wave] = inc;
+    __syncthreads();
+    uint32_t before = 0, all = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) {
+        if (w < wave) before += wsum[w];
+        all += wsum[w];
+    }
+    __syncthreads();
+    *total = all;
+    return before + inc - v;
+}
+
+__global__ void __launch_bounds__(kThreads) scan_tiles(const uint32_t *in, uint32_t *out, uint64_t n,
+                                                       uint32_t *tile_sums) {
+    const uint64_t base = (uint64_t)blockIdx.x * kTile + (uint64_t)threadIdx.x * kItems;
+    uint32_t v[kItems];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+        uint64_t i = base + k;
+        v[k] = i < n ? in[i] : 0u;
+        sum += v[k];
+    }
+    uint32_t total;
+    uint32_t run = block_exclusive_scan(sum, &total);
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+        uint64_t i = base + k;
+        if (i < n) out[i] = run;
+        run += v[k];
+    }
+    if (threadIdx.x == 0) tile_sums[blockIdx.x] = total;
+}
+
+__global__ void __launch_bounds__(kThreads) scan_add(uint32_t *out, uint64_t n, const uint32_t *tile_prefix) {
+    const uint32_t add = tile_prefix[blockIdx.x];
+    const uint64_t base = (uint64_t)blockIdx.x * kTile + (uint64_t)threadIdx.x * kItems;
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+        uint64_t i = base + k;
+        if (i < n) out[i] += add;
+    }
+}
+
+__global__ void __launch_bounds__(kThreads) radix_hist(const uint64_t *keys, uint64_t n, int shift,
+                                                       uint32_t *hist, uint32_t nblocks) {
+    __shared__ uint32_t cnt[256];
+    cnt[threadIdx.x] = 0;
+    __syncthreads();
+    const uint64_t base = (uint64_t)blockIdx.x * kTile;
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+        uint64_t i = base + (uint64_t)r * kThreads + threadIdx.x;
+        if (i < n) atomicAdd(&cnt[(keys[i] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    hist[(uint64_t)threadIdx.x * nblocks + blockIdx.x] = cnt[threadIdx.x];
+}
+
+// Stable scatter: elements of a tile are ranked in index order (round, wave,
+// lane); offs holds the exclusive scan of the digit-major histogram.
+__global__ void __launch_bounds__(kThreads) radix_scatter(const uint64_t *kin, const uint32_t *vin, uint64_t *kout,
+                                                          uint32_t *vout, uint64_t n, int shift,
+                                                          const uint32_t *offs, uint32_t nblocks) {
+    __shared__ uint32_t run[256];
+    __shared__ uint32_t wcnt[kWaves][256];
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6;
+    const int lane = tid & 63;
+    run[tid] = offs[(uint64_t)tid * nblocks + blockIdx.x];
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) wcnt[w][tid] = 0;
+    __syncthreads();
+    const uint64_t base = (uint64_t)blockIdx.x * kTile;
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    for (int r = 0; r < kItems; ++r) {
+        const uint64_t i = base + (uint64_t)r * kThreads + tid;
+        const bool valid = i < n;
+        const uint64_t k = valid ? kin[i] : 0ull;
+        const uint32_t v = valid ? vin[i] : 0u;
+        const uint32_t d = (uint32_t)(k >> shift) & 255u;
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const bool bit = (d >> b) & 1u;
+            const uint64_t bal = __ballot(bit);
+            peers &= bit ? bal : ~bal;
+        }
+        const uint32_t rank = (uint32_t)__popcll(peers & below);
+        if (valid && rank == 0) wcnt[wave][d] = (uint32_t)__popcll(peers);
+        __syncthreads();
+        if (valid) {
+            uint32_t pos = run[d] + rank;
+            for (int w = 0; w < wave; ++w) pos += wcnt[w][d];
+            kout[pos] = k;
+            vout[pos] = v;
+        }
+        __syncthreads();
+        uint32_t add = 0;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) {
+            add += wcnt[w][tid];
+            wcnt[w][tid] = 0;
+        }
+        run[tid] += add;
+        __syncthreads();
+    }
+}
+
+__global__ void merge_flags(const uint64_t *keys, uint64_t n, uint32_t *flags) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) flags[i] = (i == 0 || keys[i] != keys[i - 1]) ? 1u : 0u;
+    if (i == n) flags[i] = 0u;
+}
+
+__global__ void merge_write(const uint64_t *keys, const uint32_t *scores, uint64_t n, const uint32_t *flags,
+                            const uint32_t *pos, uint64_t *out_keys, uint32_t *out_scores) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n || !flags[i]) return;
+    const uint64_t key = keys[i];
+    int32_t best = (int32_t)scores[i];
+    for (uint64_t j = i + 1; j < n && keys[j] == key; ++j) {
+        int32_t s = (int32_t)scores[j];
+        best = s > best ? s : best;
+    }
+    out_keys[pos[i]] = key;
+    out_scores[pos[i]] = (uint32_t)best;
+}
+
+uint64_t ceil_div(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
+
+}  // namespace
+
+uint64_t scan_scratch_words(uint64_t n) {
+    uint64_t words = 0;
+    while (n > 1) {
+        n = ceil_div(n, kTile);
+        words += n + 1;
+    }
+    return words + 2;
+}
+
+hipError_t scan_exclusive_u32(const uint32_t *in, uint32_t *out, uint64_t n, uint32_t *tmp, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    const uint64_t tiles = ceil_div(n, kTile);
+    uint32_t *sums = tmp;
+    scan_tiles<<<(uint32_t)tiles, kThreads, 0, s>>>(in, out, n, sums);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || tiles == 1) return e;
+    e = scan_exclusive_u32(sums, sums, tiles, tmp + tiles + 1, s);
+    if (e != hipSuccess) return e;
+    scan_add<<<(uint32_t)tiles, kThreads, 0, s>>>(out, n, sums);
+    return hipGetLastError();
+}
+
+uint64_t radix_scratch_words(uint64_t n) {
+    const uint64_t blocks = ceil_div(n ? n : 1, kTile);
+    const uint64_t hist = 256 * blocks;
+    return hist + scan_scratch_words(hist);
+}
+
+hipError_t radix_sort_pairs(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, uint32_t *vals_alt, uint64_t n,
+                            int bits, uint32_t *scratch, bool *result_in_alt, hipStream_t s) {
+    *result_in_alt = false;
+    if (n <= 1 || bits <= 0) return hipSuccess;
+    const uint32_t blocks = (uint32_t)ceil_div(n, kTile);
+    uint32_t *hist = scratch;
+    uint32_t *tmp = scratch + 256ull * blocks;
+    uint64_t *kin = keys, *kout = keys_alt;
+    uint32_t *vin = vals, *vout = vals_alt;
+    bool alt = false;
+    for (int shift = 0; shift < bits; shift += 8) {
+        radix_hist<<<blocks, kThreads, 0, s>>>(kin, n, shift, hist, blocks);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        e = scan_exclusive_u32(hist, hist, 256ull * blocks, tmp, s);
+        if (e != hipSuccess) return e;
+        radix_scatter<<<blocks, kThreads, 0, s>>>(kin, vin, kout, vout, n, shift, hist, blocks);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        std::swap(kin, kout);
+        std::swap(vin, vout);
+        alt = !alt;
+    }
+    *result_in_alt = alt;
+    return hipSuccess;
+}
+
+hipError_t max_merge_sorted(const uint64_t *keys, const uint32_t *scores, uint64_t n, uint64_t *out_keys,
+                            uint32_t *out_scores, uint32_t *flags, uint32_t *pos, uint32_t *tmp,
+                            hipStream_t s) {
+    const uint32_t threads = 256;
+    const uint32_t grid = (uint32_t)ceil_div(n + 1, threads);
+    merge_flags<<<grid, threads, 0, s>>>(keys, n, flags);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = scan_exclusive_u32(flags, pos, n + 1, tmp, s);
+    if (e != hipSuccess) return e;
+    if (n == 0) return hipSuccess;
+    merge_write<<<(uint32_t)ceil_div(n, threads), threads, 0, s>>>(keys, scores, n, flags, pos, out_keys,
+                                                                   out_scores);
+    return hipGetLastError();
+}
+
+}  // namespace alae

@@ -1,0 +1,151 @@
+"""FM-index of the reversed text (host side): paper examples and brute force."""
+import os
+import tempfile
+
+import numpy as np
+import pytest
+
+from paper_1208_0274_amd import alae, synth
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+NOPOS = 0xFFFFFFFF
+
+
+def golden():
+    d = {}
+    with open(os.path.join(HERE, "golden", "index_gctagc.txt")) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            k, *v = line.split()
+            d[k] = v
+    return d
+
+
+def test_paper_forward_example():
+    """Section 2.3: indexing reverse(T) builds the suffix array of T$ itself, so the
+    printed SA {7,4,6,2,5,1,3} and BWT CTGGA$C of GCTAGC$ must come out."""
+    g = golden()
+    T = g["forward_text"][0]
+    idx = alae.Index.build(T[::-1], "dna")
+    n = len(T)
+    # sa_end of the index over R = reverse(T) is n-1-SA_{T$}(0-based); the '$' row holds NOPOS
+    sa = idx.sa_end()
+    fwd = [int(x) - 1 for x in g["forward_sa"]]  # 0-based SA of T$
+    expect = [NOPOS if p == n else n - 1 - p for p in fwd]
+    assert sa.tolist() == expect
+    bwt = idx.bwt()
+    letters = "".join("$" if c == 255 else "ACGT"[c] for c in bwt)
+    assert letters == g["forward_bwt"][0]
+
+
+def test_paper_reversed_example():
+    """Section 5 search (2): T=GCTAGC, reversed SA {0,4,2,6,1,5,3} (positions of T,
+    $ at 0); GC lies in rows [2,3] and starts at 1 and 5 (1-based)."""
+    g = golden()
+    idx = alae.Index.build("GCTAGC", "dna")
+    sa = idx.sa_end()
+    # our rows store 0-based end positions; the paper's 1-based position p is end p-1, $ is row 0
+    paper = [int(x) for x in g["reversed_sa"]]
+    assert sa.tolist() == [NOPOS if p == 0 else p - 1 for p in paper]
+    lo, hi = idx.range(synth_codes("GC"))
+    assert (lo, hi) == tuple(int(x) for x in g["search_gc_rows"])
+    starts = sorted(int(sa[h]) - 2 + 1 + 1 for h in range(lo, hi + 1))  # 1-based starts
+    assert starts == [int(x) for x in g["search_gc_starts"]]
+
+
+def synth_codes(s):
+    return np.array(["ACGT".index(c) for c in s], dtype=np.uint8)
+
+
+def naive_reversed_sa(T):
+    """Sort the suffixes of reverse(T)+'$' directly; return 0-based text ends."""
+    n = len(T)
+    S = [int(c) + 1 for c in T[::-1]] + [0]
+    order = sorted(range(n + 1), key=lambda k: S[k:])
+    return [NOPOS if k == n else n - 1 - k for k in order]
+
+
+@pytest.mark.parametrize("seed,sigma,n", [(0, 4, 1), (1, 4, 2), (2, 4, 50), (3, 4, 700), (4, 2, 600),
+                                          (5, 1, 300), (6, 20, 500), (7, 4, 2000), (8, 3, 1500)])
+def test_suffix_array_vs_naive(seed, sigma, n):
+    rng = np.random.default_rng(seed)
+    T = rng.integers(0, sigma, size=n).astype(np.uint8)
+    if seed == 8:  # periodic text: deep SA-IS recursion
+        T = np.tile(np.array([0, 1, 2, 0, 1], dtype=np.uint8), n // 5)
+    alpha = "protein" if sigma > 4 else "dna"
+    idx = alae.Index.build(T, alpha)
+    assert idx.sa_end().tolist() == naive_reversed_sa(T.tolist())
+    info = idx.info()
+    counts = np.bincount(T, minlength=idx.info()["sigma"])
+    assert info["C"] == [1 + int(counts[:c].sum()) for c in range(info["sigma"] + 1)]
+    # BWT row h holds the text character right after the occurrence end ($ after the last char)
+    sa = idx.sa_end()
+    bwt = idx.bwt()
+    for h in range(n + 1):
+        e = int(sa[h])
+        expect = 255 if e == n - 1 else (int(T[0]) if e == NOPOS else int(T[e + 1]))
+        assert bwt[h] == expect
+
+
+@pytest.mark.parametrize("seed,sigma", [(10, 4), (11, 20), (12, 2)])
+def test_backward_search_vs_scan(seed, sigma):
+    """Section 5 (1)-(3): the rows of X hold exactly the end positions of X in T."""
+    rng = np.random.default_rng(seed)
+    n = 3000
+    T = rng.integers(0, sigma, size=n).astype(np.uint8)
+    alpha = "protein" if sigma > 4 else "dna"
+    idx = alae.Index.build(T, alpha)
+    sa = idx.sa_end()
+    Tb = T.tobytes()
+    for _ in range(200):
+        L = int(rng.integers(1, 7))
+        st = int(rng.integers(0, n - L + 1))
+        X = T[st:st + L] if rng.random() < 0.8 else rng.integers(0, sigma, size=L).astype(np.uint8)
+        ends = []
+        pos = Tb.find(X.tobytes())
+        while pos >= 0:
+            ends.append(pos + L - 1)
+            pos = Tb.find(X.tobytes(), pos + 1)
+        lo, hi = idx.range(X)
+        got = sorted(int(sa[h]) for h in range(lo, hi + 1)) if lo <= hi else []
+        assert got == ends
+
+
+def test_save_load_roundtrip():
+    rng = np.random.default_rng(5)
+    T = rng.integers(0, 4, size=5000).astype(np.uint8)
+    idx = alae.Index.build(T, "dna")
+    with tempfile.TemporaryDirectory() as d:
+        p = os.path.join(d, "x.alae")
+        idx.save(p)
+        idx2 = alae.Index.load(p)
+        assert idx2.info() == idx.info()
+        np.testing.assert_array_equal(idx2.sa_end(), idx.sa_end())
+        np.testing.assert_array_equal(idx2.bwt(), idx.bwt())
+        with open(p, "r+b") as f:
+            f.write(b"XXXXXXXX")
+        with pytest.raises(alae.AlaeError) as ei:
+            alae.Index.load(p)
+        assert ei.value.status == 9
+
+
+def test_index_errors():
+    with pytest.raises(alae.AlaeError) as ei:
+        alae.Index.build("ACGN", "dna")
+    assert ei.value.status == 2
+    with pytest.raises(alae.AlaeError) as ei:
+        alae.Index.build("", "dna")
+    assert ei.value.status == 1
+    idx = alae.Index.build("acgtACGT", "dna")  # case-folded
+    assert idx.info()["n"] == 8
+
+
+def test_generator_shapes():
+    """Seeded generators: determinism and the planted-segment bookkeeping."""
+    a = synth.config1(planted=True)
+    b = synth.config1(planted=True)
+    np.testing.assert_array_equal(a["text"], b["text"])
+    assert len(a["plants"]) == 10 and a["text"].shape[0] == 100_000
+    ends = sorted((st, st + ln) for st, ln, _ in a["plants"])
+    assert all(ends[i][1] <= ends[i + 1][0] for i in range(len(ends) - 1))
