@@ -104,8 +104,15 @@ typedef struct {
     uint64_t sa_reads;       /* suffix-array reads at nodes that become unique          */
     uint64_t text_reads;     /* text reads of nodes walked along the text               */
     uint64_t frontier_bytes; /* frontier nodes/entries read + written, hit records      */
-    uint64_t expand_launches;/* launches of the expansion kernel                        */
-    double expand_ms;        /* summed device time of those launches                    */
+    uint64_t expand_launches;/* kernel launches of the trie walk                        */
+    double expand_ms;        /* device time of the level expansion (several occurrences) */
+    double chain_ms;         /* device time of the one-lane chain walk                   */
+    double wide_ms;          /* device time of the one-wave chain walk                   */
+    uint64_t chain_steps;    /* single-occurrence nodes computed by one lane             */
+    uint64_t wide_steps;     /* single-occurrence nodes computed by one wave             */
+    uint64_t promoted;       /* chains handed from a lane to a wave                      */
+    uint64_t dominated_gapped; /* states removed by the gapped domination test           */
+    uint64_t chain_bytes;    /* row bytes read and written by the chain kernels          */
     double merge_ms;         /* device time of the sort + max-merge of hit records      */
 } alae_stats;
 

@@ -55,7 +55,8 @@ struct alae_index {
     // Device copy, created on first use.
     mutable std::mutex mu;
     mutable bool on_device = false;
-    mutable uint8_t *d_text = nullptr;
+    mutable uint8_t *d_text = nullptr;        // first character (inside d_text_alloc)
+    mutable uint8_t *d_text_alloc = nullptr;  // text with readable slack on both sides
     mutable uint32_t *d_sa = nullptr;
     mutable uint8_t *d_occ = nullptr;
     mutable uint64_t *d_C = nullptr;

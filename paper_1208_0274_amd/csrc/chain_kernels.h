@@ -1,0 +1,632 @@
+// Chains: trie nodes with a single occurrence.
+//
+// Below a node with one occurrence ending at text position e, the trie is a
+// single path: the next character is T[e+1] (no index lookup is needed), and
+// every hit of the row is located at e.  Three walkers, by row shape:
+//
+//   k_chain_start    one lane per chain created by a level: locates it
+//                    (suffix array), tests its states for domination
+//                    (Section 3.2), and walks it in registers while every
+//                    entry is in the no-gap region (M <= |sg+ss|, no G_a):
+//                    there the row update is the diagonal step of Eq. 3;
+//   k_chain_general  one lane per chain whose row has gap states (up to
+//                    kNarrowRow entries, kept in private memory);
+//   k_chain_wide_*   one wave per chain with a longer row (LDS, or global
+//                    memory for rows beyond kWideCap entries).
+#pragma once
+
+#include "row_update.h"
+
+namespace alae {
+
+constexpr int kNarrowRow = 24;
+constexpr int kNgrSlots = 4;
+constexpr int kWideCap = 1024;  // row entries a wave keeps in LDS
+
+// Eight bytes arr[p .. p+7] as one little-endian word (arr carries kSlack
+// readable bytes around its data).
+__device__ inline uint64_t load8(const uint8_t *arr, int64_t p) {
+    const uintptr_t addr = (uintptr_t)(arr + p);
+    const uint32_t *b = reinterpret_cast<const uint32_t *>(addr & ~(uintptr_t)3);
+    const uint32_t sh = (uint32_t)(addr & 3u);
+    const uint32_t r0 = b[0], r1 = b[1], r2 = b[2];
+    const uint32_t w0 = __builtin_amdgcn_alignbyte(r1, r0, sh);
+    const uint32_t w1 = __builtin_amdgcn_alignbyte(r2, r1, sh);
+    return ((uint64_t)w1 << 32) | w0;
+}
+
+__device__ inline int32_t score_of(const SearchArgs &a, const int8_t *sub, uint32_t tc, uint32_t pc) {
+    return a.matrix_mode ? (int32_t)sub[tc * (uint32_t)a.sigma + pc] : (tc == pc ? a.s_match : a.s_mismatch);
+}
+
+// Gapped domination test of a row's states (the occurrence starts at
+// x = e_end - depth + 1): dominated states are set dead in place.  Returns
+// the number of entries that keep a live state.
+__device__ uint32_t prune_dominated(const SearchArgs &a, Entry *row, uint32_t len, uint32_t e_end, int32_t depth,
+                                    unsigned long long &dom_count) {
+    const int64_t x = (int64_t)e_end - depth + 1;
+    uint32_t memo_y[4] = {kNoPos, kNoPos, kNoPos, kNoPos};
+    bool memo_r[4] = {false, false, false, false};
+    int memo_n = 0;
+    auto test = [&](uint32_t y) {
+        for (int q = 0; q < 4; ++q)
+            if (memo_y[q] == y) return memo_r[q];
+        const bool r = dominated_gapped(a, x, y);
+        memo_y[memo_n & 3] = y;
+        memo_r[memo_n & 3] = r;
+        ++memo_n;
+        return r;
+    };
+    uint32_t live = 0;
+    for (uint32_t k = 0; k < len; ++k) {
+        Entry e = row[k];
+        if (e.M > 0 && test(e.yM)) {
+            e.M = kNeg;
+            e.yM = 0;
+            ++dom_count;
+        }
+        if (e.Ga > 0 && test(e.yGa)) {
+            e.Ga = kNeg;
+            e.yGa = 0;
+            ++dom_count;
+        }
+        row[k] = e;
+        live += (e.M > 0 || e.Ga > 0) ? 1u : 0u;
+    }
+    return live;
+}
+
+// Append a row with live entries to a chain queue (per-lane atomics).
+// Returns a pointer to the queued entries, or nullptr on overflow.
+__device__ inline Entry *queue_alloc(Counters *cnt, unsigned long long *nodes_ctr, unsigned long long *ent_ctr,
+                                     unsigned long long node_cap, unsigned long long ent_cap,
+                                     unsigned long long ov_nodes, unsigned long long ov_ent, Node *qnodes,
+                                     Entry *qents, uint32_t len, uint32_t e_end, int32_t depth) {
+    const unsigned long long slot = atomicAdd(nodes_ctr, 1ull);
+    const unsigned long long off = atomicAdd(ent_ctr, (unsigned long long)len);
+    if (slot >= node_cap || off + len > ent_cap) {
+        atomicOr(&cnt->overflow, slot >= node_cap ? ov_nodes : ov_ent);
+        return nullptr;
+    }
+    Node nd;
+    nd.lo = kUniqueBit | e_end;
+    nd.hi = (uint32_t)depth;
+    nd.off = (uint32_t)off;
+    nd.len = len;
+    qnodes[slot] = nd;
+    return qents + off;
+}
+
+// Queue a row for the wave walkers after the gapped domination test.
+__device__ void push_wide(const SearchArgs &a, Entry *row, uint32_t len, uint32_t e_end, int32_t depth,
+                          Node *witems, Entry *went, Caps caps, Counters *cnt, unsigned long long &dom_count) {
+    uint32_t keep = len;
+    if (a.use_domination) keep = prune_dominated(a, row, len, e_end, depth, dom_count);
+    if (keep == 0) return;
+    Entry *dst = queue_alloc(cnt, &cnt->wnodes, &cnt->wentries, caps.wnodes, caps.wentries, kOvWideNodes,
+                             kOvWideEntries, witems, went, keep, e_end, depth);
+    if (!dst) return;
+    uint32_t w = 0;
+    for (uint32_t k = 0; k < len; ++k) {
+        const Entry e = row[k];
+        if (e.M <= 0 && e.Ga <= 0) continue;
+        dst[w++] = e;
+    }
+}
+
+__device__ inline void emit_hit_lane(Counters *cnt, uint64_t *hkeys, uint32_t *hscores, Caps caps, uint32_t col,
+                                     uint32_t e_end, int32_t M) {
+    const unsigned long long slot = atomicAdd(&cnt->hits, 1ull);
+    if (slot < caps.hits) {
+        hkeys[slot] = ((uint64_t)col << 32) | e_end;
+        hscores[slot] = (uint32_t)M;
+    } else {
+        atomicOr(&cnt->overflow, kOvHits);
+    }
+}
+
+struct ChainQueues {
+    Node *gnodes;   // chains with gap states (general lane walker)
+    Entry *gents;
+    Node *wnodes;   // chains with long rows (wave walkers)
+    Entry *wents;
+    uint64_t *hkeys;
+    uint32_t *hscores;
+};
+
+// ---------------------------------------------------------------------------
+// k_chain_start: one lane per chain created by a level
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_chain_start(SearchArgs a, SubTable subt, const Node *items, uint32_t nitems,
+                                                     const Entry *ient, ChainQueues q, Caps caps, Counters *cnt) {
+    __shared__ int8_t sub[20 * 20];
+    for (int i = threadIdx.x; i < a.sigma * a.sigma; i += blockDim.x) sub[i] = subt.s[i];
+    __syncthreads();
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int32_t open = a.sg + a.ss;
+    unsigned long long n_dom = 0, n_steps = 0, n_entries = 0, n_hits = 0, n_general = 0, n_wide = 0;
+    if (t < nitems) {
+        const Node it = items[t];
+        uint32_t e_end = a.sa[it.lo];
+        int32_t depth = (int32_t)it.hi;
+        const uint32_t len = it.len;
+        const Entry *row = ient + it.off;
+        const int64_t x = (int64_t)e_end - depth + 1;
+        if (len > (uint32_t)kNarrowRow) {
+            // long row (repeats, or wide gap shadows at the first unique depth): both
+            // domination tests, then the wave walkers
+            Entry *dst = queue_alloc(cnt, &cnt->wnodes, &cnt->wentries, caps.wnodes, caps.wentries, kOvWideNodes,
+                                     kOvWideEntries, q.wnodes, q.wents, len, e_end, depth);
+            if (dst) {
+                for (uint32_t k = 0; k < len; ++k) {
+                    Entry e = row[k];
+                    if (a.use_domination) {
+                        if (e.M > 0 && dominated(a, sub, x, e.yM)) {
+                            e.M = kNeg;
+                            ++n_dom;
+                        }
+                        if (e.Ga > 0 && dominated(a, sub, x, e.yGa)) {
+                            e.Ga = kNeg;
+                            ++n_dom;
+                        }
+                    }
+                    dst[k] = e;
+                    if (e.M >= a.H) {
+                        emit_hit_lane(cnt, q.hkeys, q.hscores, caps, e.col, e_end, e.M);
+                        ++n_hits;
+                    }
+                }
+                if (a.use_domination) prune_dominated(a, dst, len, e_end, depth, n_dom);
+                ++n_wide;
+            }
+        } else {
+            // ungapped domination test of every state (Section 3.2)
+            uint32_t killM = 0, killGa = 0, live = 0;
+            bool ngr = true;
+            for (uint32_t k = 0; k < len; ++k) {
+                const Entry e = row[k];
+                bool aM = e.M > 0, aG = e.Ga > 0;
+                if (a.use_domination) {
+                    if (aM && dominated(a, sub, x, e.yM)) {
+                        aM = false;
+                        killM |= 1u << k;
+                        ++n_dom;
+                    }
+                    if (aG && dominated(a, sub, x, e.yGa)) {
+                        aG = false;
+                        killGa |= 1u << k;
+                        ++n_dom;
+                    }
+                }
+                if (aM && e.M >= a.H) {
+                    emit_hit_lane(cnt, q.hkeys, q.hscores, caps, e.col, e_end, e.M);
+                    ++n_hits;
+                }
+                if (aM || aG) ++live;
+                if (aG || (aM && e.M > -open)) ngr = false;
+            }
+            if (live > 0 && (!ngr || live > (uint32_t)kNgrSlots || !a.ngr_walk)) {
+                // gap states (or many entries): the general lane walker takes it
+                Entry *dst = queue_alloc(cnt, &cnt->gnodes, &cnt->gentries, caps.gnodes, caps.gentries,
+                                         kOvGeneralNodes, kOvGeneralEntries, q.gnodes, q.gents, live, e_end, depth);
+                if (dst) {
+                    uint32_t w = 0;
+                    for (uint32_t k = 0; k < len; ++k) {
+                        Entry e = row[k];
+                        if (killM & (1u << k)) e.M = kNeg;
+                        if (killGa & (1u << k)) e.Ga = kNeg;
+                        if (e.M <= 0 && e.Ga <= 0) continue;
+                        dst[w++] = e;
+                    }
+                }
+                ++n_general;
+            } else if (live > 0) {
+                // no-gap region: walk in registers, diagonal steps only (Eq. 3)
+                uint32_t col[kNgrSlots], y[kNgrSlots];
+                int32_t M[kNgrSlots];
+#pragma unroll
+                for (int s2 = 0; s2 < kNgrSlots; ++s2) {
+                    col[s2] = 0;
+                    y[s2] = 0;
+                    M[s2] = kNeg;
+                }
+                uint32_t alive = 0;
+                {
+                    int sidx = 0;
+                    for (uint32_t k = 0; k < len; ++k) {
+                        const Entry e = row[k];
+                        if ((killM & (1u << k)) || e.M <= 0) continue;
+#pragma unroll
+                        for (int s2 = 0; s2 < kNgrSlots; ++s2) {
+                            if (s2 == sidx) {
+                                col[s2] = e.col;
+                                M[s2] = e.M;
+                                y[s2] = e.yM;
+                            }
+                        }
+                        alive |= 1u << sidx;
+                        ++sidx;
+                    }
+                }
+                uint64_t tw = 0, qw[kNgrSlots];
+                int tpos = 8;
+                for (;;) {
+                    const int32_t d1 = depth + 1;
+                    if (d1 > a.lmax || (uint64_t)e_end + 1 >= a.n) break;
+                    if (tpos == 8) {
+                        tw = load8(a.text, (int64_t)e_end + 1);
+#pragma unroll
+                        for (int s2 = 0; s2 < kNgrSlots; ++s2)
+                            qw[s2] = (alive & (1u << s2)) ? load8(a.query, (int64_t)col[s2] + 1) : 0ull;
+                        tpos = 0;
+                    }
+                    const uint32_t c = (uint32_t)(tw >> (8 * tpos)) & 0xFFu;
+                    const int32_t rowgain = a.smax * (a.lmax - d1);
+                    uint32_t nalive = 0;
+                    bool fgoe = false;
+                    int32_t nM[kNgrSlots];
+#pragma unroll
+                    for (int s2 = 0; s2 < kNgrSlots; ++s2) {
+                        const uint32_t ncol = col[s2] + 1;
+                        const uint32_t pc = (uint32_t)(qw[s2] >> (8 * tpos)) & 0xFFu;
+                        const int32_t v = M[s2] + score_of(a, sub, c, pc);
+                        const bool ok = ((alive >> s2) & 1u) && ncol < a.m && keep_state(a, v, ncol, rowgain);
+                        nM[s2] = ok ? v : kNeg;
+                        nalive |= ok ? (1u << s2) : 0u;
+                        fgoe |= ok && v > -open;
+                    }
+                    if (fgoe) {
+                        // a gap can open below this row: hand the current row to the general walker
+                        uint32_t cntlive = __popc(alive);
+                        Entry *dst = queue_alloc(cnt, &cnt->gnodes, &cnt->gentries, caps.gnodes, caps.gentries,
+                                                 kOvGeneralNodes, kOvGeneralEntries, q.gnodes, q.gents, cntlive,
+                                                 e_end, depth);
+                        if (dst) {
+                            uint32_t w = 0;
+#pragma unroll
+                            for (int s2 = 0; s2 < kNgrSlots; ++s2) {
+                                if (alive & (1u << s2)) {
+                                    Entry e;
+                                    e.col = col[s2];
+                                    e.M = M[s2];
+                                    e.Ga = kNeg;
+                                    e.yM = y[s2];
+                                    e.yGa = 0;
+                                    dst[w++] = e;
+                                }
+                            }
+                        }
+                        ++n_general;
+                        break;
+                    }
+                    ++n_steps;
+                    if (!nalive) break;
+#pragma unroll
+                    for (int s2 = 0; s2 < kNgrSlots; ++s2) {
+                        if (nalive & (1u << s2)) {
+                            col[s2] += 1;
+                            M[s2] = nM[s2];
+                            ++n_entries;
+                            if (M[s2] >= a.H) {
+                                emit_hit_lane(cnt, q.hkeys, q.hscores, caps, col[s2], e_end + 1, M[s2]);
+                                ++n_hits;
+                            }
+                        }
+                    }
+                    alive = nalive;
+                    e_end += 1;
+                    depth = d1;
+                    ++tpos;
+                }
+            }
+        }
+    }
+    const int lane = threadIdx.x & 63;
+    const unsigned long long w_dom = wave_sum_u64(n_dom), w_steps = wave_sum_u64(n_steps),
+                             w_ent = wave_sum_u64(n_entries), w_hits = wave_sum_u64(n_hits),
+                             w_gen = wave_sum_u64(n_general), w_wide = wave_sum_u64(n_wide),
+                             w_items = wave_sum_u64(t < nitems ? 1ull : 0ull);
+    if (lane == 0) {
+        if (w_dom) atomicAdd(&cnt->st_dominated, w_dom);
+        if (w_steps) atomicAdd(&cnt->st_ngr_steps, w_steps);
+        if (w_ent) atomicAdd(&cnt->st_entries, w_ent);
+        if (w_ent) atomicAdd(&cnt->st_diag, w_ent);
+        if (w_hits) atomicAdd(&cnt->st_emitted, w_hits);
+        if (w_wide) atomicAdd(&cnt->st_promoted, w_wide);
+        if (w_items) {
+            atomicAdd(&cnt->st_sa_reads, w_items);
+            atomicAdd(&cnt->st_text_reads, w_items + w_steps / 8);
+        }
+        (void)w_gen;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_chain_general: one lane per chain with gap states; idle lanes take the
+// next queue items.  A row wider than kNarrowRow goes to the wave walkers.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_chain_general(SearchArgs a, const Node *items, uint32_t nitems,
+                                                       const Entry *ient, Node *witems, Entry *went,
+                                                       uint64_t *hkeys, uint32_t *hscores, Caps caps,
+                                                       Counters *cnt) {
+    const int lane = threadIdx.x & 63;
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    Entry rows[2][kNarrowRow];
+    int cur = 0;
+    bool active = false;
+    uint32_t e_end = 0, len = 0;
+    int32_t depth = 0;
+    bool exhausted = false;
+    unsigned long long n_steps = 0, n_entries = 0, n_dom = 0, n_diag = 0, n_g2 = 0, n_g3 = 0, n_bytes = 0,
+                       n_hits = 0, n_prom = 0;
+    for (;;) {
+        const uint64_t idle = __ballot(!active);
+        const uint32_t nidle = (uint32_t)__popcll(idle);
+        if (!exhausted && (nidle >= 16 || nidle == 64)) {
+            unsigned long long first = 0;
+            if (lane == 0) first = atomicAdd(&cnt->general_head, (unsigned long long)nidle);
+            first = __shfl(first, 0, 64);
+            if (first + nidle >= nitems) exhausted = true;
+            if (!active) {
+                const unsigned long long it = first + (unsigned long long)__popcll(idle & below);
+                if (it < nitems) {
+                    const Node nd = items[it];
+                    e_end = nd.lo & ~kUniqueBit;
+                    depth = (int32_t)nd.hi;
+                    len = nd.len;
+                    n_bytes += sizeof(Node) + (unsigned long long)len * sizeof(Entry);
+                    for (uint32_t k = 0; k < len; ++k) rows[0][k] = ient[nd.off + k];
+                    cur = 0;
+                    active = true;
+                }
+            }
+        }
+        if (__ballot(active) == 0ull) {
+            if (exhausted) break;
+            continue;
+        }
+        bool stepped = false;
+        uint32_t nlen = 0;
+        if (active) {
+            const int32_t d1 = depth + 1;
+            if (d1 > a.lmax || (uint64_t)e_end + 1 >= a.n) {
+                active = false;
+            } else {
+                const int c = a.text[e_end + 1];
+                RowSink s;
+                sink_init(s);
+                s.out = rows[cur ^ 1];
+                s.cap = kNarrowRow;
+                s.emit_hits = false;
+                s.unique = true;
+                s.e_end = e_end + 1;
+                child_row<true>(a, rows[cur], len, c, d1, false, 0, s);
+                ++n_steps;
+                if (s.n_entries > (uint32_t)kNarrowRow) {
+                    push_wide(a, rows[cur], len, e_end, depth, witems, went, caps, cnt, n_dom);
+                    ++n_prom;
+                    active = false;
+                } else if (s.n_entries == 0) {
+                    active = false;
+                } else {
+                    nlen = s.n_entries;
+                    stepped = true;
+                    n_entries += nlen;
+                    n_diag += s.st_diag;
+                    n_g2 += s.st_gap2;
+                    n_g3 += s.st_gap3;
+                }
+            }
+        }
+        // hit records of the new rows (one atomic per wave)
+        uint32_t nh = 0;
+        if (stepped)
+            for (uint32_t k = 0; k < nlen; ++k) nh += rows[cur ^ 1][k].M >= a.H ? 1u : 0u;
+        uint32_t htot;
+        const uint32_t hpre = wave_excl_scan_u32(nh, &htot);
+        if (htot) {
+            unsigned long long hb = 0;
+            if (lane == 0) hb = atomicAdd(&cnt->hits, (unsigned long long)htot);
+            hb = __shfl(hb, 0, 64);
+            if (lane == 0 && hb + htot > caps.hits) atomicOr(&cnt->overflow, kOvHits);
+            if (nh) {
+                unsigned long long slot = hb + hpre;
+                for (uint32_t k = 0; k < nlen; ++k) {
+                    const Entry &w = rows[cur ^ 1][k];
+                    if (w.M < a.H) continue;
+                    if (slot < caps.hits) {
+                        hkeys[slot] = ((uint64_t)w.col << 32) | (e_end + 1);
+                        hscores[slot] = (uint32_t)w.M;
+                    }
+                    ++slot;
+                }
+            }
+            n_hits += nh;
+        }
+        if (stepped) {
+            cur ^= 1;
+            len = nlen;
+            e_end += 1;
+            depth += 1;
+        }
+    }
+    const unsigned long long w_steps = wave_sum_u64(n_steps), w_ent = wave_sum_u64(n_entries),
+                             w_dom = wave_sum_u64(n_dom), w_d = wave_sum_u64(n_diag), w_2 = wave_sum_u64(n_g2),
+                             w_3 = wave_sum_u64(n_g3), w_b = wave_sum_u64(n_bytes), w_h = wave_sum_u64(n_hits),
+                             w_p = wave_sum_u64(n_prom);
+    if (lane == 0) {
+        atomicAdd(&cnt->st_chain_steps, w_steps);
+        atomicAdd(&cnt->st_entries, w_ent);
+        atomicAdd(&cnt->st_dominated_gapped, w_dom);
+        atomicAdd(&cnt->st_diag, w_d);
+        atomicAdd(&cnt->st_gap2, w_2);
+        atomicAdd(&cnt->st_gap3, w_3);
+        atomicAdd(&cnt->st_chain_bytes, w_b);
+        atomicAdd(&cnt->st_emitted, w_h);
+        atomicAdd(&cnt->st_promoted, w_p);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Wave walkers
+// ---------------------------------------------------------------------------
+
+struct WideStats {
+    unsigned long long steps, entries, diag, gap2, gap3, hits, bytes;
+};
+
+// Walk one chain whose row is held in (cur, nxt) buffers of capacity cap.
+// Returns false if the row outgrew the buffers; the live row is then in cur
+// (len, e_end, depth describe it) and the caller spills it.
+template <class Row>
+__device__ bool walk_wide(const SearchArgs &a, Row &cur, Row &nxt, uint32_t &len, uint32_t &e_end, int32_t &depth,
+                          uint32_t cap, uint64_t *hkeys, uint32_t *hscores, Caps caps, Counters *cnt, HitRes &hr,
+                          WideStats &w) {
+    const int lane = threadIdx.x & 63;
+    uint32_t txt = 0;
+    int tpos = 64;
+    for (;;) {
+        const int32_t d1 = depth + 1;
+        if (d1 > a.lmax || (uint64_t)e_end + 1 >= a.n) return true;
+        if (tpos == 64) {  // next 64 text characters, one per lane
+            const uint64_t p = (uint64_t)e_end + 1 + lane;
+            txt = p < a.n ? a.text[p] : 0u;
+            tpos = 0;
+        }
+        const int c = __shfl(txt, tpos, 64);
+        ++tpos;
+        WideOut o;
+        o.emit_hits = true;
+        o.cap = cap;
+        o.hkeys = hkeys;
+        o.hscores = hscores;
+        o.hit_cap = caps.hits;
+        o.cnt = cnt;
+        o.e_child = e_end + 1;
+        wide_child_row(a, cur, len, nxt, c, d1, o, hr);
+        __syncthreads();
+        w.steps++;
+        w.bytes += (unsigned long long)(len + o.len) * 12ull;
+        if (o.overflow) return false;
+        w.entries += o.len;
+        w.diag += o.diag;
+        w.gap2 += o.gap2;
+        w.gap3 += o.gap3;
+        w.hits += o.hits;
+        if (o.len == 0) return true;
+        Row t = cur;
+        cur = nxt;
+        nxt = t;
+        len = o.len;
+        e_end += 1;
+        depth = d1;
+    }
+}
+
+__device__ inline void wide_stats_flush(Counters *cnt, const WideStats &w) {
+    if ((threadIdx.x & 63) != 0) return;
+    atomicAdd(&cnt->st_wide_steps, w.steps);
+    atomicAdd(&cnt->st_entries, w.entries);
+    atomicAdd(&cnt->st_diag, w.diag);
+    atomicAdd(&cnt->st_gap2, w.gap2);
+    atomicAdd(&cnt->st_gap3, w.gap3);
+    atomicAdd(&cnt->st_emitted, w.hits);
+    atomicAdd(&cnt->st_chain_bytes, w.bytes);
+}
+
+// Rows in LDS (one wave per block).  A row that outgrows kWideCap entries is
+// spilled to the global spill queue and continued by k_chain_wide_global.
+__global__ void __launch_bounds__(64) k_chain_wide_lds(SearchArgs a, const Node *witems, uint32_t nw,
+                                                       const Entry *went, Node *onodes, Entry *oents,
+                                                       uint64_t *hkeys, uint32_t *hscores, Caps caps,
+                                                       Counters *cnt) {
+    __shared__ uint32_t s_col[2][kWideCap];
+    __shared__ int32_t s_M[2][kWideCap];
+    __shared__ int32_t s_Ga[2][kWideCap];
+    const int lane = threadIdx.x & 63;
+    HitRes hr = {0, 0, 0};
+    WideStats w = {0, 0, 0, 0, 0, 0, 0};
+    for (;;) {
+        unsigned long long it = 0;
+        if (lane == 0) it = atomicAdd(&cnt->wide_head, 1ull);
+        it = __shfl(it, 0, 64);
+        if (it >= nw) break;
+        const Node nd = witems[it];
+        uint32_t e_end = nd.lo & ~kUniqueBit;
+        int32_t depth = (int32_t)nd.hi;
+        uint32_t len = nd.len;
+        SoaRow cur{s_col[0], s_M[0], s_Ga[0]};
+        SoaRow nxt{s_col[1], s_M[1], s_Ga[1]};
+        bool done = true;
+        if (len <= (uint32_t)kWideCap) {
+            for (uint32_t k = lane; k < len; k += 64) cur.store(k, went[nd.off + k]);
+            __syncthreads();
+            done = walk_wide(a, cur, nxt, len, e_end, depth, (uint32_t)kWideCap, hkeys, hscores, caps, cnt, hr, w);
+        } else {
+            done = false;
+        }
+        if (!done) {
+            // spill the live row (from LDS, or the queued row if it never fit)
+            unsigned long long slot = 0, off = 0;
+            if (lane == 0) {
+                slot = atomicAdd(&cnt->onodes, 1ull);
+                off = atomicAdd(&cnt->oentries, (unsigned long long)len);
+                if (slot >= caps.onodes) atomicOr(&cnt->overflow, kOvSpillNodes);
+                if (off + len > caps.oentries) atomicOr(&cnt->overflow, kOvSpillEntries);
+            }
+            slot = __shfl(slot, 0, 64);
+            off = __shfl(off, 0, 64);
+            if (slot < caps.onodes && off + len <= caps.oentries) {
+                const bool from_lds = nd.len <= (uint32_t)kWideCap;
+                for (uint32_t k = lane; k < len; k += 64) oents[off + k] = from_lds ? cur.load(k) : went[nd.off + k];
+                if (lane == 0) {
+                    Node sn;
+                    sn.lo = kUniqueBit | e_end;
+                    sn.hi = (uint32_t)depth;
+                    sn.off = (uint32_t)off;
+                    sn.len = len;
+                    onodes[slot] = sn;
+                }
+            }
+        }
+        __syncthreads();
+    }
+    hit_release(hr, hkeys, hscores, caps.hits, cnt);
+    wide_stats_flush(cnt, w);
+}
+
+// Rows in global memory: two buffers of caps.wrow entries per block.
+__global__ void __launch_bounds__(64) k_chain_wide_global(SearchArgs a, const Node *items, uint32_t nitems,
+                                                          const Entry *ents, Entry *rowbuf, uint64_t *hkeys,
+                                                          uint32_t *hscores, Caps caps, Counters *cnt) {
+    const int lane = threadIdx.x & 63;
+    Entry *buf0 = rowbuf + (uint64_t)blockIdx.x * 2ull * caps.wrow;
+    Entry *buf1 = buf0 + caps.wrow;
+    HitRes hr = {0, 0, 0};
+    WideStats w = {0, 0, 0, 0, 0, 0, 0};
+    for (;;) {
+        unsigned long long it = 0;
+        if (lane == 0) it = atomicAdd(&cnt->overflow_head, 1ull);
+        it = __shfl(it, 0, 64);
+        if (it >= nitems) break;
+        const Node nd = items[it];
+        uint32_t e_end = nd.lo & ~kUniqueBit;
+        int32_t depth = (int32_t)nd.hi;
+        uint32_t len = nd.len;
+        if (len > caps.wrow) {
+            if (lane == 0) atomicOr(&cnt->overflow, kOvWideRow);
+            continue;
+        }
+        for (uint32_t k = lane; k < len; k += 64) buf0[k] = ents[nd.off + k];
+        __syncthreads();
+        AosRow cur{buf0}, nxt{buf1};
+        if (!walk_wide(a, cur, nxt, len, e_end, depth, (uint32_t)caps.wrow, hkeys, hscores, caps, cnt, hr, w)) {
+            if (lane == 0) atomicOr(&cnt->overflow, kOvWideRow);
+        }
+        __syncthreads();
+    }
+    hit_release(hr, hkeys, hscores, caps.hits, cnt);
+    wide_stats_flush(cnt, w);
+}
+
+}  // namespace alae

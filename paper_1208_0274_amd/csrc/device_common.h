@@ -57,8 +57,19 @@ struct SearchArgs {
     int32_t use_score_filter;
     int32_t use_domination;
     int32_t dom_reach;    // longest left extension tried by the domination test
+    int32_t u_closed;     // U(j) = smax * (m-1-j) (match/mismatch scoring)
+    int32_t matrix_mode;  // substitution scores come from a matrix
+    int32_t s_match;      // s_a (match/mismatch scoring)
+    int32_t s_mismatch;   // s_b
+    const uint8_t *query; // query codes; 64 readable bytes before index 0 and after m-1
+    int32_t ngr_walk;     // walk no-gap chains in registers (else all go to the general walker)
     uint32_t C[21];
 };
+
+// Text and query buffers carry this many readable bytes before index 0 and
+// after their last character, so fixed-size windows can be loaded without
+// bounds checks (the bytes outside are never used as characters).
+constexpr int kSlack = 64;
 
 // occ(c, i) for the four DNA codes at once: counts of each code in BWT[0..i].
 // i may be -1 (all zero).  One 64-byte block read.
@@ -120,6 +131,82 @@ __device__ inline uint32_t occ1_gen(const SearchArgs &a, int c, int64_t i) {
     }
     return cnt;
 }
+
+// ---------------------------------------------------------------------------
+// Counters shared by the kernels of one search
+// ---------------------------------------------------------------------------
+
+struct Counters {
+    unsigned long long nodes;     // child nodes allocated in the output level
+    unsigned long long entries;   // entries allocated in the output level
+    unsigned long long hits;      // hit records allocated in total
+    unsigned long long overflow;  // bit 0 nodes, bit 1 entries, bit 2 hits
+    // statistics
+    unsigned long long st_nodes;
+    unsigned long long st_entries;
+    unsigned long long st_diag;
+    unsigned long long st_gap2;
+    unsigned long long st_gap3;
+    unsigned long long st_dominated;
+    unsigned long long st_emitted;
+    unsigned long long bad_query;
+    // random-access reads of the expansion kernel (64-byte granules)
+    unsigned long long st_occ_reads;
+    unsigned long long st_sa_reads;
+    unsigned long long st_text_reads;
+    // frontier bytes read and written by the expansion kernel
+    unsigned long long st_frontier_bytes;
+    // chains: nodes with a single occurrence, walked along the text
+    unsigned long long cnodes;     // chain items allocated by the level kernel
+    unsigned long long centries;   // their row entries
+    unsigned long long chain_head; // next chain item to start (narrow chain kernel)
+    unsigned long long wnodes;     // wide chain items (rows too wide for one lane)
+    unsigned long long wentries;   // their row entries
+    unsigned long long wide_head;  // next wide item to start (wide chain kernel)
+    unsigned long long st_chain_steps;
+    unsigned long long st_wide_steps;
+    unsigned long long st_promoted;
+    unsigned long long st_dominated_gapped;
+    unsigned long long st_chain_bytes;  // row bytes moved by the chain kernels
+    unsigned long long hit_padding;     // reserved hit slots left unused (padding keys)
+    unsigned long long onodes;          // wide chains whose row outgrew the on-chip buffers
+    unsigned long long oentries;
+    unsigned long long overflow_head;
+    unsigned long long lwnodes;         // next-level nodes with rows too long for a lane
+    unsigned long long gnodes;          // chains with gaps, walked by the general lane kernel
+    unsigned long long gentries;
+    unsigned long long general_head;
+    unsigned long long st_ngr_steps;    // chain steps taken in the no-gap fast path
+};
+
+// Key of an unused hit slot: sorts after every real (column, text end) key.
+constexpr uint64_t kPadKey = ~0ull;
+
+// overflow bits
+constexpr unsigned long long kOvNodes = 1, kOvEntries = 2, kOvHits = 4, kOvChainNodes = 8, kOvChainEntries = 16,
+                             kOvWideNodes = 32, kOvWideEntries = 64, kOvWideRow = 128, kOvSpillNodes = 256,
+                             kOvSpillEntries = 512, kOvLevelWide = 1024, kOvGeneralNodes = 2048,
+                             kOvGeneralEntries = 4096;
+
+struct Caps {
+    unsigned long long nodes;
+    unsigned long long entries;
+    unsigned long long hits;
+    unsigned long long cnodes;
+    unsigned long long centries;
+    unsigned long long wnodes;
+    unsigned long long wentries;
+    unsigned long long wrow;  // entries per wide row buffer
+    unsigned long long onodes;    // spill queue of rows too wide for on-chip buffers
+    unsigned long long oentries;
+    unsigned long long lwnodes;   // next-level nodes with long rows
+    unsigned long long gnodes;    // general chain queue
+    unsigned long long gentries;
+};
+
+struct SubTable {
+    int8_t s[20 * 20];
+};
 
 __device__ inline int32_t imax(int32_t a, int32_t b) { return a > b ? a : b; }
 __device__ inline int32_t imin(int32_t a, int32_t b) { return a < b ? a : b; }

@@ -1,0 +1,723 @@
+// Sparse DP row update of a trie node (Section 2.2 recurrences with the
+// filters of Section 3), in two forms:
+//   child_row       -- one lane computes a whole child row sequentially;
+//   wide_child_row  -- one wave computes a child row 64 parent entries at a
+//                      time, with G_b as a wave-level prefix-max scan.
+// Both produce the same entries (column, M, G_a, start tags) for the same
+// parent row.
+#pragma once
+
+#include "device_common.h"
+
+namespace alae {
+
+constexpr int64_t kNegKey = INT64_MIN / 4;
+constexpr int kGapWindow = 96;  // window side of the gapped domination test
+
+// ---------------------------------------------------------------------------
+// Domination (Section 3.2, Theorem 4 case 2 and Lemma 1, tested locally)
+// ---------------------------------------------------------------------------
+// A state whose best alignment starts at text position x, query column y is
+// dominated when an alignment ending exactly at (x-1, y-1) scores above zero:
+// prepending it beats that alignment at every cell it can reach, so the state
+// can never carry the maximum of a cell.
+
+// The 32 bytes arr[p-32 .. p-1] as eight little-endian words (arr carries
+// kSlack readable bytes around its data).
+__device__ inline void load_window32(const uint8_t *arr, int64_t p, uint32_t w[8]) {
+    const uintptr_t addr = (uintptr_t)(arr + p - 32);
+    const uint32_t *base = reinterpret_cast<const uint32_t *>(addr & ~(uintptr_t)3);
+    const uint32_t sh = (uint32_t)(addr & 3u);
+    uint32_t r[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) r[i] = base[i];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) w[i] = __builtin_amdgcn_alignbyte(r[i + 1], r[i], sh);
+}
+
+// Ungapped form: some suffix of T[x-k..x-1] against P[y-k..y-1] (k <= 32)
+// scores > 0.  sub is the substitution table (LDS) for matrix scoring.
+__device__ inline bool dominated(const SearchArgs &a, const int8_t *sub, int64_t x, int64_t y) {
+    int64_t reach = a.dom_reach;
+    if (x < reach) reach = x;
+    if (y < reach) reach = y;
+    if (reach <= 0) return false;
+    uint32_t tw[8], qw[8];
+    load_window32(a.text, x, tw);
+    load_window32(a.query, y, qw);
+    int32_t sum = 0;
+    bool dom = false;
+#pragma unroll
+    for (int k = 1; k <= 32; ++k) {
+        const int j = 32 - k;
+        const uint32_t tc = (tw[j >> 2] >> (8 * (j & 3))) & 0xFFu;
+        const uint32_t pc = (qw[j >> 2] >> (8 * (j & 3))) & 0xFFu;
+        const int32_t d = a.matrix_mode ? (int32_t)sub[tc * (uint32_t)a.sigma + pc]
+                                        : (tc == pc ? a.s_match : a.s_mismatch);
+        if (k <= reach) {
+            sum += d;
+            dom |= sum > 0;
+        }
+    }
+    return dom;
+}
+
+// Gapped form: the local alignment score ending at (x-1, y-1) computed inside
+// the window T[x-K..x-1] x P[y-K..y-1] (a lower bound of the true one).
+__device__ inline bool dominated_gapped(const SearchArgs &a, int64_t x, int64_t y) {
+    const int rows = (int)(x < kGapWindow ? x : kGapWindow);
+    const int cols = (int)(y < kGapWindow ? y : kGapWindow);
+    if (rows == 0 || cols == 0) return false;
+    const int32_t open = a.sg + a.ss;
+    int32_t Hr[kGapWindow + 1], Er[kGapWindow + 1];
+    for (int j = 0; j <= cols; ++j) {
+        Hr[j] = 0;
+        Er[j] = kNeg;
+    }
+    for (int i = 1; i <= rows; ++i) {
+        const int tc = a.text[x - rows + i - 1];
+        const int8_t *pc = a.prof + (size_t)tc * a.m + (y - cols);
+        int32_t Hleft = 0, F = kNeg, Hdiag = 0;
+        for (int j = 1; j <= cols; ++j) {
+            const int32_t E = imax(Er[j] + a.ss, Hr[j] + open);
+            F = imax(F + a.ss, Hleft + open);
+            int32_t h = imax(Hdiag + pc[j - 1], imax(E, F));
+            h = imax(h, 0);
+            Hdiag = Hr[j];
+            Hr[j] = h;
+            Er[j] = E;
+            Hleft = h;
+        }
+    }
+    return Hr[cols] > 0;
+}
+
+// ---------------------------------------------------------------------------
+// Filters
+// ---------------------------------------------------------------------------
+// Zero floor (Theorem 2 (i)) and score filter (Theorem 2 (ii)) for a state of
+// value v at column col of a row at depth d1: the gain still available is at
+// most min(U(col), smax * (L_max - d1)) (query columns left, text rows left
+// under Theorem 1).  rowgain = smax * (L_max - d1).
+__device__ inline int32_t gain_after(const SearchArgs &a, uint32_t col) {
+    // match/mismatch scoring: every later column can add at most s_a
+    return a.u_closed ? a.smax * (int32_t)(a.m - 1 - col) : a.U[col];
+}
+
+__device__ inline bool keep_state(const SearchArgs &a, int32_t v, uint32_t col, int32_t rowgain) {
+    if (v <= 0) return false;
+    if (!a.use_score_filter) return true;
+    int32_t g = gain_after(a, col);
+    if (rowgain < g) g = rowgain;
+    return v + g >= a.H;
+}
+
+// ---------------------------------------------------------------------------
+// Sequential (one lane) row update
+// ---------------------------------------------------------------------------
+
+struct RowSink {
+    Entry *out;          // output row
+    uint32_t cap;        // entries that may be written to out
+    bool emit_hits;      // write hit records while producing the row
+    uint64_t *hkeys;
+    uint32_t *hscores;
+    unsigned long long hit_base;
+    unsigned long long hit_cap;
+    // occurrences of the child
+    bool unique;
+    uint32_t e_end;      // unique: text end of the occurrence
+    uint32_t lo, hi;     // otherwise: BWT rows
+    // results
+    uint32_t n_entries;  // may exceed cap (then only cap entries were written)
+    uint32_t n_hits;
+    uint32_t st_diag, st_gap2, st_gap3, st_dom;
+};
+
+__device__ inline void sink_init(RowSink &s) {
+    s.out = nullptr;
+    s.cap = 0xFFFFFFFFu;
+    s.emit_hits = true;
+    s.hkeys = nullptr;
+    s.hscores = nullptr;
+    s.hit_base = 0;
+    s.hit_cap = 0;
+    s.unique = false;
+    s.e_end = 0;
+    s.lo = s.hi = 0;
+    s.n_entries = s.n_hits = 0;
+    s.st_diag = s.st_gap2 = s.st_gap3 = s.st_dom = 0;
+}
+
+template <bool WRITE>
+__device__ inline void emit_entry(const SearchArgs &a, RowSink &s, uint32_t col, int32_t M, int32_t Ga, uint32_t yM,
+                                  uint32_t yGa, int inputs) {
+    if (WRITE) {
+        if (s.n_entries < s.cap) {
+            Entry e;
+            e.col = col;
+            e.M = M;
+            e.Ga = Ga;
+            e.yM = yM;
+            e.yGa = yGa;
+            s.out[s.n_entries] = e;
+        }
+        if (inputs <= 1)
+            s.st_diag++;
+        else if (inputs == 2)
+            s.st_gap2++;
+        else
+            s.st_gap3++;
+    }
+    s.n_entries++;
+    if (!s.emit_hits || M < a.H) return;
+    if (s.unique) {
+        if (WRITE) {
+            const unsigned long long slot = s.hit_base + s.n_hits;
+            if (slot < s.hit_cap) {
+                s.hkeys[slot] = ((uint64_t)col << 32) | s.e_end;
+                s.hscores[slot] = (uint32_t)M;
+            }
+        }
+        s.n_hits++;
+    } else {
+        for (uint32_t h = s.lo; h <= s.hi; ++h) {
+            if (WRITE) {
+                const unsigned long long slot = s.hit_base + s.n_hits;
+                if (slot < s.hit_cap) {
+                    s.hkeys[slot] = ((uint64_t)col << 32) | a.sa[h];
+                    s.hscores[slot] = (uint32_t)M;
+                }
+            }
+            s.n_hits++;
+        }
+    }
+}
+
+// The row at depth d1 of the child reached with character c, from the parent
+// row prow[0..plen) (sorted by column).  Candidate columns are the parent's
+// columns (G_a: a text character against a gap) and the parent's columns + 1
+// (diagonal); G_b (a query character against a gap) runs left to right along
+// the row, also through columns with no candidate.  check_dom applies the
+// ungapped domination test for the occurrence starting at text position x.
+template <bool WRITE>
+__device__ void child_row(const SearchArgs &a, const Entry *prow, uint32_t plen, int c, int32_t d1, bool check_dom,
+                          int64_t x, RowSink &s, const int8_t *sub = nullptr) {
+    const int8_t *pc = a.prof + (size_t)c * a.m;
+    const int32_t open = a.sg + a.ss;  // first gap character
+    const int32_t ext = a.ss;
+    const int32_t rowgain = a.smax * (a.lmax - d1);
+    int64_t last = -1;     // last column already handled
+    int32_t gnext = kNeg;  // G_b value for column last+1
+    uint32_t gy = 0;       // its start column
+
+    auto spread_to = [&](int64_t upto) {  // G_b-only columns last+1 .. upto
+        while (last < upto) {
+            if (gnext <= 0) {
+                last = upto;
+                gnext = kNeg;
+                break;
+            }
+            const uint32_t col = (uint32_t)(last + 1);
+            const int32_t v = gnext;
+            if (!keep_state(a, v, col, rowgain)) {  // later columns only lose more
+                last = upto;
+                gnext = kNeg;
+                break;
+            }
+            if (check_dom && dominated(a, sub, x, gy)) {
+                s.st_dom++;
+            } else {
+                emit_entry<WRITE>(a, s, col, v, kNeg, gy, 0, 1);
+            }
+            last = col;
+            gnext = v + ext;
+        }
+    };
+
+    auto column = [&](uint32_t j, int32_t D, uint32_t yD, int32_t Gav, uint32_t yGav) {
+        spread_to((int64_t)j - 1);
+        const int32_t Gb = (last == (int64_t)j - 1) ? gnext : kNeg;
+        const uint32_t yGb = gy;
+        int32_t M = D;
+        uint32_t yM = yD;
+        if (Gav > M) {
+            M = Gav;
+            yM = yGav;
+        }
+        if (Gb > M) {
+            M = Gb;
+            yM = yGb;
+        }
+        const bool keepM = keep_state(a, M, j, rowgain);
+        const bool keepGa = keep_state(a, Gav, j, rowgain);
+        // G_b for column j+1 from this column's states that survive the filters
+        int32_t gn = kNeg;
+        uint32_t gny = 0;
+        if (keepM) {
+            gn = M + open;
+            gny = yM;
+            if (Gb + ext > gn && Gb > 0) {
+                gn = Gb + ext;
+                gny = yGb;
+            }
+        }
+        last = j;
+        gnext = gn;
+        gy = gny;
+        bool liveM = keepM, liveGa = keepGa;
+        if (check_dom) {
+            if (liveM && dominated(a, sub, x, yM)) {
+                liveM = false;
+                s.st_dom++;
+            }
+            if (liveGa && dominated(a, sub, x, yGav)) {
+                liveGa = false;
+                s.st_dom++;
+            }
+        }
+        if (liveM || liveGa) {
+            const int inputs = (D > 0) + (Gav > 0) + (Gb > 0);
+            emit_entry<WRITE>(a, s, j, liveM ? M : kNeg, liveGa ? Gav : kNeg, liveM ? yM : 0, liveGa ? yGav : 0,
+                              inputs);
+        }
+    };
+
+    for (uint32_t k = 0; k < plen; ++k) {
+        const Entry e = prow[k];
+        const uint32_t j = e.col;
+        // diagonal from the previous parent entry, if it sits in column j-1
+        int32_t D = kNeg;
+        uint32_t yD = 0;
+        if (k > 0) {
+            const Entry p = prow[k - 1];
+            if (p.col + 1 == j && p.M > 0) {
+                D = p.M + pc[j];
+                yD = p.yM;
+            }
+        }
+        // G_a: extend the parent's G_a or open from the parent's M in column j
+        int32_t Gav = kNeg;
+        uint32_t yGav = 0;
+        if (e.Ga > 0) {
+            Gav = e.Ga + ext;
+            yGav = e.yGa;
+        }
+        if (e.M > 0 && e.M + open > Gav) {
+            Gav = e.M + open;
+            yGav = e.yM;
+        }
+        column(j, D, yD, Gav, yGav);
+        // diagonal into column j+1 when no parent entry sits there
+        if (e.M > 0 && j + 1 < a.m && !(k + 1 < plen && prow[k + 1].col == j + 1)) {
+            column(j + 1, e.M + pc[j + 1], e.yM, kNeg, 0);
+        }
+    }
+    spread_to((int64_t)a.m - 1);
+}
+
+// ---------------------------------------------------------------------------
+// Wave helpers (wave64)
+// ---------------------------------------------------------------------------
+
+__device__ inline unsigned long long wave_excl_scan_u64(unsigned long long v, unsigned long long *total) {
+    const int lane = threadIdx.x & 63;
+    unsigned long long inc = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const unsigned long long o = __shfl_up(inc, d, 64);
+        if (lane >= d) inc += o;
+    }
+    *total = __shfl(inc, 63, 64);
+    return inc - v;
+}
+
+__device__ inline uint32_t wave_excl_scan_u32(uint32_t v, uint32_t *total) {
+    const int lane = threadIdx.x & 63;
+    uint32_t inc = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t o = __shfl_up(inc, d, 64);
+        if (lane >= d) inc += o;
+    }
+    *total = __shfl(inc, 63, 64);
+    return inc - v;
+}
+
+__device__ inline unsigned long long wave_sum_u64(unsigned long long v) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+    return v;
+}
+
+// Exclusive max-scan of (key, tag) over the lanes of a wave; ties keep the
+// lower lane.  ex: max over lanes below (kNegKey if none); all: over all lanes.
+__device__ inline void wave_excl_max(int64_t key, uint32_t tag, int64_t &ex_key, uint32_t &ex_tag, int64_t &all_key,
+                                     uint32_t &all_tag) {
+    const int lane = threadIdx.x & 63;
+    int64_t k = key;
+    uint32_t t = tag;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int64_t ok = __shfl_up(k, d, 64);
+        const uint32_t ot = __shfl_up(t, d, 64);
+        if (lane >= d && ok >= k) {
+            k = ok;
+            t = ot;
+        }
+    }
+    all_key = __shfl(k, 63, 64);
+    all_tag = __shfl(t, 63, 64);
+    ex_key = __shfl_up(k, 1, 64);
+    ex_tag = __shfl_up(t, 1, 64);
+    if (lane == 0) {
+        ex_key = kNegKey;
+        ex_tag = 0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Wave-parallel row update of a single-occurrence node
+// ---------------------------------------------------------------------------
+//
+// With key(k) = M0(k) + |ss| * k over the candidate columns k (M0 = the
+// diagonal/G_a part of M), the query-gap state is
+//     G_b(j) = sg - |ss| * j + max over candidates k < j of key(k),
+// an exclusive prefix maximum along the row (opening a gap from a G_b state is
+// never better than extending it, because sg <= 0).  Each lane owns one
+// parent entry: its column (G_a, and the diagonal of the previous entry) and
+// the next column (diagonal), plus the G_b-only columns up to the next lane's
+// first column.
+
+// Row storage seen by the wave-parallel update: entries with start tags in
+// global memory, or column/M/G_a arrays (no tags) in LDS.
+struct AosRow {
+    Entry *p;
+    __device__ Entry load(uint32_t k) const { return p[k]; }
+    __device__ void store(uint32_t k, const Entry &e) const { p[k] = e; }
+};
+
+struct SoaRow {
+    uint32_t *col;
+    int32_t *M;
+    int32_t *Ga;
+    __device__ Entry load(uint32_t k) const {
+        Entry e;
+        e.col = col[k];
+        e.M = M[k];
+        e.Ga = Ga[k];
+        e.yM = 0;
+        e.yGa = 0;
+        return e;
+    }
+    __device__ void store(uint32_t k, const Entry &e) const {
+        col[k] = e.col;
+        M[k] = e.M;
+        Ga[k] = e.Ga;
+    }
+};
+
+// Hit slots reserved by one wave in chunks; slots left unused are filled with
+// kPadKey so that they sort after every real record.
+constexpr unsigned long long kHitChunk = 4096;
+struct HitRes {
+    unsigned long long base;
+    unsigned long long left;
+    unsigned long long pad;
+};
+
+__device__ inline void hit_reserve(HitRes &r, unsigned long long need, uint64_t *hkeys, uint32_t *hscores,
+                                   unsigned long long hit_cap, Counters *cnt) {
+    if (need <= r.left) return;
+    const int lane = threadIdx.x & 63;
+    for (unsigned long long k = lane; k < r.left; k += 64) {
+        const unsigned long long slot = r.base + k;
+        if (slot < hit_cap) {
+            hkeys[slot] = kPadKey;
+            hscores[slot] = 0;
+        }
+    }
+    r.pad += r.left;
+    const unsigned long long take = need > kHitChunk ? need : kHitChunk;
+    unsigned long long b = 0;
+    if (lane == 0) {
+        b = atomicAdd(&cnt->hits, take);
+        if (b + take > hit_cap) atomicOr(&cnt->overflow, kOvHits);
+    }
+    r.base = __shfl(b, 0, 64);
+    r.left = take;
+}
+
+__device__ inline void hit_release(HitRes &r, uint64_t *hkeys, uint32_t *hscores, unsigned long long hit_cap,
+                                   Counters *cnt) {
+    const int lane = threadIdx.x & 63;
+    for (unsigned long long k = lane; k < r.left; k += 64) {
+        const unsigned long long slot = r.base + k;
+        if (slot < hit_cap) {
+            hkeys[slot] = kPadKey;
+            hscores[slot] = 0;
+        }
+    }
+    r.pad += r.left;
+    r.left = 0;
+    if (lane == 0 && r.pad) atomicAdd(&cnt->hit_padding, r.pad);
+    r.pad = 0;
+}
+
+struct WideOut {
+    bool emit_hits;    // emit hit records at e_child (single-occurrence nodes)
+    uint32_t cap;      // capacity of the output row
+    uint64_t *hkeys;
+    uint32_t *hscores;
+    unsigned long long hit_cap;
+    Counters *cnt;
+    uint32_t e_child;  // text end of the child occurrence (hit coordinate)
+    // results (wave-uniform)
+    uint32_t len;
+    bool overflow;
+    unsigned long long hits, diag, gap2, gap3;
+};
+
+template <class Row>
+__device__ inline void wide_child_row(const SearchArgs &a, const Row cur, uint32_t len, const Row nxt, int c,
+                                      int32_t d1, WideOut &o, HitRes &hr) {
+    const int lane = threadIdx.x & 63;
+    const int8_t *pc = a.prof + (size_t)c * a.m;
+    const int32_t open = a.sg + a.ss;
+    const int32_t ext = a.ss;
+    const int64_t absss = -(int64_t)a.ss;
+    const int32_t rowgain = a.smax * (a.lmax - d1);
+    constexpr uint32_t kNone = 0xFFFFFFFFu;
+    // carries between rounds (wave-uniform)
+    uint32_t c_pcol = kNone, c_pyM = 0;
+    int32_t c_pM = kNeg;
+    int64_t c_key = kNegKey;
+    uint32_t c_tag = 0;
+    uint32_t out = 0;
+    bool overflow = false;
+    unsigned long long hits = 0, diag = 0, gap2 = 0, gap3 = 0;
+    for (uint32_t base = 0; base < len; base += 64) {
+        const uint32_t k = base + lane;
+        const bool valid = k < len;
+        Entry e;
+        if (valid) {
+            e = cur.load(k);
+        } else {
+            e.col = kNone;
+            e.M = kNeg;
+            e.Ga = kNeg;
+            e.yM = 0;
+            e.yGa = 0;
+        }
+        uint32_t pcol = __shfl_up(e.col, 1, 64);
+        int32_t pM = __shfl_up(e.M, 1, 64);
+        uint32_t pyM = __shfl_up(e.yM, 1, 64);
+        if (lane == 0) {
+            pcol = c_pcol;
+            pM = c_pM;
+            pyM = c_pyM;
+        }
+        uint32_t ncol = __shfl_down(e.col, 1, 64);
+        if (lane == 63) ncol = (k + 1 < len) ? cur.load(k + 1).col : kNone;
+        if (k + 1 >= len) ncol = kNone;
+        // column A = e.col: diagonal from the previous entry and G_a
+        int32_t D = kNeg;
+        uint32_t yD = 0;
+        if (valid && pcol != kNone && pcol + 1 == e.col && pM > 0) {
+            D = pM + pc[e.col];
+            yD = pyM;
+        }
+        int32_t GaA = kNeg;
+        uint32_t yGaA = 0;
+        if (valid) {
+            if (e.Ga > 0) {
+                GaA = e.Ga + ext;
+                yGaA = e.yGa;
+            }
+            if (e.M > 0 && e.M + open > GaA) {
+                GaA = e.M + open;
+                yGaA = e.yM;
+            }
+        }
+        int32_t M0A = D;
+        uint32_t yM0A = yD;
+        if (GaA > M0A) {
+            M0A = GaA;
+            yM0A = yGaA;
+        }
+        // column B = e.col + 1: diagonal only, unless the next entry owns it
+        const bool hasB = valid && e.M > 0 && e.col + 1 < a.m && ncol != e.col + 1;
+        const int32_t M0B = hasB ? e.M + pc[e.col + 1] : kNeg;
+        const uint32_t yM0B = e.yM;
+        const int64_t kA = (valid && M0A > 0) ? (int64_t)M0A + absss * (int64_t)e.col : kNegKey;
+        const int64_t kB = (hasB && M0B > 0) ? (int64_t)M0B + absss * (int64_t)(e.col + 1) : kNegKey;
+        int64_t lk = kA;
+        uint32_t lt = yM0A;
+        if (kB > lk) {
+            lk = kB;
+            lt = yM0B;
+        }
+        int64_t exk, allk;
+        uint32_t ext_tag, allt;
+        wave_excl_max(lk, lt, exk, ext_tag, allk, allt);
+        if (c_key >= exk) {  // earlier rounds come first
+            exk = c_key;
+            ext_tag = c_tag;
+        }
+        // G_b and M at A
+        int32_t GbA = kNeg;
+        if (valid && exk > kNegKey) {
+            const int64_t v = exk + a.sg - absss * (int64_t)e.col;
+            GbA = v > 0 ? (int32_t)v : kNeg;
+        }
+        int32_t MA = M0A;
+        uint32_t yMA = yM0A;
+        if (GbA > MA) {
+            MA = GbA;
+            yMA = ext_tag;
+        }
+        const bool keepMA = valid && keep_state(a, MA, e.col, rowgain);
+        const bool keepGaA = valid && keep_state(a, GaA, e.col, rowgain);
+        // G_b and M at B
+        int64_t kAB = exk;
+        uint32_t tAB = ext_tag;
+        if (kA > kAB) {
+            kAB = kA;
+            tAB = yM0A;
+        }
+        int32_t GbB = kNeg;
+        if (hasB && kAB > kNegKey) {
+            const int64_t v = kAB + a.sg - absss * (int64_t)(e.col + 1);
+            GbB = v > 0 ? (int32_t)v : kNeg;
+        }
+        int32_t MB = M0B;
+        uint32_t yMB = yM0B;
+        if (GbB > MB) {
+            MB = GbB;
+            yMB = tAB;
+        }
+        const bool keepMB = hasB && keep_state(a, MB, e.col + 1, rowgain);
+        // G_b-only columns after this lane's last candidate, up to the next candidate
+        int64_t kinc = kAB;
+        uint32_t tinc = tAB;
+        if (kB > kinc) {
+            kinc = kB;
+            tinc = yM0B;
+        }
+        const uint32_t lc = hasB ? e.col + 1 : e.col;
+        const uint32_t stop = (ncol == kNone) ? a.m : ncol;
+        uint32_t nspread = 0, nspread_hits = 0;
+        if (valid && kinc > kNegKey) {
+            for (uint32_t col = lc + 1; col < stop; ++col) {
+                const int64_t v = kinc + a.sg - absss * (int64_t)col;
+                if (v <= 0 || !keep_state(a, (int32_t)v, col, rowgain)) break;
+                ++nspread;
+                nspread_hits += (v >= a.H);
+            }
+        }
+        const uint32_t nA = (keepMA || keepGaA) ? 1u : 0u;
+        const uint32_t nB = keepMB ? 1u : 0u;
+        const uint32_t cnt_lane = nA + nB + nspread;
+        uint32_t tot;
+        const uint32_t pre = wave_excl_scan_u32(cnt_lane, &tot);
+        if (out + tot <= o.cap) {
+            uint32_t p = out + pre;
+            if (nA) {
+                Entry w;
+                w.col = e.col;
+                w.M = keepMA ? MA : kNeg;
+                w.Ga = keepGaA ? GaA : kNeg;
+                w.yM = keepMA ? yMA : 0;
+                w.yGa = keepGaA ? yGaA : 0;
+                nxt.store(p++, w);
+            }
+            if (nB) {
+                Entry w;
+                w.col = e.col + 1;
+                w.M = MB;
+                w.Ga = kNeg;
+                w.yM = yMB;
+                w.yGa = 0;
+                nxt.store(p++, w);
+            }
+            for (uint32_t s = 0; s < nspread; ++s) {
+                const uint32_t col = lc + 1 + s;
+                Entry w;
+                w.col = col;
+                w.M = (int32_t)(kinc + a.sg - absss * (int64_t)col);
+                w.Ga = kNeg;
+                w.yM = tinc;
+                w.yGa = 0;
+                nxt.store(p++, w);
+            }
+        } else {
+            overflow = true;
+        }
+        // hit records of this round's entries
+        const uint32_t nh = !o.emit_hits ? 0u
+                                         : (nA && keepMA && MA >= a.H ? 1u : 0u) + (nB && MB >= a.H ? 1u : 0u) +
+                                               nspread_hits;
+        uint32_t htot;
+        const uint32_t hpre = wave_excl_scan_u32(nh, &htot);
+        if (htot) {
+            hit_reserve(hr, htot, o.hkeys, o.hscores, o.hit_cap, o.cnt);
+            unsigned long long slot = hr.base + hpre;
+            auto put = [&](uint32_t col, int32_t M) {
+                if (slot < o.hit_cap) {
+                    o.hkeys[slot] = ((uint64_t)col << 32) | o.e_child;
+                    o.hscores[slot] = (uint32_t)M;
+                }
+                ++slot;
+            };
+            if (nA && keepMA && MA >= a.H) put(e.col, MA);
+            if (nB && MB >= a.H) put(e.col + 1, MB);
+            for (uint32_t s = 0; s < nspread; ++s) {
+                const uint32_t col = lc + 1 + s;
+                const int32_t v = (int32_t)(kinc + a.sg - absss * (int64_t)col);
+                if (v < a.H) break;
+                put(col, v);
+            }
+            hr.base += htot;
+            hr.left -= htot;
+            hits += htot;
+        }
+        // cost classes of the entries of this round
+        uint32_t c1 = nspread, c2 = 0, c3 = 0;
+        if (nA) {
+            const int in = (D > 0) + (GaA > 0) + (GbA > 0);
+            if (in <= 1)
+                ++c1;
+            else if (in == 2)
+                ++c2;
+            else
+                ++c3;
+        }
+        if (nB) {
+            if (GbB > 0)
+                ++c2;
+            else
+                ++c1;
+        }
+        diag += wave_sum_u64(c1);
+        gap2 += wave_sum_u64(c2);
+        gap3 += wave_sum_u64(c3);
+        // carries for the next round
+        const int lastlane = (int)((len - base - 1) < 63u ? (len - base - 1) : 63u);
+        c_pcol = __shfl(e.col, lastlane, 64);
+        c_pM = __shfl(e.M, lastlane, 64);
+        c_pyM = __shfl(e.yM, lastlane, 64);
+        if (allk > c_key) {
+            c_key = allk;
+            c_tag = allt;
+        }
+        out += tot;
+    }
+    o.len = out;
+    o.overflow = overflow;
+    o.hits = hits;
+    o.diag = diag;
+    o.gap2 = gap2;
+    o.gap3 = gap3;
+}
+
+}  // namespace alae

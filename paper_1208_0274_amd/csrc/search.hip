@@ -29,6 +29,9 @@
 #include "alae_internal.h"
 #include "device_algos.h"
 #include "device_common.h"
+#include "row_update.h"
+#include "level_kernels.h"
+#include "chain_kernels.h"
 
 namespace alae {
 
@@ -58,7 +61,9 @@ alae_status ensure_device(const alae_index *idx) {
         return ALAE_E_DEVICE;
     }
     HIP_TRY(hipSetDevice(idx->device));
-    HIP_TRY(hipMalloc(&idx->d_text, idx->text.size() + 64));
+    HIP_TRY(hipMalloc(&idx->d_text_alloc, idx->text.size() + 2 * kSlack));
+    HIP_TRY(hipMemset(idx->d_text_alloc, 0, idx->text.size() + 2 * kSlack));
+    idx->d_text = idx->d_text_alloc + kSlack;
     HIP_TRY(hipMalloc(&idx->d_sa, idx->sa_end.size() * sizeof(uint32_t)));
     HIP_TRY(hipMalloc(&idx->d_occ, idx->occ.size()));
     HIP_TRY(hipMemcpy(idx->d_text, idx->text.data(), idx->text.size(), hipMemcpyHostToDevice));
@@ -72,50 +77,15 @@ void release_device(const alae_index *idx) {
     std::lock_guard<std::mutex> lock(idx->mu);
     if (!idx->on_device) return;
     hipSetDevice(idx->device);
-    hipFree(idx->d_text);
+    hipFree(idx->d_text_alloc);
     hipFree(idx->d_sa);
     hipFree(idx->d_occ);
     idx->d_text = nullptr;
+    idx->d_text_alloc = nullptr;
     idx->d_sa = nullptr;
     idx->d_occ = nullptr;
     idx->on_device = false;
 }
-
-// ---------------------------------------------------------------------------
-// Counters shared by the kernels of one search
-// ---------------------------------------------------------------------------
-
-struct Counters {
-    unsigned long long nodes;     // child nodes allocated in the output level
-    unsigned long long entries;   // entries allocated in the output level
-    unsigned long long hits;      // hit records allocated in total
-    unsigned long long overflow;  // bit 0 nodes, bit 1 entries, bit 2 hits
-    // statistics
-    unsigned long long st_nodes;
-    unsigned long long st_entries;
-    unsigned long long st_diag;
-    unsigned long long st_gap2;
-    unsigned long long st_gap3;
-    unsigned long long st_dominated;
-    unsigned long long st_emitted;
-    unsigned long long bad_query;
-    // random-access reads of the expansion kernel (64-byte granules)
-    unsigned long long st_occ_reads;
-    unsigned long long st_sa_reads;
-    unsigned long long st_text_reads;
-    // frontier bytes read and written by the expansion kernel
-    unsigned long long st_frontier_bytes;
-};
-
-struct Caps {
-    unsigned long long nodes;
-    unsigned long long entries;
-    unsigned long long hits;
-};
-
-struct SubTable {
-    int8_t s[20 * 20];
-};
 
 // ---------------------------------------------------------------------------
 // Query preparation kernels
@@ -190,6 +160,7 @@ __device__ inline void backward_step(const SearchArgs &a, int c, int64_t &l, int
 // Seed entries and nodes from the sorted (key, column) pairs.
 __global__ void k_seed_nodes(SearchArgs a, const uint64_t *keys, const uint32_t *vals, uint64_t count,
                              uint64_t invalid, int qeff, int matrix_mode, int32_t seedM, Entry *ent, Node *nodes,
+                             Node *wide_nodes,
                              Counters *cnt) {
     uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= count) return;
@@ -216,13 +187,18 @@ __global__ void k_seed_nodes(SearchArgs a, const uint64_t *keys, const uint32_t 
     }
     for (int k = 0; k < qeff && l <= r; ++k) backward_step(a, chars[k], l, r);
     if (l > r) return;
-    unsigned long long slot = atomicAdd(&cnt->nodes, 1ull);
     Node nd;
     nd.lo = (uint32_t)l;
     nd.hi = (uint32_t)r;
     nd.off = (uint32_t)i;
     nd.len = (uint32_t)(end - i);
-    nodes[slot] = nd;
+    if (nd.len > kLaneRow) {  // long seed rows are expanded by a whole wave
+        const unsigned long long slot = atomicAdd(&cnt->lwnodes, 1ull);
+        wide_nodes[slot] = nd;
+    } else {
+        const unsigned long long slot = atomicAdd(&cnt->nodes, 1ull);
+        nodes[slot] = nd;
+    }
 }
 
 // Hits of the seed level (only when a seed entry already reaches H).
@@ -244,402 +220,6 @@ __global__ void k_seed_hits(SearchArgs a, const Node *nodes, uint32_t nn, const 
             hscores[slot] = (uint32_t)e.M;
         }
         atomicAdd(&cnt->st_emitted, (unsigned long long)(nd.hi - nd.lo + 1));
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Row update
-// ---------------------------------------------------------------------------
-
-// Section 3.2 (Theorem 4, case 2), tested locally: the state whose best
-// alignment starts at text position x and query column y is dominated when
-// an ungapped alignment ending at (x-1, y-1) scores above zero, because
-// prepending it would beat that alignment at every cell it reaches.
-__device__ inline bool dominated(const SearchArgs &a, int64_t x, int64_t y) {
-    int64_t reach = a.dom_reach;
-    if (x < reach) reach = x;
-    if (y < reach) reach = y;
-    int32_t sum = 0;
-    for (int64_t k = 1; k <= reach; ++k) {
-        sum += a.prof[(size_t)a.text[x - k] * a.m + (y - k)];
-        if (sum > 0) return true;
-        if (sum + a.smax * (int32_t)(reach - k) <= 0) return false;
-    }
-    return false;
-}
-
-struct RowSink {
-    // output row (WRITE mode)
-    Entry *out;
-    uint64_t *hkeys;
-    uint32_t *hscores;
-    unsigned long long hit_base;
-    unsigned long long hit_cap;
-    // occurrences of the child
-    bool unique;
-    uint32_t e_end;  // unique: text end
-    uint32_t lo, hi; // otherwise: BWT rows
-    // results
-    uint32_t n_entries;
-    uint32_t n_hits;
-    uint32_t st_diag, st_gap2, st_gap3, st_dom;
-};
-
-template <bool WRITE>
-__device__ inline void emit_entry(const SearchArgs &a, RowSink &s, uint32_t col, int32_t M, int32_t Ga, uint32_t yM,
-                                  uint32_t yGa, int inputs) {
-    if (WRITE) {
-        Entry e;
-        e.col = col;
-        e.M = M;
-        e.Ga = Ga;
-        e.yM = yM;
-        e.yGa = yGa;
-        s.out[s.n_entries] = e;
-        if (inputs <= 1)
-            s.st_diag++;
-        else if (inputs == 2)
-            s.st_gap2++;
-        else
-            s.st_gap3++;
-    }
-    s.n_entries++;
-    if (M >= a.H) {
-        if (s.unique) {
-            if (WRITE) {
-                unsigned long long slot = s.hit_base + s.n_hits;
-                if (slot < s.hit_cap) {
-                    s.hkeys[slot] = ((uint64_t)col << 32) | s.e_end;
-                    s.hscores[slot] = (uint32_t)M;
-                }
-            }
-            s.n_hits++;
-        } else {
-            for (uint32_t h = s.lo; h <= s.hi; ++h) {
-                if (WRITE) {
-                    unsigned long long slot = s.hit_base + s.n_hits;
-                    if (slot < s.hit_cap) {
-                        s.hkeys[slot] = ((uint64_t)col << 32) | a.sa[h];
-                        s.hscores[slot] = (uint32_t)M;
-                    }
-                }
-                s.n_hits++;
-            }
-        }
-    }
-}
-
-// Filters applied to one state value at column `col` of a row at depth d1:
-// zero floor (Theorem 2 (i)) and score filter (Theorem 2 (ii)) with the gain
-// bound min(U(col), smax * (L_max - d1)).
-__device__ inline bool keep_state(const SearchArgs &a, int32_t v, uint32_t col, int32_t rowgain) {
-    if (v <= 0) return false;
-    if (!a.use_score_filter) return true;
-    int32_t g = a.U[col];
-    if (rowgain < g) g = rowgain;
-    return v + g >= a.H;
-}
-
-// Computes the row at depth d1 of the child reached with character c from the
-// parent row prow[0..plen).  Candidate columns are the parent's columns (G_a:
-// a text character against a gap) and the parent's columns + 1 (diagonal);
-// G_b (a query character against a gap) runs left to right along the row,
-// including through columns with no candidate.  `check_dom` applies the
-// domination test with the occurrence starting at text position x.
-template <bool WRITE>
-__device__ void child_row(const SearchArgs &a, const Entry *prow, uint32_t plen, int c, int32_t d1, bool check_dom,
-                          int64_t x, RowSink &s) {
-    const int8_t *pc = a.prof + (size_t)c * a.m;
-    const int32_t open = a.sg + a.ss;  // first gap character
-    const int32_t ext = a.ss;
-    const int32_t rowgain = a.smax * (a.lmax - d1);
-    int64_t last = -1;       // last column already handled
-    int32_t gnext = kNeg;    // G_b value for column last+1
-    uint32_t gy = 0;         // its start column
-
-    auto spread_to = [&](int64_t upto) {  // G_b-only columns last+1 .. upto
-        while (last < upto) {
-            if (gnext <= 0) {
-                last = upto;
-                gnext = kNeg;
-                break;
-            }
-            const uint32_t col = (uint32_t)(last + 1);
-            const int32_t v = gnext;
-            if (keep_state(a, v, col, rowgain)) {
-                bool dom = check_dom && dominated(a, x, gy);
-                if (dom) {
-                    s.st_dom++;
-                } else {
-                    emit_entry<WRITE>(a, s, col, v, kNeg, gy, 0, 1);
-                }
-            }
-            last = col;
-            gnext = v + ext;
-        }
-    };
-
-    auto column = [&](uint32_t j, int32_t D, uint32_t yD, int32_t Gav, uint32_t yGav) {
-        spread_to((int64_t)j - 1);
-        const int32_t Gb = (last == (int64_t)j - 1) ? gnext : kNeg;
-        const uint32_t yGb = gy;
-        int32_t M = D;
-        uint32_t yM = yD;
-        if (Gav > M) {
-            M = Gav;
-            yM = yGav;
-        }
-        if (Gb > M) {
-            M = Gb;
-            yM = yGb;
-        }
-        const bool keepM = keep_state(a, M, j, rowgain);
-        const bool keepGa = keep_state(a, Gav, j, rowgain);
-        // G_b for column j+1 from this column's states that survive the filters
-        int32_t gn = kNeg;
-        uint32_t gny = 0;
-        if (keepM) {
-            gn = M + open;
-            gny = yM;
-            if (Gb + ext > gn && Gb > 0) {
-                gn = Gb + ext;
-                gny = yGb;
-            }
-        }
-        last = j;
-        gnext = gn;
-        gy = gny;
-        bool liveM = keepM, liveGa = keepGa;
-        if (check_dom) {
-            if (liveM && dominated(a, x, yM)) {
-                liveM = false;
-                s.st_dom++;
-            }
-            if (liveGa && dominated(a, x, yGav)) {
-                liveGa = false;
-                s.st_dom++;
-            }
-        }
-        if (liveM || liveGa) {
-            const int inputs = (D > 0) + (Gav > 0) + (Gb > 0);
-            emit_entry<WRITE>(a, s, j, liveM ? M : kNeg, liveGa ? Gav : kNeg, liveM ? yM : 0, liveGa ? yGav : 0,
-                              inputs);
-        }
-    };
-
-    for (uint32_t k = 0; k < plen; ++k) {
-        const Entry e = prow[k];
-        const uint32_t j = e.col;
-        // diagonal from the previous parent entry, if it sits in column j-1
-        int32_t D = kNeg;
-        uint32_t yD = 0;
-        if (k > 0) {
-            const Entry p = prow[k - 1];
-            if (p.col + 1 == j && p.M > 0) {
-                D = p.M + pc[j];
-                yD = p.yM;
-            }
-        }
-        // G_a: extend the parent's G_a or open from the parent's M in column j
-        int32_t Gav = kNeg;
-        uint32_t yGav = 0;
-        if (e.Ga > 0) {
-            Gav = e.Ga + ext;
-            yGav = e.yGa;
-        }
-        if (e.M > 0 && e.M + open > Gav) {
-            Gav = e.M + open;
-            yGav = e.yM;
-        }
-        column(j, D, yD, Gav, yGav);
-        // diagonal into column j+1 when no parent entry sits there
-        if (e.M > 0 && j + 1 < a.m && !(k + 1 < plen && prow[k + 1].col == j + 1)) {
-            column(j + 1, e.M + pc[j + 1], e.yM, kNeg, 0);
-        }
-    }
-    spread_to((int64_t)a.m - 1);
-}
-
-// ---------------------------------------------------------------------------
-// Level expansion: one lane per frontier node
-// ---------------------------------------------------------------------------
-
-__device__ inline unsigned long long wave_excl_scan_u64(unsigned long long v, unsigned long long *total) {
-    const int lane = threadIdx.x & 63;
-    unsigned long long inc = v;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        unsigned long long o = __shfl_up(inc, d, 64);
-        if (lane >= d) inc += o;
-    }
-    *total = __shfl(inc, 63, 64);
-    return inc - v;
-}
-
-__device__ inline unsigned long long wave_sum_u64(unsigned long long v) {
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
-    return v;
-}
-
-struct ChildIter {
-    int64_t lo[20];
-    int64_t hi[20];
-};
-
-template <bool WRITE>
-__device__ void expand_node(const SearchArgs &a, const Node &nd, const Entry *prow, int32_t d1, uint32_t &nodes_out,
-                            uint32_t &entries_out, uint32_t &hits_out, Node *onodes, Entry *oent,
-                            uint64_t *hkeys, uint32_t *hscores, unsigned long long node_base,
-                            unsigned long long ent_base, unsigned long long hit_base, Caps caps,
-                            uint32_t st[7]) {
-    nodes_out = entries_out = hits_out = 0;
-    const bool parent_unique = (nd.lo & kUniqueBit) != 0;
-    uint32_t o_lo[4] = {0, 0, 0, 0}, o_hi[4] = {0, 0, 0, 0};
-    if (!parent_unique) {
-        if (a.sigma == 4) {
-            occ4_dna(a, (int64_t)nd.lo - 1, o_lo);
-            occ4_dna(a, (int64_t)nd.hi, o_hi);
-        }
-        const int bc = a.sigma == 4 ? kDnaBlockChars : kGenBlockChars;
-        const int64_t b0 = nd.lo == 0 ? -1 : ((int64_t)nd.lo - 1) / bc;
-        const int64_t b1 = (int64_t)nd.hi / bc;
-        st[4] += (b0 >= 0 && b0 != b1) ? 2u : 1u;
-    } else {
-        st[6] += 1;  // the next text character
-    }
-    for (int c = 0; c < a.sigma; ++c) {
-        RowSink s;
-        int64_t x = 0;
-        bool check = false;
-        if (parent_unique) {
-            const uint32_t e = nd.lo & ~kUniqueBit;
-            if ((uint64_t)e + 1 >= a.n || a.text[e + 1] != c) continue;
-            s.unique = true;
-            s.e_end = e + 1;
-            s.lo = s.hi = 0;
-        } else {
-            int64_t l, r;
-            if (a.sigma == 4) {
-                l = (int64_t)a.C[c] + o_lo[c];
-                r = (int64_t)a.C[c] + o_hi[c] - 1;
-            } else {
-                l = (int64_t)a.C[c] + occ1_gen(a, c, (int64_t)nd.lo - 1);
-                r = (int64_t)a.C[c] + occ1_gen(a, c, (int64_t)nd.hi) - 1;
-            }
-            if (l > r) continue;
-            if (l == r) {
-                s.unique = true;
-                s.e_end = a.sa[l];
-                st[5] += 1;
-                check = a.use_domination != 0;
-            } else {
-                s.unique = false;
-                s.lo = (uint32_t)l;
-                s.hi = (uint32_t)r;
-            }
-        }
-        if (check) x = (int64_t)s.e_end - d1 + 1;
-        s.out = oent + ent_base + entries_out;
-        s.hkeys = hkeys;
-        s.hscores = hscores;
-        s.hit_base = hit_base + hits_out;
-        s.hit_cap = caps.hits;
-        s.n_entries = s.n_hits = 0;
-        s.st_diag = s.st_gap2 = s.st_gap3 = s.st_dom = 0;
-        child_row<WRITE>(a, prow, nd.len, c, d1, check, x, s);
-        if (s.n_entries > 0) {
-            if (WRITE) {
-                Node cn;
-                if (s.unique) {
-                    cn.lo = kUniqueBit | s.e_end;
-                    cn.hi = 0;
-                } else {
-                    cn.lo = s.lo;
-                    cn.hi = s.hi;
-                }
-                cn.off = (uint32_t)(ent_base + entries_out);
-                cn.len = s.n_entries;
-                onodes[node_base + nodes_out] = cn;
-            }
-            nodes_out++;
-        }
-        entries_out += s.n_entries;
-        hits_out += s.n_hits;
-        st[0] += s.st_diag;
-        st[1] += s.st_gap2;
-        st[2] += s.st_gap3;
-        st[3] += s.st_dom;
-    }
-}
-
-__global__ void __launch_bounds__(256) k_expand_level(SearchArgs a, const Node *nodes, uint32_t nn, const Entry *ent,
-                                                      int32_t d1, Node *onodes, Entry *oent, uint64_t *hkeys,
-                                                      uint32_t *hscores, Caps caps, Counters *cnt) {
-    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-    const bool active = t < nn;
-    Node nd;
-    nd.lo = nd.hi = nd.off = nd.len = 0;
-    if (active) nd = nodes[t];
-    uint32_t n_nodes = 0, n_ent = 0, n_hits = 0;
-    uint32_t st[7] = {0, 0, 0, 0, 0, 0, 0};
-    if (active) {
-        expand_node<false>(a, nd, ent + nd.off, d1, n_nodes, n_ent, n_hits, nullptr, nullptr, nullptr, nullptr, 0,
-                           0, 0, caps, st);
-    }
-    // allocate this wave's output with one atomic per counter
-    unsigned long long tot_nodes, tot_ent, tot_hits;
-    unsigned long long pre_nodes = wave_excl_scan_u64(n_nodes, &tot_nodes);
-    unsigned long long pre_ent = wave_excl_scan_u64(n_ent, &tot_ent);
-    unsigned long long pre_hits = wave_excl_scan_u64(n_hits, &tot_hits);
-    const int lane = threadIdx.x & 63;
-    unsigned long long b_nodes = 0, b_ent = 0, b_hits = 0;
-    if (lane == 0) {
-        if (tot_nodes) b_nodes = atomicAdd(&cnt->nodes, tot_nodes);
-        if (tot_ent) b_ent = atomicAdd(&cnt->entries, tot_ent);
-        if (tot_hits) b_hits = atomicAdd(&cnt->hits, tot_hits);
-    }
-    b_nodes = __shfl(b_nodes, 0, 64);
-    b_ent = __shfl(b_ent, 0, 64);
-    b_hits = __shfl(b_hits, 0, 64);
-    bool fits = true;
-    if (lane == 0) {
-        unsigned long long of = 0;
-        if (b_nodes + tot_nodes > caps.nodes) of |= 1ull;
-        if (b_ent + tot_ent > caps.entries) of |= 2ull;
-        if (b_hits + tot_hits > caps.hits) of |= 4ull;
-        if (of) atomicOr(&cnt->overflow, of);
-    }
-    if (b_nodes + tot_nodes > caps.nodes || b_ent + tot_ent > caps.entries) fits = false;
-    uint32_t st2[7] = {0, 0, 0, 0, 0, 0, 0};
-    if (active && fits && n_nodes > 0) {
-        uint32_t w_nodes, w_ent, w_hits;
-        expand_node<true>(a, nd, ent + nd.off, d1, w_nodes, w_ent, w_hits, onodes, oent, hkeys, hscores,
-                          b_nodes + pre_nodes, b_ent + pre_ent, b_hits + pre_hits, caps, st2);
-    }
-    unsigned long long s_nodes = wave_sum_u64(active ? 1 : 0);
-    unsigned long long s_ent = wave_sum_u64(n_ent);
-    unsigned long long s_diag = wave_sum_u64(st2[0]);
-    unsigned long long s_g2 = wave_sum_u64(st2[1]);
-    unsigned long long s_g3 = wave_sum_u64(st2[2]);
-    unsigned long long s_dom = wave_sum_u64(st[3]);
-    unsigned long long s_occ = wave_sum_u64(st[4]);
-    unsigned long long s_sa = wave_sum_u64(st[5]);
-    unsigned long long s_txt = wave_sum_u64(st[6]);
-    unsigned long long s_in = wave_sum_u64(active ? (unsigned long long)(sizeof(Node) + nd.len * sizeof(Entry)) : 0ull);
-    if (lane == 0) {
-        if (s_occ) atomicAdd(&cnt->st_occ_reads, s_occ);
-        if (s_sa) atomicAdd(&cnt->st_sa_reads, s_sa);
-        if (s_txt) atomicAdd(&cnt->st_text_reads, s_txt);
-        atomicAdd(&cnt->st_frontier_bytes,
-                  s_in + tot_nodes * sizeof(Node) + tot_ent * sizeof(Entry) + tot_hits * 12ull);
-        if (s_nodes) atomicAdd(&cnt->st_nodes, s_nodes);
-        if (s_ent) atomicAdd(&cnt->st_entries, s_ent);
-        if (s_diag) atomicAdd(&cnt->st_diag, s_diag);
-        if (s_g2) atomicAdd(&cnt->st_gap2, s_g2);
-        if (s_g3) atomicAdd(&cnt->st_gap3, s_g3);
-        if (s_dom) atomicAdd(&cnt->st_dominated, s_dom);
-        if (tot_hits) atomicAdd(&cnt->st_emitted, tot_hits);
     }
 }
 
@@ -723,6 +303,8 @@ struct alae_workspace {
     // query
     uint8_t *d_query = nullptr;
     uint64_t q_cap = 0;
+    uint8_t *qpad = nullptr;
+    uint64_t qpad_cap = 0;
     int8_t *prof = nullptr;
     uint64_t prof_cap = 0;
     int32_t *U = nullptr;
@@ -735,6 +317,30 @@ struct alae_workspace {
     uint64_t *seed_keys_alt = nullptr;
     uint32_t *seed_vals_alt = nullptr;
     uint64_t seed_alt_cap = 0;
+    // wide queue (whole search), its spill queue, global row buffers
+    Node *lwide[2] = {nullptr, nullptr};  // level nodes with rows longer than a lane takes
+    uint64_t lwide_cap[2] = {0, 0};
+    Node *cnodes = nullptr;               // chains created by one level
+    uint64_t cnode_cap = 0;
+    Entry *cents = nullptr;
+    uint64_t cent_cap = 0;
+    Node *gnodes = nullptr;               // chains with gap states
+    uint64_t gnode_cap = 0;
+    Entry *gents = nullptr;
+    uint64_t gent_cap = 0;
+    Entry *stage = nullptr;               // per-block row staging of k_expand_level_wide
+    uint64_t stage_cap = 0;
+    Node *onodes = nullptr;
+    uint64_t onode_cap = 0;
+    Entry *oents = nullptr;
+    uint64_t oent_cap = 0;
+    Node *wnodes = nullptr;
+    uint64_t wnode_cap = 0;
+    Entry *wents = nullptr;
+    uint64_t went_cap = 0;
+    Entry *rowbuf = nullptr;
+    uint64_t rowbuf_cap = 0;
+    uint64_t wrow_cap = 0;
     // counters
     Counters *d_cnt = nullptr;
     Counters *h_cnt = nullptr;
@@ -760,6 +366,7 @@ static void ws_release(alae_workspace *ws) {
     hipFree(ws->res_keys);
     hipFree(ws->res_scores);
     hipFree(ws->d_query);
+    hipFree(ws->qpad);
     hipFree(ws->prof);
     hipFree(ws->U);
     hipFree(ws->colrev);
@@ -767,6 +374,18 @@ static void ws_release(alae_workspace *ws) {
     hipFree(ws->seed_vals);
     hipFree(ws->seed_keys_alt);
     hipFree(ws->seed_vals_alt);
+    hipFree(ws->onodes);
+    hipFree(ws->oents);
+    hipFree(ws->lwide[0]);
+    hipFree(ws->lwide[1]);
+    hipFree(ws->cnodes);
+    hipFree(ws->cents);
+    hipFree(ws->gnodes);
+    hipFree(ws->gents);
+    hipFree(ws->stage);
+    hipFree(ws->wnodes);
+    hipFree(ws->wents);
+    hipFree(ws->rowbuf);
     hipFree(ws->d_cnt);
     if (ws->h_cnt) hipHostFree(ws->h_cnt);
     if (ws->ev0) hipEventDestroy(ws->ev0);
@@ -922,6 +541,11 @@ static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64
     a.lmax = (int32_t)lmax;
     a.use_score_filter = use_score_filter ? 1 : 0;
     a.use_domination = use_dom ? 1 : 0;
+    a.u_closed = sch.matrix_mode ? 0 : 1;
+    a.ngr_walk = getenv("ALAE_NO_NGR") ? 0 : 1;
+    a.matrix_mode = sch.matrix_mode;
+    a.s_match = sch.matrix_mode ? 0 : scoring->sa;
+    a.s_mismatch = sch.matrix_mode ? 0 : scoring->sb;
     a.dom_reach = 32;
     for (int c = 0; c <= sigma; ++c) a.C[c] = (uint32_t)idx->C[c];
 
@@ -929,6 +553,12 @@ static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64
     memset(&sub, 0, sizeof(sub));
     memcpy(sub.s, sch.sub, (size_t)sigma * sigma);
 
+    // the query with readable slack around it (windows of the domination test)
+    if ((st = grow(ws->qpad, ws->qpad_cap, m + 2 * kSlack, false, 0, s)) != ALAE_OK) return st;
+    HIP_TRY(hipMemsetAsync(ws->qpad, 0, kSlack, s));
+    HIP_TRY(hipMemsetAsync(ws->qpad + kSlack + m, 0, kSlack, s));
+    HIP_TRY(hipMemcpyAsync(ws->qpad + kSlack, d_query, m, hipMemcpyDeviceToDevice, s));
+    a.query = ws->qpad + kSlack;
     HIP_TRY(hipMemsetAsync(ws->d_cnt, 0, sizeof(Counters), s));
     const uint32_t tb = 256;
     const uint32_t gm = (uint32_t)((m + tb - 1) / tb);
@@ -963,13 +593,16 @@ static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64
         if ((st = grow(ws->nodes[i], ws->node_cap[i], std::max<uint64_t>(nseed, 1ull << 20), false, 0, s)) != ALAE_OK)
             return st;
     }
+    if ((st = grow(ws->lwide[0], ws->lwide_cap[0], std::max<uint64_t>(nseed, 1ull << 12), false, 0, s)) != ALAE_OK)
+        return st;
+    if ((st = grow(ws->lwide[1], ws->lwide_cap[1], 1ull << 12, false, 0, s)) != ALAE_OK) return st;
     uint64_t hit_want = opts && opts->hit_capacity ? opts->hit_capacity : (1ull << 20);
     if ((st = grow_pair(ws->hkeys, ws->hscores, ws->hit_cap, hit_want, 0, s)) != ALAE_OK) return st;
 
     const int32_t seedM = matrix_seeds ? 0 : qeff * sch.sa;
     k_seed_nodes<<<(uint32_t)((nseed + tb - 1) / tb), tb, 0, s>>>(a, sk, sv, nseed, invalid, seed_depth,
                                                                    matrix_seeds ? 1 : 0, seedM, ws->ents[0],
-                                                                   ws->nodes[0], ws->d_cnt);
+                                                                   ws->nodes[0], ws->lwide[0], ws->d_cnt);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipMemcpyAsync(ws->h_cnt, ws->d_cnt, sizeof(Counters), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
@@ -983,15 +616,22 @@ static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64
     Caps caps;
     caps.hits = ws->hit_cap;
     // seed-level hits (only when a seed score reaches H)
+    uint64_t nlw0 = ws->h_cnt->lwnodes;
     int32_t seed_best = matrix_seeds ? sch.smax : seedM;
-    if (seed_best >= H && nn > 0) {
+    if (seed_best >= H && (nn > 0 || nlw0 > 0)) {
         for (;;) {
             caps.hits = ws->hit_cap;
-            k_seed_hits<<<(uint32_t)((nn + tb - 1) / tb), tb, 0, s>>>(a, ws->nodes[cur], (uint32_t)nn, ws->ents[cur],
-                                                                     caps, ws->hkeys, ws->hscores, ws->d_cnt);
+            if (nn > 0)
+                k_seed_hits<<<(uint32_t)((nn + tb - 1) / tb), tb, 0, s>>>(a, ws->nodes[cur], (uint32_t)nn,
+                                                                         ws->ents[cur], caps, ws->hkeys, ws->hscores,
+                                                                         ws->d_cnt);
+            if (nlw0 > 0)
+                k_seed_hits<<<(uint32_t)((nlw0 + tb - 1) / tb), tb, 0, s>>>(a, ws->lwide[cur], (uint32_t)nlw0,
+                                                                           ws->ents[cur], caps, ws->hkeys,
+                                                                           ws->hscores, ws->d_cnt);
             HIP_TRY(hipMemcpyAsync(ws->h_cnt, ws->d_cnt, sizeof(Counters), hipMemcpyDeviceToHost, s));
             HIP_TRY(hipStreamSynchronize(s));
-            if (!(ws->h_cnt->overflow & 4ull)) break;
+            if (!(ws->h_cnt->overflow & kOvHits)) break;
             if ((st = grow_pair(ws->hkeys, ws->hscores, ws->hit_cap, ws->h_cnt->hits, 0, s)) != ALAE_OK) return st;
             Counters z = *ws->h_cnt;
             z.hits = 0;
@@ -1004,57 +644,258 @@ static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64
 
     uint64_t levels = 0, retries = 0, max_depth = nn ? (uint64_t)seed_depth : 0;
     uint64_t launches = 0;
-    double expand_ms = 0.0;
+    double expand_ms = 0.0, chain_ms = 0.0, wide_ms = 0.0;
     int32_t depth = seed_depth;
-    while (nn > 0 && depth < lmax) {
+    int cus = 256;
+    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ws->device);
+    const uint32_t max_waves = (uint32_t)cus * 8u;
+    const uint64_t wrow = m + 2;  // a row never holds more than m entries
+    // queues that live through the whole search
+    for (int i = 0; i < 2; ++i)
+        if ((st = grow(ws->lwide[i], ws->lwide_cap[i], 1ull << 12, false, 0, s)) != ALAE_OK) return st;
+    if ((st = grow(ws->cnodes, ws->cnode_cap, 1ull << 20, false, 0, s)) != ALAE_OK) return st;
+    if ((st = grow(ws->cents, ws->cent_cap, 1ull << 21, false, 0, s)) != ALAE_OK) return st;
+    if ((st = grow(ws->gnodes, ws->gnode_cap, 1ull << 16, false, 0, s)) != ALAE_OK) return st;
+    if ((st = grow(ws->gents, ws->gent_cap, 1ull << 20, false, 0, s)) != ALAE_OK) return st;
+    if ((st = grow(ws->wnodes, ws->wnode_cap, 1ull << 14, false, 0, s)) != ALAE_OK) return st;
+    if ((st = grow(ws->wents, ws->went_cap, 1ull << 20, false, 0, s)) != ALAE_OK) return st;
+    if ((st = grow(ws->onodes, ws->onode_cap, 1ull << 10, false, 0, s)) != ALAE_OK) return st;
+    if ((st = grow(ws->oents, ws->oent_cap, 1ull << 18, false, 0, s)) != ALAE_OK) return st;
+    auto timed = [&](double &acc) -> alae_status {
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipEventRecord(ws->evk1, s));
+        HIP_TRY(hipMemcpyAsync(ws->h_cnt, ws->d_cnt, sizeof(Counters), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        float kms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&kms, ws->evk0, ws->evk1));
+        acc += kms;
+        ++launches;
+        return ALAE_OK;
+    };
+    auto set_caps = [&](int nxt) {
+        caps.nodes = ws->node_cap[nxt];
+        caps.entries = ws->ent_cap[nxt];
+        caps.lwnodes = ws->lwide_cap[nxt];
+        caps.hits = ws->hit_cap;
+        caps.cnodes = ws->cnode_cap;
+        caps.centries = ws->cent_cap;
+        caps.gnodes = ws->gnode_cap;
+        caps.gentries = ws->gent_cap;
+        caps.wnodes = ws->wnode_cap;
+        caps.wentries = ws->went_cap;
+        caps.wrow = wrow;
+        caps.onodes = ws->onode_cap;
+        caps.oentries = ws->oent_cap;
+    };
+    // Grow what overflowed; queues that outlive one launch keep their first `keep` records.
+    auto grow_overflowed = [&](const Counters &c, const Counters &keep, int nxt) -> alae_status {
+        alae_status g = ALAE_OK;
+        // record offsets are 32-bit: a count beyond that is a runaway, not a capacity problem
+        const unsigned long long lim = 0xFFFFFFFFull;
+        const struct {
+            const char *name;
+            unsigned long long v;
+        } checks[] = {{"nodes", c.nodes},         {"entries", c.entries},   {"level-wide nodes", c.lwnodes},
+                      {"chains", c.cnodes},       {"chain entries", c.centries}, {"general", c.gnodes},
+                      {"general entries", c.gentries}, {"wide", c.wnodes}, {"wide entries", c.wentries},
+                      {"spill", c.onodes},        {"spill entries", c.oentries}, {"hits", c.hits}};
+        for (const auto &ck : checks) {
+            if (ck.v > lim) {
+                set_error("internal counter '%s' ran away to %llu (overflow bits %llx, depth %d)", ck.name, ck.v,
+                          c.overflow, depth);
+                return ALAE_E_INTERNAL;
+            }
+        }
+        if ((c.overflow & kOvNodes) && (g = grow(ws->nodes[nxt], ws->node_cap[nxt], c.nodes, false, 0, s))) return g;
+        if ((c.overflow & kOvEntries) && (g = grow(ws->ents[nxt], ws->ent_cap[nxt], c.entries, false, 0, s)))
+            return g;
+        if ((c.overflow & kOvLevelWide) &&
+            (g = grow(ws->lwide[nxt], ws->lwide_cap[nxt], c.lwnodes, false, 0, s)))
+            return g;
+        if ((c.overflow & kOvChainNodes) && (g = grow(ws->cnodes, ws->cnode_cap, c.cnodes, false, 0, s))) return g;
+        if ((c.overflow & kOvChainEntries) && (g = grow(ws->cents, ws->cent_cap, c.centries, false, 0, s)))
+            return g;
+        if ((c.overflow & kOvGeneralNodes) &&
+            (g = grow(ws->gnodes, ws->gnode_cap, c.gnodes, true, keep.gnodes, s)))
+            return g;
+        if ((c.overflow & kOvGeneralEntries) &&
+            (g = grow(ws->gents, ws->gent_cap, c.gentries, true, keep.gentries, s)))
+            return g;
+        if ((c.overflow & kOvWideNodes) && (g = grow(ws->wnodes, ws->wnode_cap, c.wnodes, true, keep.wnodes, s)))
+            return g;
+        if ((c.overflow & kOvWideEntries) &&
+            (g = grow(ws->wents, ws->went_cap, c.wentries, true, keep.wentries, s)))
+            return g;
+        if ((c.overflow & kOvSpillNodes) && (g = grow(ws->onodes, ws->onode_cap, c.onodes, false, 0, s))) return g;
+        if ((c.overflow & kOvSpillEntries) && (g = grow(ws->oents, ws->oent_cap, c.oentries, false, 0, s)))
+            return g;
+        if ((c.overflow & kOvHits) && (g = grow_pair(ws->hkeys, ws->hscores, ws->hit_cap, c.hits, keep.hits, s)))
+            return g;
+        if (c.overflow & kOvWideRow) {
+            set_error("a row exceeded the query length (internal error)");
+            return ALAE_E_INTERNAL;
+        }
+        return ALAE_OK;
+    };
+    static const bool trace = getenv("ALAE_TRACE") != nullptr;
+    uint64_t nlw = nlw0;  // nodes of the current level with long rows (in ws->lwide[cur])
+    while ((nn > 0 || nlw > 0) && depth < lmax) {
         const int32_t d1 = depth + 1;
         const int nxt = cur ^ 1;
-        // reset the per-level allocation counters; keep hits and statistics
-        Counters before = *ws->h_cnt;
+        const double t0 = expand_ms;
+        // level expansion (lane kernel + wave kernel); per-level buffers restart,
+        // hits and queues carry over
+        const Counters before = *ws->h_cnt;
         for (;;) {
             Counters z = before;
-            z.nodes = 0;
-            z.entries = 0;
+            z.nodes = z.entries = z.lwnodes = z.cnodes = z.centries = 0;
             z.overflow = 0;
             HIP_TRY(hipMemcpyAsync(ws->d_cnt, &z, sizeof(Counters), hipMemcpyHostToDevice, s));
-            caps.nodes = ws->node_cap[nxt];
-            caps.entries = ws->ent_cap[nxt];
-            caps.hits = ws->hit_cap;
+            set_caps(nxt);
+            LevelOut o;
+            o.onodes = ws->nodes[nxt];
+            o.owide = ws->lwide[nxt];
+            o.oent = ws->ents[nxt];
+            o.chains = ws->cnodes;
+            o.cent = ws->cents;
+            o.hkeys = ws->hkeys;
+            o.hscores = ws->hscores;
+            o.node_base = o.wide_base = o.ent_base = o.chain_base = o.cent_base = o.hit_base = 0;
             HIP_TRY(hipEventRecord(ws->evk0, s));
-            k_expand_level<<<(uint32_t)((nn + tb - 1) / tb), tb, 0, s>>>(a, ws->nodes[cur], (uint32_t)nn,
-                                                                        ws->ents[cur], d1, ws->nodes[nxt],
-                                                                        ws->ents[nxt], ws->hkeys, ws->hscores, caps,
-                                                                        ws->d_cnt);
-            HIP_TRY(hipGetLastError());
-            HIP_TRY(hipEventRecord(ws->evk1, s));
-            HIP_TRY(hipMemcpyAsync(ws->h_cnt, ws->d_cnt, sizeof(Counters), hipMemcpyDeviceToHost, s));
-            HIP_TRY(hipStreamSynchronize(s));
-            {
-                float kms = 0.f;
-                HIP_TRY(hipEventElapsedTime(&kms, ws->evk0, ws->evk1));
-                expand_ms += kms;
-                ++launches;
+            if (nn > 0)
+                k_expand_level<<<(uint32_t)((nn + tb - 1) / tb), tb, 0, s>>>(a, ws->nodes[cur], (uint32_t)nn,
+                                                                            ws->ents[cur], d1, o, caps, ws->d_cnt);
+            if (nlw > 0) {
+                const uint32_t blocks = (uint32_t)std::min<uint64_t>(nlw, 2048);
+                if ((st = grow(ws->stage, ws->stage_cap, (uint64_t)blocks * wrow, false, 0, s)) != ALAE_OK) return st;
+                k_expand_level_wide<<<blocks, 64, 0, s>>>(a, ws->lwide[cur], (uint32_t)nlw, ws->ents[cur], d1, o,
+                                                          caps, ws->d_cnt, ws->stage);
             }
+            if ((st = timed(expand_ms)) != ALAE_OK) return st;
             const Counters &c = *ws->h_cnt;
             if (!c.overflow) break;
             ++retries;
-            if (c.overflow & 1ull)
-                if ((st = grow(ws->nodes[nxt], ws->node_cap[nxt], c.nodes, false, 0, s)) != ALAE_OK) return st;
-            if (c.overflow & 2ull)
-                if ((st = grow(ws->ents[nxt], ws->ent_cap[nxt], c.entries, false, 0, s)) != ALAE_OK) return st;
-            if (c.overflow & 4ull)
-                if ((st = grow_pair(ws->hkeys, ws->hscores, ws->hit_cap, c.hits, before.hits, s)) != ALAE_OK)
-                    return st;
+            if ((st = grow_overflowed(c, before, nxt)) != ALAE_OK) return st;
         }
+        const uint64_t nc = ws->h_cnt->cnodes;
+        const double t1 = expand_ms;
+        // chains created by this level
+        if (nc > 0) {
+            const Counters before2 = *ws->h_cnt;
+            for (;;) {
+                Counters z = before2;
+                z.overflow = 0;
+                HIP_TRY(hipMemcpyAsync(ws->d_cnt, &z, sizeof(Counters), hipMemcpyHostToDevice, s));
+                set_caps(nxt);
+                ChainQueues q{ws->gnodes, ws->gents, ws->wnodes, ws->wents, ws->hkeys, ws->hscores};
+                HIP_TRY(hipEventRecord(ws->evk0, s));
+                k_chain_start<<<(uint32_t)((nc + tb - 1) / tb), tb, 0, s>>>(a, sub, ws->cnodes, (uint32_t)nc,
+                                                                           ws->cents, q, caps, ws->d_cnt);
+                if ((st = timed(chain_ms)) != ALAE_OK) return st;
+                const Counters &c = *ws->h_cnt;
+                if (!c.overflow) break;
+                ++retries;
+                if ((st = grow_overflowed(c, before2, nxt)) != ALAE_OK) return st;
+            }
+        }
+        if (trace)
+            fprintf(stderr,
+                    "[alae] depth %d: %llu+%llu nodes -> %llu+%llu nodes, %llu entries, %llu chains "
+                    "(general %llu, wide %llu); level %.3f ms, chains %.3f ms\n",
+                    d1, (unsigned long long)nn, (unsigned long long)nlw, (unsigned long long)ws->h_cnt->nodes,
+                    (unsigned long long)ws->h_cnt->lwnodes, (unsigned long long)ws->h_cnt->entries,
+                    (unsigned long long)nc, (unsigned long long)ws->h_cnt->gnodes,
+                    (unsigned long long)ws->h_cnt->wnodes, t1 - t0, chain_ms);
         nn = ws->h_cnt->nodes;
+        nlw = ws->h_cnt->lwnodes;
         cur = nxt;
         depth = d1;
         ++levels;
-        if (nn) max_depth = (uint64_t)d1;
+        if (nn || nlw || nc) max_depth = (uint64_t)d1;
+    }
+
+    // chains with gap states: one lane each
+    const uint64_t ng = ws->h_cnt->gnodes;
+    if (ng > 0) {
+        const Counters before = *ws->h_cnt;
+        for (;;) {
+            Counters z = before;
+            z.general_head = 0;
+            z.overflow = 0;
+            HIP_TRY(hipMemcpyAsync(ws->d_cnt, &z, sizeof(Counters), hipMemcpyHostToDevice, s));
+            set_caps(cur);
+            const uint32_t waves = (uint32_t)std::min<uint64_t>((ng + 63) / 64, max_waves);
+            HIP_TRY(hipEventRecord(ws->evk0, s));
+            k_chain_general<<<(waves + 3) / 4, 256, 0, s>>>(a, ws->gnodes, (uint32_t)ng, ws->gents, ws->wnodes,
+                                                            ws->wents, ws->hkeys, ws->hscores, caps, ws->d_cnt);
+            if ((st = timed(chain_ms)) != ALAE_OK) return st;
+            const Counters &c = *ws->h_cnt;
+            if (!c.overflow) break;
+            ++retries;
+            if ((st = grow_overflowed(c, before, cur)) != ALAE_OK) return st;
+        }
+    }
+    // chains whose rows are too wide for a lane: one wave each, rows in LDS
+    const uint64_t nw = ws->h_cnt->wnodes;
+    if (nw > 0) {
+        const Counters before = *ws->h_cnt;
+        const uint32_t blocks = (uint32_t)std::min<uint64_t>(nw, (uint64_t)cus * 24u);
+        for (;;) {
+            Counters z = before;
+            z.wide_head = 0;
+            z.onodes = z.oentries = 0;
+            z.overflow = 0;
+            HIP_TRY(hipMemcpyAsync(ws->d_cnt, &z, sizeof(Counters), hipMemcpyHostToDevice, s));
+            set_caps(cur);
+            HIP_TRY(hipEventRecord(ws->evk0, s));
+            k_chain_wide_lds<<<blocks, 64, 0, s>>>(a, ws->wnodes, (uint32_t)nw, ws->wents, ws->onodes, ws->oents,
+                                                   ws->hkeys, ws->hscores, caps, ws->d_cnt);
+            if ((st = timed(wide_ms)) != ALAE_OK) return st;
+            const Counters &c = *ws->h_cnt;
+            if (!c.overflow) break;
+            ++retries;
+            if ((st = grow_overflowed(c, before, cur)) != ALAE_OK) return st;
+        }
+    }
+    // rows that outgrew LDS: one wave each, rows in global memory
+    const uint64_t no = ws->h_cnt->onodes;
+    if (no > 0) {
+        const uint64_t budget_entries = (8ull << 30) / sizeof(Entry);
+        uint64_t waves = std::min<uint64_t>(no, (uint64_t)max_waves);
+        waves = std::max<uint64_t>(1, std::min<uint64_t>(waves, budget_entries / (2 * wrow)));
+        if (ws->wrow_cap != wrow || ws->rowbuf_cap < waves * 2 * wrow) {
+            hipFree(ws->rowbuf);
+            ws->rowbuf = nullptr;
+            ws->rowbuf_cap = 0;
+            if (hipMalloc(&ws->rowbuf, waves * 2 * wrow * sizeof(Entry)) != hipSuccess) {
+                hipGetLastError();
+                set_error("device allocation of wide-chain row buffers failed");
+                return ALAE_E_NOMEM;
+            }
+            ws->rowbuf_cap = waves * 2 * wrow;
+            ws->wrow_cap = wrow;
+        }
+        const Counters before = *ws->h_cnt;
+        for (;;) {
+            Counters z = before;
+            z.overflow_head = 0;
+            z.overflow = 0;
+            HIP_TRY(hipMemcpyAsync(ws->d_cnt, &z, sizeof(Counters), hipMemcpyHostToDevice, s));
+            set_caps(cur);
+            HIP_TRY(hipEventRecord(ws->evk0, s));
+            k_chain_wide_global<<<(uint32_t)waves, 64, 0, s>>>(a, ws->onodes, (uint32_t)no, ws->oents, ws->rowbuf,
+                                                               ws->hkeys, ws->hscores, caps, ws->d_cnt);
+            if ((st = timed(wide_ms)) != ALAE_OK) return st;
+            const Counters &c = *ws->h_cnt;
+            if (!c.overflow) break;
+            ++retries;
+            if ((st = grow_overflowed(c, before, cur)) != ALAE_OK) return st;
+        }
     }
 
     // ---- max-merge and sort --------------------------------------------------
-    const uint64_t emitted = ws->h_cnt->hits;
+    const uint64_t emitted = ws->h_cnt->hits;           // hit slots written, padding included
+    const uint64_t padding = ws->h_cnt->hit_padding;    // unused reserved slots (sorted last)
     uint64_t unique = 0;
     float merge_ms = 0.f;
     HIP_TRY(hipEventRecord(ws->evk0, s));
@@ -1071,10 +912,11 @@ static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64
         if ((st = grow(ws->flags, ws->flags_cap, emitted + 1, false, 0, s)) != ALAE_OK) return st;
         if ((st = grow(ws->pos, ws->pos_cap, emitted + 1, false, 0, s)) != ALAE_OK) return st;
         if ((st = grow_pair(ws->res_keys, ws->res_scores, ws->res_cap, emitted, 0, s)) != ALAE_OK) return st;
-        HIP_TRY(max_merge_sorted(k, v, emitted, ws->res_keys, ws->res_scores, ws->flags, ws->pos, ws->scratch, s));
+        const uint64_t valid = emitted - padding;
+        HIP_TRY(max_merge_sorted(k, v, valid, ws->res_keys, ws->res_scores, ws->flags, ws->pos, ws->scratch, s));
         uint32_t cnt32 = 0;
         HIP_TRY(hipEventRecord(ws->evk1, s));
-        HIP_TRY(hipMemcpyAsync(&cnt32, ws->pos + emitted, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(&cnt32, ws->pos + valid, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
         HIP_TRY(hipEventElapsedTime(&merge_ms, ws->evk0, ws->evk1));
         unique = cnt32;
@@ -1090,7 +932,7 @@ static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64
         o->entries_gap2 = c.st_gap2;
         o->entries_gap3 = c.st_gap3;
         o->dominated = c.st_dominated;
-        o->emitted = emitted;
+        o->emitted = emitted - padding;
         o->hits = unique;
         o->levels = levels;
         o->retries = retries;
@@ -1101,6 +943,13 @@ static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64
         o->frontier_bytes = c.st_frontier_bytes;
         o->expand_launches = launches;
         o->expand_ms = expand_ms;
+        o->chain_ms = chain_ms;
+        o->wide_ms = wide_ms;
+        o->chain_steps = c.st_chain_steps + c.st_ngr_steps;
+        o->wide_steps = c.st_wide_steps;
+        o->promoted = c.st_promoted;
+        o->dominated_gapped = c.st_dominated_gapped;
+        o->chain_bytes = c.st_chain_bytes;
         o->merge_ms = merge_ms;
     }
     return ALAE_OK;

@@ -204,3 +204,36 @@ def test_device_resident_path():
     exp2 = oracle.sw_hits(T, P[20:120], oracle.scoring_table(4, 1, -3), -5, -2, 10, threads=8)
     assert cnt2 == exp2[0].shape[0]
     ws.free()
+
+
+@pytest.mark.parametrize("scheme", [(1, -3, -5, -2), (1, -1, -5, -2), (2, -3, -4, -1)])
+def test_long_homolog_wide_rows(scheme):
+    """A long mutated copy makes gap wedges hundreds of columns wide: rows are
+    walked by whole waves over several 64-entry rounds."""
+    rng = np.random.default_rng(71)
+    m = 4000
+    P = rng.integers(0, 4, size=m).astype(np.uint8)
+    T = rng.integers(0, 4, size=30000).astype(np.uint8)
+    synth.plant_segments(rng, T, [P[200:3200], P[3300:3900]], 4, 0.10, 0.02)
+    H = 30 if scheme[0] == 1 else 60
+    got, exp, st = run_pair(T, P, scheme, H)
+    print(f"scheme={scheme} hits={exp[0].shape[0]} stats={st.as_dict()}", flush=True)
+    assert st.promoted > 0 and st.wide_steps > 0
+    assert_same(got, exp)
+
+
+def test_domination_switch_same_hits_on_homologs():
+    """The gapped domination test removes interior starts inside homologs without changing hits."""
+    rng = np.random.default_rng(72)
+    m = 2000
+    P = rng.integers(0, 4, size=m).astype(np.uint8)
+    T = rng.integers(0, 4, size=40000).astype(np.uint8)
+    synth.plant_segments(rng, T, [P[100:1100], P[1200:1900], P[300:800]], 4, 0.15, 0.02)
+    idx = alae.Index.build(T, "dna")
+    on, exp, st_on = run_pair(T, P, (1, -3, -5, -2), 30, index=idx)
+    st_off = alae.Stats()
+    off = alae.search(idx, P, 30, alae.make_scoring(), stats=st_off, use_domination=False)
+    assert_same(on, exp)
+    assert_same(off, exp)
+    assert st_on.dominated + st_on.dominated_gapped > 0
+    assert st_on.entries < st_off.entries
