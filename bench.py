@@ -48,26 +48,38 @@ def workload(name: str):
 
 
 def cpu_baseline(w, budget_s: float):
-    """The oracle as it stands, on a bounded slice of the same text (all host threads)."""
+    """The oracle as it stands, on a bounded slice of the same text.
+
+    The chunked oracle recomputes L_max text rows in front of every thread's
+    chunk (that overlap makes it exact), so the thread count is chosen to keep
+    that overlap at most half of each thread's rows; with too small a budget
+    the oracle runs on one thread without chunking."""
     import oracle
 
     T, P = w["text"], w["queries"][0]
     m = P.shape[0]
-    threads = min(os.cpu_count() or 1, 64)
+    cores = os.cpu_count() or 1
     sub = oracle.scoring_table(w["sigma"], w["sa"], w["sb"])
-    # calibrate on a short slice, then size the sample to the budget
-    L = max(2000, int(2e8 // m))
+    lmax = oracle.lmax(m, int(sub.max()), w["sg"], w["ss"], w["H"])
+    # single-thread rate on a short slice
+    L = max(1000, int(1e8 // m))
     t0 = time.perf_counter()
-    oracle.sw_hits(T[:L], P, sub, w["sg"], w["ss"], w["H"], threads=threads)
-    dt = time.perf_counter() - t0
-    rate = m * L / max(dt, 1e-6)
-    L2 = int(min(T.shape[0], max(L, rate * budget_s / m)))
+    oracle.sw_hits(T[:L], P, sub, w["sg"], w["ss"], w["H"], threads=1)
+    r1 = m * L / max(time.perf_counter() - t0, 1e-6)
+    rows_per_thread = r1 * budget_s / m
+    threads = min(cores, 64) if rows_per_thread >= 2 * lmax else 1
+    if threads > 1:
+        L2 = int(threads * (rows_per_thread - lmax))
+    else:
+        L2 = int(rows_per_thread)
+    L2 = max(L, min(T.shape[0], L2))
     t0 = time.perf_counter()
     oracle.sw_hits(T[:L2], P, sub, w["sg"], w["ss"], w["H"], threads=threads)
-    dt2 = time.perf_counter() - t0
-    return {"value": m * L2 / dt2, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
-            "sample": f"full query (m={m}) against the first {L2} text characters; {dt2:.1f} s wall; "
-                      f"chunked by text with an L_max overlap per thread"}
+    dt = time.perf_counter() - t0
+    return {"value": m * L2 / dt, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"full query (m={m}) against the first {L2} text characters in {dt:.1f} s "
+                      f"({threads} thread(s); L_max={lmax} rows recomputed in front of each chunk); "
+                      f"host has {cores} cores"}
 
 
 def main():
@@ -77,7 +89,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=30.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the search has no multi-GPU path in this build "
@@ -117,11 +129,10 @@ def main():
     ms = float(np.mean(times) * 1e3)
     st = stats[-1]
     entries_per_s = float(np.mean([s.entries / t for s, t in zip(stats, times)]))
-    exp_ms = float(np.mean([s.expand_ms for s in stats]))
-    alg_bytes = st.expand_alg_bytes()
-    launches = max(1, st.expand_launches)
-    per_launch_ms = exp_ms / launches
-    achieved = alg_bytes / (exp_ms * 1e-3) / 1e9 if exp_ms > 0 else 0.0
+    level_ms = float(np.mean([s.level_ms for s in stats]))
+    launches = max(1, st.level_launches)
+    alg_bytes = st.level_alg_bytes()
+    achieved = alg_bytes / (level_ms * 1e-3) / 1e9 if level_ms > 0 else 0.0
     out = {
         "metric": METRIC,
         "value": m * n / (ms * 1e-3),
@@ -140,11 +151,15 @@ def main():
         "p50_ms": float(np.percentile(times, 50) * 1e3),
         "p99_ms": float(np.percentile(times, 99) * 1e3),
         "hits": int(cnt),
+        "kernels_ms": {"level": level_ms, "chain_start": float(np.mean([s.start_ms for s in stats])),
+                       "chain_general": float(np.mean([s.general_ms for s in stats])),
+                       "chain_wide": float(np.mean([s.wide_ms for s in stats])),
+                       "sort_merge": float(np.mean([s.merge_ms for s in stats]))},
         "search_stats": {k: (float(v) if isinstance(v, float) else int(v)) for k, v in st.as_dict().items()},
         "roofline": {"kernel": "k_expand_level", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "alg_bytes_per_launch": alg_bytes / launches, "avg_launch_ms": per_launch_ms,
-                     "launches_per_step": int(st.expand_launches)},
+                     "alg_bytes_per_launch": alg_bytes / launches, "avg_launch_ms": level_ms / launches,
+                     "launches_per_step": int(st.level_launches)},
     }
     if not args.no_cpu:
         log("timing the CPU oracle on a bounded sample")

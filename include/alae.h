@@ -99,21 +99,22 @@ typedef struct {
     uint64_t retries;        /* capacity or int16-saturation re-runs                    */
     uint64_t max_depth;      /* deepest trie node with a live entry                    */
     double device_ms;        /* device time of the search (events around the work)      */
-    /* traffic and time of the frontier-expansion kernel (roofline accounting) */
-    uint64_t occ_reads;      /* occurrence-block reads (64-byte granules)              */
-    uint64_t sa_reads;       /* suffix-array reads at nodes that become unique          */
-    uint64_t text_reads;     /* text reads of nodes walked along the text               */
-    uint64_t frontier_bytes; /* frontier nodes/entries read + written, hit records      */
-    uint64_t expand_launches;/* kernel launches of the trie walk                        */
-    double expand_ms;        /* device time of the level expansion (several occurrences) */
-    double chain_ms;         /* device time of the one-lane chain walk                   */
-    double wide_ms;          /* device time of the one-wave chain walk                   */
-    uint64_t chain_steps;    /* single-occurrence nodes computed by one lane             */
-    uint64_t wide_steps;     /* single-occurrence nodes computed by one wave             */
-    uint64_t promoted;       /* chains handed from a lane to a wave                      */
-    uint64_t dominated_gapped; /* states removed by the gapped domination test           */
-    uint64_t chain_bytes;    /* row bytes read and written by the chain kernels          */
-    double merge_ms;         /* device time of the sort + max-merge of hit records      */
+    /* traffic and time per kernel family (roofline accounting) */
+    uint64_t occ_reads;      /* occurrence-block reads of the level kernels (64-byte granules) */
+    uint64_t sa_reads;       /* suffix-array reads locating new chains                     */
+    uint64_t text_reads;     /* text granules read by the chain walkers                     */
+    uint64_t frontier_bytes; /* level-kernel bytes: frontier nodes/rows in and out, hits    */
+    uint64_t level_launches; /* launches of the level kernels                               */
+    double level_ms;         /* device time of the level kernels                            */
+    double start_ms;         /* device time of the chain-start kernel (locate, domination, no-gap walk) */
+    double general_ms;       /* device time of the one-lane chain walker                     */
+    double wide_ms;          /* device time of the one-wave chain walkers                    */
+    uint64_t chain_steps;    /* chain nodes computed by one lane                             */
+    uint64_t wide_steps;     /* chain nodes computed by one wave                             */
+    uint64_t promoted;       /* chains handed to the wave walkers                            */
+    uint64_t dominated_gapped; /* states removed by the gapped domination test               */
+    uint64_t chain_bytes;    /* row bytes read and written by the chain walkers              */
+    double merge_ms;         /* device time of the sort + max-merge of hit records          */
 } alae_stats;
 
 /* Search options; pass NULL for the defaults. */

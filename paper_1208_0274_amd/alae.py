@@ -59,15 +59,16 @@ class Stats(ctypes.Structure):
                 ("levels", ctypes.c_uint64), ("retries", ctypes.c_uint64), ("max_depth", ctypes.c_uint64),
                 ("device_ms", ctypes.c_double), ("occ_reads", ctypes.c_uint64), ("sa_reads", ctypes.c_uint64),
                 ("text_reads", ctypes.c_uint64), ("frontier_bytes", ctypes.c_uint64),
-                ("expand_launches", ctypes.c_uint64), ("expand_ms", ctypes.c_double), ("chain_ms", ctypes.c_double),
-                ("wide_ms", ctypes.c_double), ("chain_steps", ctypes.c_uint64), ("wide_steps", ctypes.c_uint64),
-                ("promoted", ctypes.c_uint64), ("dominated_gapped", ctypes.c_uint64),
-                ("chain_bytes", ctypes.c_uint64), ("merge_ms", ctypes.c_double)]
+                ("level_launches", ctypes.c_uint64), ("level_ms", ctypes.c_double), ("start_ms", ctypes.c_double),
+                ("general_ms", ctypes.c_double), ("wide_ms", ctypes.c_double), ("chain_steps", ctypes.c_uint64),
+                ("wide_steps", ctypes.c_uint64), ("promoted", ctypes.c_uint64),
+                ("dominated_gapped", ctypes.c_uint64), ("chain_bytes", ctypes.c_uint64),
+                ("merge_ms", ctypes.c_double)]
 
-    def expand_alg_bytes(self) -> int:
-        """Algorithmic bytes of the expansion kernel: one 64-byte granule per random
-        occ/SA/text read plus the frontier records it must read and write."""
-        return 64 * (self.occ_reads + self.sa_reads + self.text_reads) + self.frontier_bytes
+    def level_alg_bytes(self) -> int:
+        """Algorithmic bytes of the level kernels: one 64-byte granule per
+        occurrence-block read plus the frontier records they read and write."""
+        return 64 * self.occ_reads + self.frontier_bytes
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

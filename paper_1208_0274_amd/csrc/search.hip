@@ -643,8 +643,8 @@ static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64
     }
 
     uint64_t levels = 0, retries = 0, max_depth = nn ? (uint64_t)seed_depth : 0;
-    uint64_t launches = 0;
-    double expand_ms = 0.0, chain_ms = 0.0, wide_ms = 0.0;
+    uint64_t launches = 0, level_launches = 0;  // launches counts every timed kernel
+    double expand_ms = 0.0, start_ms = 0.0, general_ms = 0.0, wide_ms = 0.0;
     int32_t depth = seed_depth;
     int cus = 256;
     hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ws->device);
@@ -772,6 +772,7 @@ static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64
                                                           caps, ws->d_cnt, ws->stage);
             }
             if ((st = timed(expand_ms)) != ALAE_OK) return st;
+            ++level_launches;
             const Counters &c = *ws->h_cnt;
             if (!c.overflow) break;
             ++retries;
@@ -791,7 +792,7 @@ static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64
                 HIP_TRY(hipEventRecord(ws->evk0, s));
                 k_chain_start<<<(uint32_t)((nc + tb - 1) / tb), tb, 0, s>>>(a, sub, ws->cnodes, (uint32_t)nc,
                                                                            ws->cents, q, caps, ws->d_cnt);
-                if ((st = timed(chain_ms)) != ALAE_OK) return st;
+                if ((st = timed(start_ms)) != ALAE_OK) return st;
                 const Counters &c = *ws->h_cnt;
                 if (!c.overflow) break;
                 ++retries;
@@ -805,7 +806,7 @@ static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64
                     d1, (unsigned long long)nn, (unsigned long long)nlw, (unsigned long long)ws->h_cnt->nodes,
                     (unsigned long long)ws->h_cnt->lwnodes, (unsigned long long)ws->h_cnt->entries,
                     (unsigned long long)nc, (unsigned long long)ws->h_cnt->gnodes,
-                    (unsigned long long)ws->h_cnt->wnodes, t1 - t0, chain_ms);
+                    (unsigned long long)ws->h_cnt->wnodes, t1 - t0, start_ms);
         nn = ws->h_cnt->nodes;
         nlw = ws->h_cnt->lwnodes;
         cur = nxt;
@@ -828,7 +829,7 @@ static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64
             HIP_TRY(hipEventRecord(ws->evk0, s));
             k_chain_general<<<(waves + 3) / 4, 256, 0, s>>>(a, ws->gnodes, (uint32_t)ng, ws->gents, ws->wnodes,
                                                             ws->wents, ws->hkeys, ws->hscores, caps, ws->d_cnt);
-            if ((st = timed(chain_ms)) != ALAE_OK) return st;
+            if ((st = timed(general_ms)) != ALAE_OK) return st;
             const Counters &c = *ws->h_cnt;
             if (!c.overflow) break;
             ++retries;
@@ -941,9 +942,10 @@ static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64
         o->sa_reads = c.st_sa_reads;
         o->text_reads = c.st_text_reads;
         o->frontier_bytes = c.st_frontier_bytes;
-        o->expand_launches = launches;
-        o->expand_ms = expand_ms;
-        o->chain_ms = chain_ms;
+        o->level_launches = level_launches;
+        o->level_ms = expand_ms;
+        o->start_ms = start_ms;
+        o->general_ms = general_ms;
         o->wide_ms = wide_ms;
         o->chain_steps = c.st_chain_steps + c.st_ngr_steps;
         o->wide_steps = c.st_wide_steps;

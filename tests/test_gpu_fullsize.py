@@ -1,0 +1,98 @@
+"""Parity at the full workload sizes, in the launch configuration bench.py times
+(device-resident query and result, one workspace).
+
+Config 2 (text 1e8, query 1e5): the hits whose text end falls in a window are
+exactly the oracle's hits on T[window start - L_max .. window end] (Theorem 1
+bounds the text span of any alignment scoring >= H), so planted-copy windows
+and random background windows are checked exactly, many in parallel.
+Config 3 (protein stand-in, text 5e7, query 5e3) is checked in full.
+"""
+import concurrent.futures as cf
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1208_0274_amd import alae, synth
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+
+def device_search(w):
+    import torch
+
+    T, P = w["text"], w["queries"][0]
+    idx = alae.Index.build(T, w["alphabet"])
+    ws = alae.Workspace(idx)
+    dq = torch.from_numpy(P).to("cuda")
+    st = alae.Stats()
+    cnt = ws.search_device(dq, w["H"], alae.make_scoring(w["sa"], w["sb"], w["sg"], w["ss"]), stats=st)
+    keys, scores = ws.result_torch()
+    torch.cuda.synchronize()
+    keys = keys.cpu().numpy().view(np.uint64)
+    scores = scores.cpu().numpy().astype(np.int64)
+    ws.free()
+    assert keys.shape[0] == cnt
+    return (keys >> np.uint64(32)).astype(np.int64), (keys & np.uint64(0xFFFFFFFF)).astype(np.int64), scores, st
+
+
+def check_global_properties(j, t, s, w):
+    """Properties that hold at any size: sorted unique (j, t), scores >= H, ends in range."""
+    assert np.all(s >= w["H"])
+    assert np.all((j >= 0) & (j < w["queries"][0].shape[0]))
+    assert np.all((t >= 0) & (t < w["text"].shape[0]))
+    key = j * (1 << 32) + t
+    assert np.all(np.diff(key) > 0)
+
+
+def test_config2_windows():
+    w = synth.config2()
+    T, P, H = w["text"], w["queries"][0], w["H"]
+    j, t, s, st = device_search(w)
+    print(f"C2: {j.shape[0]} hits, {st.entries} entries, {st.device_ms:.1f} ms", flush=True)
+    check_global_properties(j, t, s, w)
+    sub = oracle.scoring_table(4, 1, -3)
+    lmax = oracle.lmax(P.shape[0], 1, w["sg"], w["ss"], H)
+    rng = np.random.default_rng(2024)
+    plants = w["plants"]
+    pick = list(rng.choice(len(plants), size=10, replace=False))
+    pick.append(int(np.argmin([p[1] for p in plants])))
+    pick.append(int(np.argmax([p[1] for p in plants])))
+    windows = [(plants[k][0], plants[k][0] + plants[k][1] + 50) for k in pick]
+    for _ in range(4):  # background windows
+        a = int(rng.integers(lmax, T.shape[0] - 3000))
+        windows.append((a, a + 2000))
+
+    def one(win):
+        a, b = win
+        lo = max(0, a - lmax)
+        ej, et, es = oracle.sw_hits(T[lo:b], P, sub, w["sg"], w["ss"], H, t_lo=a - lo, t_hi=b - lo, threads=1)
+        return a, b, ej, et + lo, es
+
+    with cf.ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        results = list(ex.map(one, windows))
+    checked = 0
+    for a, b, ej, et, es in results:
+        sel = (t >= a) & (t < b)
+        gj, gt, gs = j[sel], t[sel], s[sel]
+        order = np.lexsort((gt, gj))
+        np.testing.assert_array_equal(gj[order], ej)
+        np.testing.assert_array_equal(gt[order], et)
+        np.testing.assert_array_equal(gs[order], es)
+        checked += ej.shape[0]
+    print(f"C2 windows: {len(windows)} windows, {checked} hits checked exactly", flush=True)
+    assert checked > 0
+
+
+def test_config3_full():
+    w = synth.config3()
+    T, P, H = w["text"], w["queries"][0], w["H"]
+    j, t, s, st = device_search(w)
+    print(f"C3: {j.shape[0]} hits, {st.entries} entries, {st.device_ms:.1f} ms", flush=True)
+    check_global_properties(j, t, s, w)
+    ej, et, es = oracle.sw_hits(T, P, oracle.scoring_table(20, 1, -3), w["sg"], w["ss"], H,
+                                threads=min(64, os.cpu_count() or 1))
+    np.testing.assert_array_equal(j, ej)
+    np.testing.assert_array_equal(t, et)
+    np.testing.assert_array_equal(s, es)
