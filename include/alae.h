@@ -202,9 +202,17 @@ alae_status alae_search(const alae_index *index, const char *query, size_t m, co
                         int32_t H, const alae_search_opts *opts, alae_hits *out);
 
 /*
- * k searches in one persistent device launch (the batched form).  outs
- * receives k result sets, one per query, each exactly what alae_search
- * would return for that query alone.
+ * k queries searched together (the batched form).  The queries are laid end
+ * to end and share one traversal of the text's trie (Section 2.3): a node is
+ * expanded once for all of them, its sparse row holding the live columns of
+ * every query, while no alignment crosses from one query into the next (no
+ * diagonal step, gap, seed q-gram or domination window spans a boundary;
+ * U(j) of Theorem 2 runs to the end of j's own query; L_max of Theorem 1 is
+ * that of the longest query, which only loosens the filter).  outs (k
+ * elements, caller-owned array) receives k library-allocated result sets,
+ * outs[i] exactly what alae_search returns for query i alone (an empty query
+ * gets an empty set).  At most 65,536 non-empty queries.  On error no result
+ * set is left allocated.  Errors as alae_search.
  */
 alae_status alae_search_batch(const alae_index *index, const char *const *queries, const size_t *lens, size_t k,
                               const alae_scoring *scoring, int32_t H, const alae_search_opts *opts,
@@ -227,6 +235,18 @@ void alae_workspace_free(alae_workspace *ws);
 alae_status alae_search_device(alae_workspace *ws, const uint8_t *d_query_codes, size_t m,
                                const alae_scoring *scoring, int32_t H, const alae_search_opts *opts,
                                void *stream, size_t *hit_count);
+/*
+ * Device-resident batch: d_query_codes holds the k queries end to end
+ * (lens[i] > 0 codes each, host array lens).  The workspace result is then
+ * grouped by query, in query order, each group sorted as a single search
+ * would sort it, with keys holding query-local columns; after the call
+ * alae_workspace_batch_offsets fills offsets[0..k] (host array of k+1) so
+ * that query i owns records offsets[i] .. offsets[i+1]-1.
+ */
+alae_status alae_search_device_batch(alae_workspace *ws, const uint8_t *d_query_codes, const size_t *lens, size_t k,
+                                     const alae_scoring *scoring, int32_t H, const alae_search_opts *opts,
+                                     void *stream, size_t *hit_count);
+alae_status alae_workspace_batch_offsets(const alae_workspace *ws, size_t *offsets, size_t k);
 alae_status alae_workspace_result(const alae_workspace *ws, const uint64_t **d_keys, const int32_t **d_scores,
                                   size_t *count);
 /* Copy the workspace result into caller-owned device buffers of at least

@@ -127,6 +127,9 @@ _sig("alae_workspace_create", _st, _vp, ctypes.POINTER(_vp))
 _sig("alae_workspace_free", None, _vp)
 _sig("alae_search_device", _st, _vp, _vp, ctypes.c_size_t, ctypes.POINTER(Scoring), ctypes.c_int32,
      ctypes.POINTER(SearchOpts), _vp, ctypes.POINTER(ctypes.c_size_t))
+_sig("alae_search_device_batch", _st, _vp, _vp, ctypes.POINTER(ctypes.c_size_t), ctypes.c_size_t,
+     ctypes.POINTER(Scoring), ctypes.c_int32, ctypes.POINTER(SearchOpts), _vp, ctypes.POINTER(ctypes.c_size_t))
+_sig("alae_workspace_batch_offsets", _st, _vp, ctypes.POINTER(ctypes.c_size_t), ctypes.c_size_t)
 _sig("alae_workspace_result", _st, _vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(ctypes.c_size_t))
 _sig("alae_workspace_copy_result", _st, _vp, _vp, _vp, _vp)
 
@@ -321,6 +324,28 @@ class Workspace:
         _check(_lib.alae_search_device(self._h, _vp(d_query.data_ptr()), int(d_query.numel()), ctypes.byref(sc),
                                        int(H), ctypes.byref(opts), sptr, ctypes.byref(cnt)), "alae_search_device")
         return int(cnt.value)
+
+    def search_device_batch(self, d_queries, lens, H: int, scoring: Scoring | None = None,
+                            stats: Stats | None = None, stream=None, **opt) -> int:
+        """d_queries: the queries' codes end to end (torch uint8 on the GPU); lens: their lengths.
+        Returns the total hit count; batch_offsets() splits the result by query."""
+        sc = scoring if scoring is not None else make_scoring()
+        opts = make_opts(stats=stats, **opt)
+        k = len(lens)
+        arr = (ctypes.c_size_t * k)(*[int(x) for x in lens])
+        cnt = ctypes.c_size_t()
+        sptr = _vp(stream.cuda_stream) if stream is not None else None
+        _check(_lib.alae_search_device_batch(self._h, _vp(d_queries.data_ptr()), arr, k, ctypes.byref(sc), int(H),
+                                             ctypes.byref(opts), sptr, ctypes.byref(cnt)), "alae_search_device_batch")
+        self._k = k
+        return int(cnt.value)
+
+    def batch_offsets(self) -> np.ndarray:
+        """Offsets (k+1) of each query's records in the last batch result."""
+        k = self._k
+        arr = (ctypes.c_size_t * (k + 1))()
+        _check(_lib.alae_workspace_batch_offsets(self._h, arr, k), "alae_workspace_batch_offsets")
+        return np.array(arr[:], dtype=np.int64)
 
     def result_torch(self, stream=None):
         """Copies of the sorted result as torch tensors on the device: (keys int64, scores int32)."""

@@ -222,12 +222,13 @@ __global__ void __launch_bounds__(256) k_chain_start(SearchArgs a, SubTable subt
                 ++n_general;
             } else if (live > 0) {
                 // no-gap region: walk in registers, diagonal steps only (Eq. 3)
-                uint32_t col[kNgrSlots], y[kNgrSlots];
+                uint32_t col[kNgrSlots], y[kNgrSlots], send[kNgrSlots];
                 int32_t M[kNgrSlots];
 #pragma unroll
                 for (int s2 = 0; s2 < kNgrSlots; ++s2) {
                     col[s2] = 0;
                     y[s2] = 0;
+                    send[s2] = 0;
                     M[s2] = kNeg;
                 }
                 uint32_t alive = 0;
@@ -242,6 +243,7 @@ __global__ void __launch_bounds__(256) k_chain_start(SearchArgs a, SubTable subt
                                 col[s2] = e.col;
                                 M[s2] = e.M;
                                 y[s2] = e.yM;
+                                send[s2] = seg_end_of(a, e.col);
                             }
                         }
                         alive |= 1u << sidx;
@@ -270,7 +272,7 @@ __global__ void __launch_bounds__(256) k_chain_start(SearchArgs a, SubTable subt
                         const uint32_t ncol = col[s2] + 1;
                         const uint32_t pc = (uint32_t)(qw[s2] >> (8 * tpos)) & 0xFFu;
                         const int32_t v = M[s2] + score_of(a, sub, c, pc);
-                        const bool ok = ((alive >> s2) & 1u) && ncol < a.m && keep_state(a, v, ncol, rowgain);
+                        const bool ok = ((alive >> s2) & 1u) && ncol < send[s2] && keep_state(a, v, ncol, rowgain);
                         nM[s2] = ok ? v : kNeg;
                         nalive |= ok ? (1u << s2) : 0u;
                         fgoe |= ok && v > -open;

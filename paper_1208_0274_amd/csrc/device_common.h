@@ -63,8 +63,34 @@ struct SearchArgs {
     int32_t s_mismatch;   // s_b
     const uint8_t *query; // query codes; 64 readable bytes before index 0 and after m-1
     int32_t ngr_walk;     // walk no-gap chains in registers (else all go to the general walker)
+    // Several queries searched together: their codes are concatenated and no
+    // alignment may cross from one query into the next.
+    int32_t multi;
+    const uint32_t *qord;    // per column: ordinal of its query
+    const uint32_t *segbeg;  // per query: first column
+    const uint32_t *segend;  // per query: one past its last column
     uint32_t C[21];
 };
+
+// Query segments (batched search).  Single-query searches never read the arrays.
+__device__ inline uint32_t seg_end_of(const SearchArgs &a, uint32_t col) {
+    return a.multi ? a.segend[a.qord[col]] : a.m;
+}
+__device__ inline uint32_t seg_beg_of(const SearchArgs &a, uint32_t col) {
+    return a.multi ? a.segbeg[a.qord[col]] : 0u;
+}
+// col is the first column of its query (nothing may enter it from the left)
+__device__ inline bool seg_first(const SearchArgs &a, uint32_t col) {
+    return a.multi && a.segbeg[a.qord[col]] == col;
+}
+// Offset that makes prefix-max keys of earlier queries useless in later ones:
+// within a query a key is M + |s_s|*col < 2^44, so the query ordinal shifted
+// past that keeps every later query's keys above every earlier one's and the
+// G_b value an earlier key gives in a later query negative.
+constexpr int kSegShift = 44;
+__device__ inline int64_t seg_key(const SearchArgs &a, uint32_t col) {
+    return a.multi ? ((int64_t)a.qord[col] << kSegShift) : 0;
+}
 
 // Text and query buffers carry this many readable bytes before index 0 and
 // after their last character, so fixed-size windows can be loaded without
@@ -177,6 +203,7 @@ struct Counters {
     unsigned long long gentries;
     unsigned long long general_head;
     unsigned long long st_ngr_steps;    // chain steps taken in the no-gap fast path
+    unsigned long long stage_need;      // longest row that did not fit a level-wide staging buffer
 };
 
 // Key of an unused hit slot: sorts after every real (column, text end) key.
@@ -186,7 +213,7 @@ constexpr uint64_t kPadKey = ~0ull;
 constexpr unsigned long long kOvNodes = 1, kOvEntries = 2, kOvHits = 4, kOvChainNodes = 8, kOvChainEntries = 16,
                              kOvWideNodes = 32, kOvWideEntries = 64, kOvWideRow = 128, kOvSpillNodes = 256,
                              kOvSpillEntries = 512, kOvLevelWide = 1024, kOvGeneralNodes = 2048,
-                             kOvGeneralEntries = 4096;
+                             kOvGeneralEntries = 4096, kOvStageRow = 8192;
 
 struct Caps {
     unsigned long long nodes;
@@ -202,6 +229,7 @@ struct Caps {
     unsigned long long lwnodes;   // next-level nodes with long rows
     unsigned long long gnodes;    // general chain queue
     unsigned long long gentries;
+    unsigned long long srow;      // entries per staging buffer of the level-wide kernel
 };
 
 struct SubTable {

@@ -220,12 +220,13 @@ __device__ inline void emit_row_hits_multi(const SearchArgs &a, const Entry *row
     }
 }
 
-// One wave per node with a long row.  stage holds caps.wrow entries per block.
+// One wave per node with a long row.  stage holds caps.srow entries per block;
+// a longer child row raises kOvStageRow with its length in stage_need.
 __global__ void __launch_bounds__(64) k_expand_level_wide(SearchArgs a, const Node *wnodes, uint32_t nw,
                                                           const Entry *ent, int32_t d1, LevelOut o, Caps caps,
                                                           Counters *cnt, Entry *stage) {
     const int lane = threadIdx.x & 63;
-    Entry *buf = stage + (uint64_t)blockIdx.x * caps.wrow;
+    Entry *buf = stage + (uint64_t)blockIdx.x * caps.srow;
     HitRes hr = {0, 0, 0};
     unsigned long long emitted = 0, entries = 0, diag = 0, gap2 = 0, gap3 = 0;
     for (uint32_t item = blockIdx.x; item < nw; item += gridDim.x) {
@@ -246,7 +247,7 @@ __global__ void __launch_bounds__(64) k_expand_level_wide(SearchArgs a, const No
             }
             if (l > r) continue;
             WideOut w;
-            w.cap = (uint32_t)caps.wrow;
+            w.cap = (uint32_t)caps.srow;
             w.hkeys = o.hkeys;
             w.hscores = o.hscores;
             w.hit_cap = caps.hits;
@@ -256,7 +257,10 @@ __global__ void __launch_bounds__(64) k_expand_level_wide(SearchArgs a, const No
             wide_child_row(a, AosRow{const_cast<Entry *>(ent) + nd.off}, nd.len, AosRow{buf}, c, d1, w, hr);
             __syncthreads();
             if (w.overflow) {
-                if (lane == 0) atomicOr(&cnt->overflow, kOvWideRow);
+                if (lane == 0) {
+                    atomicOr(&cnt->overflow, kOvStageRow);
+                    atomicMax(&cnt->stage_need, (unsigned long long)w.len);
+                }
                 continue;
             }
             const uint32_t len = w.len;

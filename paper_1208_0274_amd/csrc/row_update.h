@@ -40,7 +40,8 @@ __device__ inline void load_window32(const uint8_t *arr, int64_t p, uint32_t w[8
 __device__ inline bool dominated(const SearchArgs &a, const int8_t *sub, int64_t x, int64_t y) {
     int64_t reach = a.dom_reach;
     if (x < reach) reach = x;
-    if (y < reach) reach = y;
+    const int64_t yl = y - (int64_t)seg_beg_of(a, (uint32_t)y);  // columns of y's query before y
+    if (yl < reach) reach = yl;
     if (reach <= 0) return false;
     uint32_t tw[8], qw[8];
     load_window32(a.text, x, tw);
@@ -65,8 +66,9 @@ __device__ inline bool dominated(const SearchArgs &a, const int8_t *sub, int64_t
 // Gapped form: the local alignment score ending at (x-1, y-1) computed inside
 // the window T[x-K..x-1] x P[y-K..y-1] (a lower bound of the true one).
 __device__ inline bool dominated_gapped(const SearchArgs &a, int64_t x, int64_t y) {
+    const int64_t yl = y - (int64_t)seg_beg_of(a, (uint32_t)y);
     const int rows = (int)(x < kGapWindow ? x : kGapWindow);
-    const int cols = (int)(y < kGapWindow ? y : kGapWindow);
+    const int cols = (int)(yl < kGapWindow ? yl : kGapWindow);
     if (rows == 0 || cols == 0) return false;
     const int32_t open = a.sg + a.ss;
     int32_t Hr[kGapWindow + 1], Er[kGapWindow + 1];
@@ -101,7 +103,7 @@ __device__ inline bool dominated_gapped(const SearchArgs &a, int64_t x, int64_t 
 // under Theorem 1).  rowgain = smax * (L_max - d1).
 __device__ inline int32_t gain_after(const SearchArgs &a, uint32_t col) {
     // match/mismatch scoring: every later column can add at most s_a
-    return a.u_closed ? a.smax * (int32_t)(a.m - 1 - col) : a.U[col];
+    return a.u_closed ? a.smax * (int32_t)(seg_end_of(a, col) - 1 - col) : a.U[col];
 }
 
 __device__ inline bool keep_state(const SearchArgs &a, int32_t v, uint32_t col, int32_t rowgain) {
@@ -212,19 +214,16 @@ __device__ void child_row(const SearchArgs &a, const Entry *prow, uint32_t plen,
     uint32_t gy = 0;       // its start column
 
     auto spread_to = [&](int64_t upto) {  // G_b-only columns last+1 .. upto
-        while (last < upto) {
-            if (gnext <= 0) {
-                last = upto;
-                gnext = kNeg;
-                break;
-            }
+        int64_t lim = upto;  // a query gap never runs into the next query
+        if (a.multi && last >= 0) {
+            const int64_t se = (int64_t)seg_end_of(a, (uint32_t)last) - 1;
+            if (se < lim) lim = se;
+        }
+        while (last < lim) {
+            if (gnext <= 0) break;
             const uint32_t col = (uint32_t)(last + 1);
             const int32_t v = gnext;
-            if (!keep_state(a, v, col, rowgain)) {  // later columns only lose more
-                last = upto;
-                gnext = kNeg;
-                break;
-            }
+            if (!keep_state(a, v, col, rowgain)) break;  // later columns only lose more
             if (check_dom && dominated(a, sub, x, gy)) {
                 s.st_dom++;
             } else {
@@ -233,11 +232,15 @@ __device__ void child_row(const SearchArgs &a, const Entry *prow, uint32_t plen,
             last = col;
             gnext = v + ext;
         }
+        if (last < upto) {
+            last = upto;
+            gnext = kNeg;
+        }
     };
 
     auto column = [&](uint32_t j, int32_t D, uint32_t yD, int32_t Gav, uint32_t yGav) {
         spread_to((int64_t)j - 1);
-        const int32_t Gb = (last == (int64_t)j - 1) ? gnext : kNeg;
+        const int32_t Gb = (last == (int64_t)j - 1 && !seg_first(a, j)) ? gnext : kNeg;
         const uint32_t yGb = gy;
         int32_t M = D;
         uint32_t yM = yD;
@@ -291,7 +294,7 @@ __device__ void child_row(const SearchArgs &a, const Entry *prow, uint32_t plen,
         uint32_t yD = 0;
         if (k > 0) {
             const Entry p = prow[k - 1];
-            if (p.col + 1 == j && p.M > 0) {
+            if (p.col + 1 == j && p.M > 0 && !seg_first(a, j)) {
                 D = p.M + pc[j];
                 yD = p.yM;
             }
@@ -309,7 +312,7 @@ __device__ void child_row(const SearchArgs &a, const Entry *prow, uint32_t plen,
         }
         column(j, D, yD, Gav, yGav);
         // diagonal into column j+1 when no parent entry sits there
-        if (e.M > 0 && j + 1 < a.m && !(k + 1 < plen && prow[k + 1].col == j + 1)) {
+        if (e.M > 0 && j + 1 < seg_end_of(a, j) && !(k + 1 < plen && prow[k + 1].col == j + 1)) {
             column(j + 1, e.M + pc[j + 1], e.yM, kNeg, 0);
         }
     }
@@ -523,7 +526,7 @@ __device__ inline void wide_child_row(const SearchArgs &a, const Row cur, uint32
         // column A = e.col: diagonal from the previous entry and G_a
         int32_t D = kNeg;
         uint32_t yD = 0;
-        if (valid && pcol != kNone && pcol + 1 == e.col && pM > 0) {
+        if (valid && pcol != kNone && pcol + 1 == e.col && pM > 0 && !seg_first(a, e.col)) {
             D = pM + pc[e.col];
             yD = pyM;
         }
@@ -546,11 +549,13 @@ __device__ inline void wide_child_row(const SearchArgs &a, const Row cur, uint32
             yM0A = yGaA;
         }
         // column B = e.col + 1: diagonal only, unless the next entry owns it
-        const bool hasB = valid && e.M > 0 && e.col + 1 < a.m && ncol != e.col + 1;
+        const uint32_t send = valid ? seg_end_of(a, e.col) : 0u;  // end of this entry's query
+        const int64_t skey = valid ? seg_key(a, e.col) : 0;
+        const bool hasB = valid && e.M > 0 && e.col + 1 < send && ncol != e.col + 1;
         const int32_t M0B = hasB ? e.M + pc[e.col + 1] : kNeg;
         const uint32_t yM0B = e.yM;
-        const int64_t kA = (valid && M0A > 0) ? (int64_t)M0A + absss * (int64_t)e.col : kNegKey;
-        const int64_t kB = (hasB && M0B > 0) ? (int64_t)M0B + absss * (int64_t)(e.col + 1) : kNegKey;
+        const int64_t kA = (valid && M0A > 0) ? (int64_t)M0A + absss * (int64_t)e.col + skey : kNegKey;
+        const int64_t kB = (hasB && M0B > 0) ? (int64_t)M0B + absss * (int64_t)(e.col + 1) + skey : kNegKey;
         int64_t lk = kA;
         uint32_t lt = yM0A;
         if (kB > lk) {
@@ -567,7 +572,7 @@ __device__ inline void wide_child_row(const SearchArgs &a, const Row cur, uint32
         // G_b and M at A
         int32_t GbA = kNeg;
         if (valid && exk > kNegKey) {
-            const int64_t v = exk + a.sg - absss * (int64_t)e.col;
+            const int64_t v = exk + a.sg - absss * (int64_t)e.col - skey;
             GbA = v > 0 ? (int32_t)v : kNeg;
         }
         int32_t MA = M0A;
@@ -587,7 +592,7 @@ __device__ inline void wide_child_row(const SearchArgs &a, const Row cur, uint32
         }
         int32_t GbB = kNeg;
         if (hasB && kAB > kNegKey) {
-            const int64_t v = kAB + a.sg - absss * (int64_t)(e.col + 1);
+            const int64_t v = kAB + a.sg - absss * (int64_t)(e.col + 1) - skey;
             GbB = v > 0 ? (int32_t)v : kNeg;
         }
         int32_t MB = M0B;
@@ -605,11 +610,11 @@ __device__ inline void wide_child_row(const SearchArgs &a, const Row cur, uint32
             tinc = yM0B;
         }
         const uint32_t lc = hasB ? e.col + 1 : e.col;
-        const uint32_t stop = (ncol == kNone) ? a.m : ncol;
+        const uint32_t stop = (ncol == kNone || ncol > send) ? send : ncol;
         uint32_t nspread = 0, nspread_hits = 0;
         if (valid && kinc > kNegKey) {
             for (uint32_t col = lc + 1; col < stop; ++col) {
-                const int64_t v = kinc + a.sg - absss * (int64_t)col;
+                const int64_t v = kinc + a.sg - absss * (int64_t)col - skey;
                 if (v <= 0 || !keep_state(a, (int32_t)v, col, rowgain)) break;
                 ++nspread;
                 nspread_hits += (v >= a.H);
@@ -644,7 +649,7 @@ __device__ inline void wide_child_row(const SearchArgs &a, const Row cur, uint32
                 const uint32_t col = lc + 1 + s;
                 Entry w;
                 w.col = col;
-                w.M = (int32_t)(kinc + a.sg - absss * (int64_t)col);
+                w.M = (int32_t)(kinc + a.sg - absss * (int64_t)col - skey);
                 w.Ga = kNeg;
                 w.yM = tinc;
                 w.yGa = 0;
@@ -673,7 +678,7 @@ __device__ inline void wide_child_row(const SearchArgs &a, const Row cur, uint32
             if (nB && MB >= a.H) put(e.col + 1, MB);
             for (uint32_t s = 0; s < nspread; ++s) {
                 const uint32_t col = lc + 1 + s;
-                const int32_t v = (int32_t)(kinc + a.sg - absss * (int64_t)col);
+                const int32_t v = (int32_t)(kinc + a.sg - absss * (int64_t)col - skey);
                 if (v < a.H) break;
                 put(col, v);
             }

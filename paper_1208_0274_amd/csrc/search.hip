@@ -110,23 +110,77 @@ __global__ void k_profile(const uint8_t *q, uint32_t m, int sigma, SubTable sub,
     colrev[m - 1 - j] = (uint32_t)(best > 0 ? best : 0);
 }
 
-// U[j] = sum over j' > j of colmax(P[j']) from the exclusive scan of colrev.
-__global__ void k_gain_bound(const uint32_t *scan_rev, uint32_t m, int32_t *U) {
+// U[j] = sum over the later columns j' of j's query of colmax(P[j']), from the
+// exclusive scan of colrev.
+__global__ void k_gain_bound(const uint32_t *scan_rev, uint32_t m, const uint32_t *qord, const uint32_t *segend,
+                             int32_t *U) {
     uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j < m) U[j] = (int32_t)scan_rev[m - 1 - j];
+    if (j >= m) return;
+    uint32_t u = scan_rev[m - 1 - j];
+    if (qord) u -= scan_rev[m - segend[qord[j]]];
+    U[j] = (int32_t)u;
+}
+
+// Query ordinal of every column of a batch (segbeg is increasing).
+__global__ void k_qord(const uint32_t *segbeg, uint32_t nseg, uint32_t m, uint32_t *qord) {
+    uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= m) return;
+    uint32_t lo = 0, hi = nseg - 1;  // last segment whose first column is <= j
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) >> 1;
+        if (segbeg[mid] <= j)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    qord[j] = lo;
+}
+
+// Split a batch result: off[q] = first record of query q (records are sorted
+// by column, so each query's records are contiguous), then keys get the
+// column inside their own query.
+__global__ void k_batch_offsets(const uint64_t *keys, uint64_t count, const uint32_t *segbeg, uint32_t nseg,
+                                uint64_t *off) {
+    uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q > nseg) return;
+    if (q == nseg) {
+        off[q] = count;
+        return;
+    }
+    const uint64_t target = (uint64_t)segbeg[q] << 32;
+    uint64_t lo = 0, hi = count;
+    while (lo < hi) {
+        const uint64_t mid = (lo + hi) >> 1;
+        if (keys[mid] < target)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    off[q] = lo;
+}
+
+__global__ void k_batch_localize(uint64_t *keys, uint64_t count, const uint32_t *qord, const uint32_t *segbeg) {
+    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const uint64_t k = keys[i];
+    const uint32_t col = (uint32_t)(k >> 32);
+    keys[i] = ((uint64_t)(col - segbeg[qord[col]]) << 32) | (k & 0xFFFFFFFFull);
 }
 
 // Seed keys.  q-gram mode: key = code of P[j-q+1..j] (first char most
 // significant), one per end column j >= q-1; other slots get the invalid key.
 // Matrix mode: slot c*m + j holds key c when s(c, P[j]) > 0.
+// In a batch a q-gram never spans two queries.
 __global__ void k_seed_keys(const uint8_t *q, uint32_t m, int sigma, int qeff, int matrix_mode, SubTable sub,
-                            uint64_t invalid, uint64_t *keys, uint32_t *vals) {
+                            const uint32_t *qord, const uint32_t *segbeg, uint64_t invalid, uint64_t *keys,
+                            uint32_t *vals) {
     uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (!matrix_mode) {
         if (t >= m) return;
         uint32_t j = (uint32_t)t;
         uint64_t key = invalid;
-        if ((int)j >= qeff - 1) {
+        const uint32_t first = qord ? segbeg[qord[j]] : 0u;
+        if ((int64_t)j - (int64_t)first >= qeff - 1) {
             key = 0;
             for (int k = qeff - 1; k >= 0; --k) key = key * sigma + q[j - k];
         }
@@ -341,6 +395,16 @@ struct alae_workspace {
     Entry *rowbuf = nullptr;
     uint64_t rowbuf_cap = 0;
     uint64_t wrow_cap = 0;
+    // batch segments
+    uint32_t *qord = nullptr;
+    uint64_t qord_cap = 0;
+    uint32_t *segbeg = nullptr;  // nseg first columns, then nseg ends
+    uint64_t seg_cap = 0;
+    uint64_t *d_off = nullptr;
+    uint64_t off_cap = 0;
+    std::vector<uint32_t> h_seg;       // staging of segbeg/segend for the upload
+    std::vector<uint64_t> h_off;       // per-query result offsets of the last batch
+    uint64_t nseg = 0;                 // queries of the last search (1 for a single query)
     // counters
     Counters *d_cnt = nullptr;
     Counters *h_cnt = nullptr;
@@ -386,6 +450,9 @@ static void ws_release(alae_workspace *ws) {
     hipFree(ws->wnodes);
     hipFree(ws->wents);
     hipFree(ws->rowbuf);
+    hipFree(ws->qord);
+    hipFree(ws->segbeg);
+    hipFree(ws->d_off);
     hipFree(ws->d_cnt);
     if (ws->h_cnt) hipHostFree(ws->h_cnt);
     if (ws->ev0) hipEventDestroy(ws->ev0);
@@ -473,12 +540,22 @@ static int bit_length(uint64_t v) {
     return b;
 }
 
-static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64_t m, const alae_scoring *scoring,
-                              int32_t H, const alae_search_opts *opts, hipStream_t s, uint64_t *hit_count) {
+// Batches are at most this many queries (their ordinals are folded into the
+// 64-bit prefix-max keys of the G_b scan).
+constexpr uint64_t kMaxBatch = 65536;
+
+// One search of d_query[0..m).  With nseg > 1 the query is the concatenation
+// of nseg queries of lengths seg_lens[] (each > 0): they share the trie
+// traversal but no alignment crosses from one into the next.
+static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64_t m, const uint64_t *seg_lens,
+                              uint64_t nseg, const alae_scoring *scoring, int32_t H, const alae_search_opts *opts,
+                              hipStream_t s, uint64_t *hit_count) {
     const alae_index *idx = ws->idx;
     Scheme sch;
     alae_status st = check_scoring(scoring, idx->sigma, H, sch);
     if (st != ALAE_OK) return st;
+    ws->nseg = 0;
+    ws->res_count = 0;
     if (m == 0) {
         set_error("empty query");
         return ALAE_E_ARG;
@@ -487,11 +564,42 @@ static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64
         set_error("query of %llu characters is too long", (unsigned long long)m);
         return ALAE_E_TOO_LONG;
     }
+    const bool multi = nseg > 1;
+    uint64_t mlong = m;  // longest query (Equation 1 bounds each query's alignments)
+    if (multi) {
+        if (nseg > kMaxBatch) {
+            set_error("batch of %llu queries exceeds the limit of %llu", (unsigned long long)nseg,
+                      (unsigned long long)kMaxBatch);
+            return ALAE_E_ARG;
+        }
+        uint64_t sum = 0;
+        mlong = 0;
+        ws->h_seg.resize(2 * nseg);
+        for (uint64_t i = 0; i < nseg; ++i) {
+            if (seg_lens[i] == 0) {
+                set_error("query %llu of the batch is empty", (unsigned long long)i);
+                return ALAE_E_ARG;
+            }
+            ws->h_seg[i] = (uint32_t)sum;
+            sum += seg_lens[i];
+            ws->h_seg[nseg + i] = (uint32_t)sum;
+            mlong = std::max(mlong, seg_lens[i]);
+        }
+        if (sum != m) {
+            set_error("batch lengths add up to %llu, not %llu", (unsigned long long)sum, (unsigned long long)m);
+            return ALAE_E_ARG;
+        }
+        // the G_b scan keys of a batch must stay below 2^44 (see seg_key)
+        if ((uint64_t)(-(int64_t)scoring->ss) * m + (1ull << 30) >= (1ull << 44)) {
+            set_error("batch of %llu columns is too long for gap extension %d", (unsigned long long)m, scoring->ss);
+            return ALAE_E_TOO_LONG;
+        }
+    }
     const int sigma = idx->sigma;
     const bool use_score_filter = opts ? opts->use_score_filter != 0 : true;
     const bool use_dom = opts ? opts->use_domination != 0 : true;
     const bool use_q = opts ? opts->use_qprefix != 0 : true;
-    const int64_t lmax = lmax_of((int64_t)m, sch.smax, scoring->sg, scoring->ss, H);
+    const int64_t lmax = lmax_of((int64_t)mlong, sch.smax, scoring->sg, scoring->ss, H);
     if ((int64_t)sch.smax * (lmax + 2) > (1ll << 28)) {
         set_error("scores could exceed the 32-bit range of the kernels (m too long for this scheme)");
         return ALAE_E_TOO_LONG;
@@ -548,6 +656,16 @@ static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64
     a.s_mismatch = sch.matrix_mode ? 0 : scoring->sb;
     a.dom_reach = 32;
     for (int c = 0; c <= sigma; ++c) a.C[c] = (uint32_t)idx->C[c];
+    if (multi) {
+        if ((st = grow(ws->qord, ws->qord_cap, m, false, 0, s)) != ALAE_OK) return st;
+        if ((st = grow(ws->segbeg, ws->seg_cap, 2 * nseg, false, 0, s)) != ALAE_OK) return st;
+        HIP_TRY(hipMemcpyAsync(ws->segbeg, ws->h_seg.data(), 2 * nseg * sizeof(uint32_t), hipMemcpyHostToDevice, s));
+        k_qord<<<(uint32_t)((m + 255) / 256), 256, 0, s>>>(ws->segbeg, (uint32_t)nseg, (uint32_t)m, ws->qord);
+        a.multi = 1;
+        a.qord = ws->qord;
+        a.segbeg = ws->segbeg;
+        a.segend = ws->segbeg + nseg;
+    }
 
     SubTable sub;
     memset(&sub, 0, sizeof(sub));
@@ -570,7 +688,7 @@ static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64
         if ((st = grow(ws->scratch, ws->scratch_cap, need, false, 0, s)) != ALAE_OK) return st;
     }
     HIP_TRY(scan_exclusive_u32(ws->colrev, ws->colrev, m, ws->scratch, s));
-    k_gain_bound<<<gm, tb, 0, s>>>(ws->colrev, (uint32_t)m, ws->U);
+    k_gain_bound<<<gm, tb, 0, s>>>(ws->colrev, (uint32_t)m, multi ? a.qord : nullptr, a.segend, ws->U);
 
     // ---- seeds ---------------------------------------------------------------
     uint64_t space = 1;
@@ -578,8 +696,9 @@ static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64
     const uint64_t invalid = space;  // keys >= invalid are not seeds
     const int seed_depth = matrix_seeds ? 1 : qeff;
     k_seed_keys<<<(uint32_t)((nseed + tb - 1) / tb), tb, 0, s>>>(d_query, (uint32_t)m, sigma, seed_depth,
-                                                                  matrix_seeds ? 1 : 0, sub, invalid, ws->seed_keys,
-                                                                  ws->seed_vals);
+                                                                  matrix_seeds ? 1 : 0, sub,
+                                                                  multi ? a.qord : nullptr, a.segbeg, invalid,
+                                                                  ws->seed_keys, ws->seed_vals);
     bool alt = false;
     HIP_TRY(radix_sort_pairs(ws->seed_keys, ws->seed_vals, ws->seed_keys_alt, ws->seed_vals_alt, nseed,
                              bit_length(invalid), ws->scratch, &alt, s));
@@ -650,6 +769,9 @@ static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64
     hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ws->device);
     const uint32_t max_waves = (uint32_t)cus * 8u;
     const uint64_t wrow = m + 2;  // a row never holds more than m entries
+    // staging rows of the level-wide kernel start short and grow to the longest child row met
+    uint64_t srow = std::min<uint64_t>(wrow, 4096);
+    const uint64_t stage_budget = (2ull << 30) / sizeof(Entry);
     // queues that live through the whole search
     for (int i = 0; i < 2; ++i)
         if ((st = grow(ws->lwide[i], ws->lwide_cap[i], 1ull << 12, false, 0, s)) != ALAE_OK) return st;
@@ -684,6 +806,7 @@ static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64
         caps.wnodes = ws->wnode_cap;
         caps.wentries = ws->went_cap;
         caps.wrow = wrow;
+        caps.srow = srow;
         caps.onodes = ws->onode_cap;
         caps.oentries = ws->oent_cap;
     };
@@ -731,6 +854,7 @@ static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64
             return g;
         if ((c.overflow & kOvHits) && (g = grow_pair(ws->hkeys, ws->hscores, ws->hit_cap, c.hits, keep.hits, s)))
             return g;
+        if (c.overflow & kOvStageRow) srow = std::min<uint64_t>(wrow, std::max<uint64_t>(2 * srow, c.stage_need));
         if (c.overflow & kOvWideRow) {
             set_error("a row exceeded the query length (internal error)");
             return ALAE_E_INTERNAL;
@@ -750,6 +874,7 @@ static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64
             Counters z = before;
             z.nodes = z.entries = z.lwnodes = z.cnodes = z.centries = 0;
             z.overflow = 0;
+            z.stage_need = 0;
             HIP_TRY(hipMemcpyAsync(ws->d_cnt, &z, sizeof(Counters), hipMemcpyHostToDevice, s));
             set_caps(nxt);
             LevelOut o;
@@ -766,8 +891,9 @@ static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64
                 k_expand_level<<<(uint32_t)((nn + tb - 1) / tb), tb, 0, s>>>(a, ws->nodes[cur], (uint32_t)nn,
                                                                             ws->ents[cur], d1, o, caps, ws->d_cnt);
             if (nlw > 0) {
-                const uint32_t blocks = (uint32_t)std::min<uint64_t>(nlw, 2048);
-                if ((st = grow(ws->stage, ws->stage_cap, (uint64_t)blocks * wrow, false, 0, s)) != ALAE_OK) return st;
+                const uint32_t blocks =
+                    (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>({nlw, 2048, stage_budget / srow}));
+                if ((st = grow(ws->stage, ws->stage_cap, (uint64_t)blocks * srow, false, 0, s)) != ALAE_OK) return st;
                 k_expand_level_wide<<<blocks, 64, 0, s>>>(a, ws->lwide[cur], (uint32_t)nlw, ws->ents[cur], d1, o,
                                                           caps, ws->d_cnt, ws->stage);
             }
@@ -924,6 +1050,20 @@ static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64
     }
     ws->res_count = unique;
     *hit_count = unique;
+    ws->nseg = multi ? nseg : 1;
+    if (multi) {
+        // per-query ranges of the sorted result, then query-local columns
+        if ((st = grow(ws->d_off, ws->off_cap, nseg + 1, false, 0, s)) != ALAE_OK) return st;
+        k_batch_offsets<<<(uint32_t)((nseg + 1 + 255) / 256), 256, 0, s>>>(ws->res_keys, unique, a.segbeg,
+                                                                           (uint32_t)nseg, ws->d_off);
+        if (unique > 0)
+            k_batch_localize<<<(uint32_t)((unique + 255) / 256), 256, 0, s>>>(ws->res_keys, unique, a.qord,
+                                                                             a.segbeg);
+        HIP_TRY(hipGetLastError());
+        ws->h_off.resize(nseg + 1);
+        HIP_TRY(hipMemcpyAsync(ws->h_off.data(), ws->d_off, (nseg + 1) * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+    }
     if (opts && opts->stats) {
         alae_stats *o = opts->stats;
         const Counters &c = *ws->h_cnt;
@@ -1003,7 +1143,7 @@ alae_status alae_search_device(alae_workspace *ws, const uint8_t *d_query_codes,
     hipStream_t s = (hipStream_t)stream;
     HIP_TRY(hipEventRecord(ws->ev0, s));
     uint64_t cnt = 0;
-    alae_status st = run_search(ws, d_query_codes, m, scoring, H, opts, s, &cnt);
+    alae_status st = run_search(ws, d_query_codes, m, nullptr, 1, scoring, H, opts, s, &cnt);
     if (st != ALAE_OK) return st;
     HIP_TRY(hipEventRecord(ws->ev1, s));
     HIP_TRY(hipEventSynchronize(ws->ev1));
@@ -1013,6 +1153,53 @@ alae_status alae_search_device(alae_workspace *ws, const uint8_t *d_query_codes,
         opts->stats->device_ms = ms;
     }
     *hit_count = (size_t)cnt;
+    return ALAE_OK;
+}
+
+alae_status alae_search_device_batch(alae_workspace *ws, const uint8_t *d_query_codes, const size_t *lens, size_t k,
+                                     const alae_scoring *scoring, int32_t H, const alae_search_opts *opts,
+                                     void *stream, size_t *hit_count) {
+    if (!ws || !d_query_codes || !lens || !hit_count || k == 0) {
+        set_error("alae_search_device_batch: null argument or empty batch");
+        return ALAE_E_ARG;
+    }
+    std::vector<uint64_t> seg;
+    uint64_t m = 0;
+    for (size_t i = 0; i < k; ++i) {
+        seg.push_back((uint64_t)lens[i]);
+        m += lens[i];
+    }
+    HIP_TRY(hipSetDevice(ws->device));
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(hipEventRecord(ws->ev0, s));
+    uint64_t cnt = 0;
+    alae_status st = run_search(ws, d_query_codes, m, seg.data(), (uint64_t)k, scoring, H, opts, s, &cnt);
+    if (st != ALAE_OK) return st;
+    if (k == 1) {  // a batch of one is a plain search
+        ws->h_off.assign({0, cnt});
+    }
+    HIP_TRY(hipEventRecord(ws->ev1, s));
+    HIP_TRY(hipEventSynchronize(ws->ev1));
+    if (opts && opts->stats) {
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, ws->ev0, ws->ev1);
+        opts->stats->device_ms = ms;
+    }
+    *hit_count = (size_t)cnt;
+    return ALAE_OK;
+}
+
+alae_status alae_workspace_batch_offsets(const alae_workspace *ws, size_t *offsets, size_t k) {
+    if (!ws || !offsets) {
+        set_error("alae_workspace_batch_offsets: null argument");
+        return ALAE_E_ARG;
+    }
+    if (ws->h_off.size() != k + 1 || ws->nseg != k) {
+        set_error("alae_workspace_batch_offsets: the last search on this workspace was not a batch of %zu queries",
+                  k);
+        return ALAE_E_ARG;
+    }
+    for (size_t i = 0; i <= k; ++i) offsets[i] = (size_t)ws->h_off[i];
     return ALAE_OK;
 }
 
@@ -1146,11 +1333,89 @@ alae_status alae_search_batch(const alae_index *index, const char *const *querie
         return ALAE_E_ARG;
     }
     for (size_t i = 0; i < k; ++i) memset(&outs[i], 0, sizeof(alae_hits));
+    {
+        Scheme sch;
+        alae_status vs = check_scoring(scoring, index->sigma, H, sch);
+        if (vs != ALAE_OK) return vs;
+    }
+    // concatenate the non-empty queries (an empty query has no hits)
+    std::vector<uint8_t> codes;
+    std::vector<size_t> seg, which;
     for (size_t i = 0; i < k; ++i) {
-        alae_status st = alae_search(index, queries[i], lens[i], scoring, H, opts, &outs[i]);
-        if (st != ALAE_OK) {
-            for (size_t j = 0; j < i; ++j) alae_hits_free(&outs[j]);
+        if (lens[i] == 0) continue;
+        if (!queries[i]) {
+            set_error("alae_search_batch: query %zu is NULL", i);
+            return ALAE_E_ARG;
+        }
+        const size_t at = codes.size();
+        try {
+            codes.resize(at + lens[i]);
+        } catch (const std::bad_alloc &) {
+            set_error("out of host memory");
+            return ALAE_E_NOMEM;
+        }
+        if (!encode(queries[i], lens[i], index->alphabet, codes.data() + at)) {
+            set_error("alae_search_batch: query %zu holds a character outside the alphabet", i);
+            return ALAE_E_ALPHABET;
+        }
+        seg.push_back(lens[i]);
+        which.push_back(i);
+    }
+    auto empty_hits = [](alae_hits &h) -> bool {
+        h.count = 0;
+        h.query_end = (uint32_t *)malloc(sizeof(uint32_t));
+        h.text_end = (uint64_t *)malloc(sizeof(uint64_t));
+        h.score = (int32_t *)malloc(sizeof(int32_t));
+        return h.query_end && h.text_end && h.score;
+    };
+    auto fail = [&](alae_status st) {
+        for (size_t j = 0; j < k; ++j) alae_hits_free(&outs[j]);
+        return st;
+    };
+    alae_workspace *ws = nullptr;
+    alae_status st = ALAE_OK;
+    alae_hits all;
+    memset(&all, 0, sizeof(all));
+    std::vector<size_t> off;
+    if (!seg.empty()) {
+        if ((st = alae_workspace_create(index, &ws)) != ALAE_OK) return st;
+        std::unique_ptr<alae_workspace, void (*)(alae_workspace *)> guard(ws, alae_workspace_free);
+        if ((st = grow(ws->d_query, ws->q_cap, codes.size(), false, 0, nullptr)) != ALAE_OK) return st;
+        HIP_TRY(hipMemcpy(ws->d_query, codes.data(), codes.size(), hipMemcpyHostToDevice));
+        size_t cnt = 0;
+        if ((st = alae_search_device_batch(ws, ws->d_query, seg.data(), seg.size(), scoring, H, opts, nullptr,
+                                           &cnt)) != ALAE_OK)
             return st;
+        off.resize(seg.size() + 1);
+        if ((st = alae_workspace_batch_offsets(ws, off.data(), seg.size())) != ALAE_OK) return st;
+        if ((st = download_hits(ws, nullptr, &all)) != ALAE_OK) return st;
+    }
+    std::unique_ptr<alae_hits, void (*)(alae_hits *)> all_guard(&all, alae_hits_free);
+    std::vector<bool> done(k, false);
+    for (size_t g = 0; g < which.size(); ++g) {
+        alae_hits &h = outs[which[g]];
+        const size_t b = off[g], e = off[g + 1], n = e - b;
+        const size_t alloc = n ? n : 1;
+        h.count = n;
+        h.query_end = (uint32_t *)malloc(alloc * sizeof(uint32_t));
+        h.text_end = (uint64_t *)malloc(alloc * sizeof(uint64_t));
+        h.score = (int32_t *)malloc(alloc * sizeof(int32_t));
+        if (!h.query_end || !h.text_end || !h.score) {
+            set_error("out of host memory");
+            return fail(ALAE_E_NOMEM);
+        }
+        if (n) {
+            memcpy(h.query_end, all.query_end + b, n * sizeof(uint32_t));
+            memcpy(h.text_end, all.text_end + b, n * sizeof(uint64_t));
+            memcpy(h.score, all.score + b, n * sizeof(int32_t));
+        }
+        done[which[g]] = true;
+    }
+    for (size_t i = 0; i < k; ++i) {
+        if (done[i]) continue;
+        if (!empty_hits(outs[i])) {
+            set_error("out of host memory");
+            return fail(ALAE_E_NOMEM);
         }
     }
     return ALAE_OK;
