@@ -115,6 +115,11 @@ typedef struct {
     uint64_t dominated_gapped; /* states removed by the gapped domination test               */
     uint64_t chain_bytes;    /* row bytes read and written by the chain walkers              */
     double merge_ms;         /* device time of the sort + max-merge of hit records          */
+    /* reuse of duplicate score calculations (Section 4): entries whose values were
+     * copied from an identical fork instead of computed; the reusing ratio of
+     * Equation 6 is reused / (reused + entries) */
+    uint64_t reused;
+    uint64_t replay_chains;  /* chains whose row was recognised as copies of one fork  */
 } alae_stats;
 
 /* Search options; pass NULL for the defaults. */
@@ -123,7 +128,7 @@ typedef struct {
     int32_t use_domination;    /* Section 3.2 domination test (default 1)                  */
     int32_t use_score_filter;  /* Theorem 2 (default 1)                                     */
     int32_t use_qprefix;       /* Theorem 3 q-prefix seeding (default 1)                    */
-    int32_t reserved0;
+    int32_t use_reuse;         /* Section 4 reuse of duplicate forks (default 0)             */
     int32_t reserved1;
     uint64_t entry_capacity;   /* frontier entries per level buffer, 0 = automatic          */
     uint64_t hit_capacity;     /* emitted hit records, 0 = automatic                        */

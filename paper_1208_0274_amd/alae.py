@@ -63,7 +63,12 @@ class Stats(ctypes.Structure):
                 ("general_ms", ctypes.c_double), ("wide_ms", ctypes.c_double), ("chain_steps", ctypes.c_uint64),
                 ("wide_steps", ctypes.c_uint64), ("promoted", ctypes.c_uint64),
                 ("dominated_gapped", ctypes.c_uint64), ("chain_bytes", ctypes.c_uint64),
-                ("merge_ms", ctypes.c_double)]
+                ("merge_ms", ctypes.c_double), ("reused", ctypes.c_uint64), ("replay_chains", ctypes.c_uint64)]
+
+    def reusing_ratio(self) -> float:
+        """Equation 6: reused entries over accessed (reused + computed) entries."""
+        acc = self.reused + self.entries
+        return self.reused / acc if acc else 0.0
 
     def level_alg_bytes(self) -> int:
         """Algorithmic bytes of the level kernels: one 64-byte granule per
@@ -77,7 +82,7 @@ class Stats(ctypes.Structure):
 class SearchOpts(ctypes.Structure):
     _fields_ = [("score_bits", ctypes.c_int32), ("use_domination", ctypes.c_int32),
                 ("use_score_filter", ctypes.c_int32), ("use_qprefix", ctypes.c_int32),
-                ("reserved0", ctypes.c_int32), ("reserved1", ctypes.c_int32),
+                ("use_reuse", ctypes.c_int32), ("reserved1", ctypes.c_int32),
                 ("entry_capacity", ctypes.c_uint64), ("hit_capacity", ctypes.c_uint64),
                 ("stats", ctypes.POINTER(Stats))]
 
@@ -159,8 +164,9 @@ def make_scoring(sa=1, sb=-3, sg=-5, ss=-2, matrix=None):
 
 
 def make_opts(stats: Stats | None = None, use_domination=True, use_score_filter=True, use_qprefix=True,
-              entry_capacity=0, hit_capacity=0, score_bits=0):
+              entry_capacity=0, hit_capacity=0, score_bits=0, use_reuse=False):
     o = SearchOpts()
+    o.use_reuse = 1 if use_reuse else 0
     o.score_bits = int(score_bits)
     o.use_domination = 1 if use_domination else 0
     o.use_score_filter = 1 if use_score_filter else 0

@@ -474,22 +474,180 @@ __global__ void __launch_bounds__(256) k_chain_general(SearchArgs a, const Node 
 // ---------------------------------------------------------------------------
 
 struct WideStats {
-    unsigned long long steps, entries, diag, gap2, gap3, hits, bytes;
+    unsigned long long steps, entries, diag, gap2, gap3, hits, bytes, reused, replay;
 };
+
+// ---------------------------------------------------------------------------
+// Reuse of duplicate forks (Section 4.1, Lemmas 2 and 3)
+// ---------------------------------------------------------------------------
+// A chain row may consist of K+1 copies of one fork: entries k*L+i equal
+// entry i with every column moved by delta_k (delta_0 = 0).  Scores in the
+// copies stay equal while (a) each copy only touches columns whose query
+// characters equal those under the first copy (the common prefix of the query
+// suffixes at the copies' first columns) and (b) no copy reaches the next one
+// (columns only influence columns to their right).  While that holds the
+// walker computes the first copy alone and emits every hit once per copy;
+// when the next row could break it, the copies are written out and the row is
+// walked in full from there on.  The first copy is filtered with its own gain
+// bound U(j) of Theorem 2, which is at least that of every later copy (U does
+// not increase with j): a later copy then keeps a superset of the states its
+// own bound would keep, each with a score some alignment reaches, so after the
+// max-merge its hits are unchanged.
+struct Replay {
+    uint32_t K;         // copies besides the first (0: none)
+    uint32_t col0;      // first column of the first copy
+    uint32_t span_lim;  // a row may reach columns col0 .. col0 + span_lim - 1
+    uint32_t dK;        // offset of the last copy
+};
+
+__device__ inline uint32_t wave_min_u32(uint32_t v) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        const uint32_t o = __shfl_xor(v, d, 64);
+        v = o < v ? o : v;
+    }
+    return v;
+}
+
+__device__ inline int32_t wave_max_i32(int32_t v) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        const int32_t o = __shfl_xor(v, d, 64);
+        v = o > v ? o : v;
+    }
+    return v;
+}
+
+// Recognise a row made of copies of its first fork; deltas[0..K] go to LDS.
+template <class Row>
+__device__ void replay_detect(const SearchArgs &a, const Row &cur, uint32_t len, Replay &rp, uint32_t *deltas) {
+    const int lane = threadIdx.x & 63;
+    rp.K = 0;
+    if (len < 2) return;
+    const Entry e0 = cur.load(0);
+    // candidate copy length L: a column hole before entry L, the same state as
+    // entry 0, and len a multiple of L with at most 63 further copies
+    uint32_t L = 0;
+    for (uint32_t base = 1; base < len && L == 0; base += 64) {
+        const uint32_t k = base + lane;
+        bool cand = false;
+        if (k < len && 2 * k <= len && len % k == 0 && len / k <= 64) {
+            const Entry ek = cur.load(k), ep = cur.load(k - 1);
+            cand = ek.col > ep.col + 1 && ek.M == e0.M && ek.Ga == e0.Ga;
+        }
+        const unsigned long long b = __ballot(cand);
+        if (b) L = base + (uint32_t)__ffsll((long long)b) - 1;
+    }
+    if (L == 0) return;
+    const uint32_t K = len / L - 1;
+    for (uint32_t base = L; base < len; base += 64) {
+        const uint32_t k = base + lane;
+        bool bad = false;
+        if (k < len) {
+            const uint32_t c = k / L, i = k - c * L;
+            const Entry ek = cur.load(k), ei = cur.load(i), eh = cur.load(c * L);
+            bad = (ek.col - eh.col) != (ei.col - e0.col) || ek.M != ei.M || ek.Ga != ei.Ga;
+            if (i == 0) bad = bad || ek.col <= cur.load(k - 1).col + 1;
+        }
+        if (__ballot(bad)) return;
+    }
+    if ((uint32_t)lane <= K) deltas[lane] = cur.load((uint32_t)lane * L).col - e0.col;
+    __syncthreads();
+    uint32_t gap = 0xFFFFFFFFu;  // lane k < K: distance from copy k to copy k+1
+    if ((uint32_t)lane < K) gap = deltas[lane + 1] - deltas[lane];
+    const uint32_t mingap = wave_min_u32(gap);
+    uint32_t lcp = 0xFFFFFFFFu;  // lane k < K: common prefix of the query at col0 and at col0 + delta_{k+1}
+    if ((uint32_t)lane < K) {
+        const uint32_t d = deltas[lane + 1];
+        const uint32_t avail = a.m - (e0.col + d);
+        const uint32_t lim = mingap < avail ? mingap : avail;
+        uint32_t t = 0;
+        while (t < lim && a.query[e0.col + t] == a.query[e0.col + d + t]) ++t;
+        lcp = t;
+    }
+    const uint32_t minlcp = wave_min_u32(lcp);
+    rp.span_lim = mingap < minlcp ? mingap : minlcp;
+    rp.col0 = e0.col;
+    rp.dK = deltas[K];
+    rp.K = K;
+}
+
+// Rightmost column the next row of the first copy can touch: the diagonal
+// reaches one column past the last entry, a G_b run continues while its value
+// stays positive, and no state of the next row exceeds the largest state of
+// this row plus s_max.
+template <class Row>
+__device__ inline int64_t replay_reach(const SearchArgs &a, const Row &cur, uint32_t len) {
+    int32_t v = kNeg;
+    for (uint32_t k = (uint32_t)(threadIdx.x & 63); k < len; k += 64) {
+        const Entry e = cur.load(k);
+        v = imax(v, imax(e.M, e.Ga));
+    }
+    v = wave_max_i32(v);
+    const int64_t num = (int64_t)v + a.smax + a.sg;
+    const int64_t ext = num > 0 ? (num - 1) / (-(int64_t)a.ss) : 0;
+    return (int64_t)cur.load(len - 1).col + 1 + ext;
+}
+
+// Entry k of the row with its copies written out.
+template <class Row>
+__device__ inline Entry replay_entry(const Row &cur, uint32_t len, const uint32_t *deltas, uint32_t k) {
+    const uint32_t c = k / len;
+    Entry e = cur.load(k - c * len);
+    if (c) {
+        const uint32_t d = deltas[c];
+        e.col += d;
+        if (e.M > 0) e.yM += d;
+        if (e.Ga > 0) e.yGa += d;
+    }
+    return e;
+}
+
+template <class Row>
+__device__ void replay_materialize(Row &cur, uint32_t len, uint32_t K, const uint32_t *deltas) {
+    const int lane = threadIdx.x & 63;
+    for (uint32_t k = len + (uint32_t)lane; k < (K + 1) * len; k += 64) cur.store(k, replay_entry(cur, len, deltas, k));
+    __syncthreads();
+}
 
 // Walk one chain whose row is held in (cur, nxt) buffers of capacity cap.
 // Returns false if the row outgrew the buffers; the live row is then in cur
 // (len, e_end, depth describe it) and the caller spills it.
+// With reuse on, the row may be held as its first copy (rp.K > 0); on a false
+// return the caller writes out the copies (replay_entry) when it spills.
 template <class Row>
 __device__ bool walk_wide(const SearchArgs &a, Row &cur, Row &nxt, uint32_t &len, uint32_t &e_end, int32_t &depth,
                           uint32_t cap, uint64_t *hkeys, uint32_t *hscores, Caps caps, Counters *cnt, HitRes &hr,
-                          WideStats &w) {
+                          WideStats &w, Replay &rp, uint32_t *deltas) {
     const int lane = threadIdx.x & 63;
     uint32_t txt = 0;
     int tpos = 64;
+    rp.K = 0;
+    // look for copies now and every 16 rows (background forks die early in a
+    // chain, leaving the copies), until copies have been written out once
+    bool look = a.use_reuse != 0;
+    uint32_t since = 0;
     for (;;) {
         const int32_t d1 = depth + 1;
         if (d1 > a.lmax || (uint64_t)e_end + 1 >= a.n) return true;
+        if (look && rp.K == 0 && (since++ & 15u) == 0) {
+            replay_detect(a, cur, len, rp, deltas);
+            if (rp.K) {
+                len /= rp.K + 1;  // keep the first copy only
+                w.replay++;
+            }
+        }
+        if (rp.K) {
+            const int64_t R = replay_reach(a, cur, len);
+            const bool ok = R - (int64_t)rp.col0 < (int64_t)rp.span_lim && R + (int64_t)rp.dK < (int64_t)a.m;
+            if (!ok) {  // the copies could diverge: write them out
+                if ((uint64_t)(rp.K + 1) * len > cap) return false;
+                replay_materialize(cur, len, rp.K, deltas);
+                len *= rp.K + 1;
+                rp.K = 0;
+                look = false;
+            }
+        }
         if (tpos == 64) {  // next 64 text characters, one per lane
             const uint64_t p = (uint64_t)e_end + 1 + lane;
             txt = p < a.n ? a.text[p] : 0u;
@@ -505,12 +663,15 @@ __device__ bool walk_wide(const SearchArgs &a, Row &cur, Row &nxt, uint32_t &len
         o.hit_cap = caps.hits;
         o.cnt = cnt;
         o.e_child = e_end + 1;
+        o.rK = rp.K;
+        o.rdelta = deltas;
         wide_child_row(a, cur, len, nxt, c, d1, o, hr);
         __syncthreads();
         w.steps++;
         w.bytes += (unsigned long long)(len + o.len) * 12ull;
         if (o.overflow) return false;
         w.entries += o.len;
+        w.reused += (unsigned long long)rp.K * o.len;
         w.diag += o.diag;
         w.gap2 += o.gap2;
         w.gap3 += o.gap3;
@@ -534,6 +695,8 @@ __device__ inline void wide_stats_flush(Counters *cnt, const WideStats &w) {
     atomicAdd(&cnt->st_gap3, w.gap3);
     atomicAdd(&cnt->st_emitted, w.hits);
     atomicAdd(&cnt->st_chain_bytes, w.bytes);
+    if (w.reused) atomicAdd(&cnt->st_reused, w.reused);
+    if (w.replay) atomicAdd(&cnt->st_replay, w.replay);
 }
 
 // Rows in LDS (one wave per block).  A row that outgrows kWideCap entries is
@@ -545,9 +708,10 @@ __global__ void __launch_bounds__(64) k_chain_wide_lds(SearchArgs a, const Node 
     __shared__ uint32_t s_col[2][kWideCap];
     __shared__ int32_t s_M[2][kWideCap];
     __shared__ int32_t s_Ga[2][kWideCap];
+    __shared__ uint32_t s_delta[64];
     const int lane = threadIdx.x & 63;
     HitRes hr = {0, 0, 0};
-    WideStats w = {0, 0, 0, 0, 0, 0, 0};
+    WideStats w = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     for (;;) {
         unsigned long long it = 0;
         if (lane == 0) it = atomicAdd(&cnt->wide_head, 1ull);
@@ -560,15 +724,21 @@ __global__ void __launch_bounds__(64) k_chain_wide_lds(SearchArgs a, const Node 
         SoaRow cur{s_col[0], s_M[0], s_Ga[0]};
         SoaRow nxt{s_col[1], s_M[1], s_Ga[1]};
         bool done = true;
+        Replay rp;
+        rp.K = 0;
         if (len <= (uint32_t)kWideCap) {
             for (uint32_t k = lane; k < len; k += 64) cur.store(k, went[nd.off + k]);
             __syncthreads();
-            done = walk_wide(a, cur, nxt, len, e_end, depth, (uint32_t)kWideCap, hkeys, hscores, caps, cnt, hr, w);
+            done = walk_wide(a, cur, nxt, len, e_end, depth, (uint32_t)kWideCap, hkeys, hscores, caps, cnt, hr, w,
+                             rp, s_delta);
         } else {
             done = false;
         }
         if (!done) {
-            // spill the live row (from LDS, or the queued row if it never fit)
+            // spill the live row (from LDS, or the queued row if it never fit),
+            // with its copies written out
+            const uint32_t part = len;
+            len *= rp.K + 1;
             unsigned long long slot = 0, off = 0;
             if (lane == 0) {
                 slot = atomicAdd(&cnt->onodes, 1ull);
@@ -580,7 +750,8 @@ __global__ void __launch_bounds__(64) k_chain_wide_lds(SearchArgs a, const Node 
             off = __shfl(off, 0, 64);
             if (slot < caps.onodes && off + len <= caps.oentries) {
                 const bool from_lds = nd.len <= (uint32_t)kWideCap;
-                for (uint32_t k = lane; k < len; k += 64) oents[off + k] = from_lds ? cur.load(k) : went[nd.off + k];
+                for (uint32_t k = lane; k < len; k += 64)
+                    oents[off + k] = from_lds ? replay_entry(cur, part, s_delta, k) : went[nd.off + k];
                 if (lane == 0) {
                     Node sn;
                     sn.lo = kUniqueBit | e_end;
@@ -604,8 +775,9 @@ __global__ void __launch_bounds__(64) k_chain_wide_global(SearchArgs a, const No
     const int lane = threadIdx.x & 63;
     Entry *buf0 = rowbuf + (uint64_t)blockIdx.x * 2ull * caps.wrow;
     Entry *buf1 = buf0 + caps.wrow;
+    __shared__ uint32_t s_delta[64];
     HitRes hr = {0, 0, 0};
-    WideStats w = {0, 0, 0, 0, 0, 0, 0};
+    WideStats w = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     for (;;) {
         unsigned long long it = 0;
         if (lane == 0) it = atomicAdd(&cnt->overflow_head, 1ull);
@@ -622,7 +794,9 @@ __global__ void __launch_bounds__(64) k_chain_wide_global(SearchArgs a, const No
         for (uint32_t k = lane; k < len; k += 64) buf0[k] = ents[nd.off + k];
         __syncthreads();
         AosRow cur{buf0}, nxt{buf1};
-        if (!walk_wide(a, cur, nxt, len, e_end, depth, (uint32_t)caps.wrow, hkeys, hscores, caps, cnt, hr, w)) {
+        Replay rp;
+        if (!walk_wide(a, cur, nxt, len, e_end, depth, (uint32_t)caps.wrow, hkeys, hscores, caps, cnt, hr, w, rp,
+                       s_delta)) {
             if (lane == 0) atomicOr(&cnt->overflow, kOvWideRow);
         }
         __syncthreads();

@@ -66,6 +66,7 @@ struct SearchArgs {
     // Several queries searched together: their codes are concatenated and no
     // alignment may cross from one query into the next.
     int32_t multi;
+    int32_t use_reuse;       // replay forks that are copies of one another (Section 4)
     const uint32_t *qord;    // per column: ordinal of its query
     const uint32_t *segbeg;  // per query: first column
     const uint32_t *segend;  // per query: one past its last column
@@ -204,6 +205,8 @@ struct Counters {
     unsigned long long general_head;
     unsigned long long st_ngr_steps;    // chain steps taken in the no-gap fast path
     unsigned long long stage_need;      // longest row that did not fit a level-wide staging buffer
+    unsigned long long st_reused;       // entries replayed from an identical fork instead of computed
+    unsigned long long st_replay;       // chains recognised as copies of one fork
 };
 
 // Key of an unused hit slot: sorts after every real (column, text end) key.

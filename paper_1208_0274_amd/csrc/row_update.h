@@ -475,6 +475,9 @@ struct WideOut {
     unsigned long long hit_cap;
     Counters *cnt;
     uint32_t e_child;  // text end of the child occurrence (hit coordinate)
+    // replayed forks: every hit is also emitted at col + rdelta[r], r = 1..rK
+    uint32_t rK;
+    const uint32_t *rdelta;
     // results (wave-uniform)
     uint32_t len;
     bool overflow;
@@ -665,14 +668,18 @@ __device__ inline void wide_child_row(const SearchArgs &a, const Row cur, uint32
         uint32_t htot;
         const uint32_t hpre = wave_excl_scan_u32(nh, &htot);
         if (htot) {
-            hit_reserve(hr, htot, o.hkeys, o.hscores, o.hit_cap, o.cnt);
-            unsigned long long slot = hr.base + hpre;
+            const uint32_t copies = o.rK + 1;
+            const unsigned long long hall = (unsigned long long)htot * copies;
+            hit_reserve(hr, hall, o.hkeys, o.hscores, o.hit_cap, o.cnt);
+            unsigned long long slot = hr.base + (unsigned long long)hpre * copies;
             auto put = [&](uint32_t col, int32_t M) {
-                if (slot < o.hit_cap) {
-                    o.hkeys[slot] = ((uint64_t)col << 32) | o.e_child;
-                    o.hscores[slot] = (uint32_t)M;
+                for (uint32_t r = 0; r < copies; ++r) {
+                    if (slot < o.hit_cap) {
+                        o.hkeys[slot] = ((uint64_t)(col + (r ? o.rdelta[r] : 0u)) << 32) | o.e_child;
+                        o.hscores[slot] = (uint32_t)M;
+                    }
+                    ++slot;
                 }
-                ++slot;
             };
             if (nA && keepMA && MA >= a.H) put(e.col, MA);
             if (nB && MB >= a.H) put(e.col + 1, MB);
@@ -682,9 +689,9 @@ __device__ inline void wide_child_row(const SearchArgs &a, const Row cur, uint32
                 if (v < a.H) break;
                 put(col, v);
             }
-            hr.base += htot;
-            hr.left -= htot;
-            hits += htot;
+            hr.base += hall;
+            hr.left -= hall;
+            hits += hall;
         }
         // cost classes of the entries of this round
         uint32_t c1 = nspread, c2 = 0, c3 = 0;

@@ -651,6 +651,7 @@ static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64
     a.use_domination = use_dom ? 1 : 0;
     a.u_closed = sch.matrix_mode ? 0 : 1;
     a.ngr_walk = getenv("ALAE_NO_NGR") ? 0 : 1;
+    a.use_reuse = (opts && opts->use_reuse && !multi) ? 1 : 0;
     a.matrix_mode = sch.matrix_mode;
     a.s_match = sch.matrix_mode ? 0 : scoring->sa;
     a.s_mismatch = sch.matrix_mode ? 0 : scoring->sb;
@@ -1093,6 +1094,8 @@ static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64
         o->dominated_gapped = c.st_dominated_gapped;
         o->chain_bytes = c.st_chain_bytes;
         o->merge_ms = merge_ms;
+        o->reused = c.st_reused;
+        o->replay_chains = c.st_replay;
     }
     return ALAE_OK;
 }
