@@ -120,7 +120,40 @@ typedef struct {
      * Equation 6 is reused / (reused + entries) */
     uint64_t reused;
     uint64_t replay_chains;  /* chains whose row was recognised as copies of one fork  */
+    uint64_t partitioned;    /* lane-queue chains the work predictor sent to the first wave pass */
+    uint64_t leftover;       /* wave-queue chains walked after the concurrent pass            */
+    double order_ms;         /* device time of features, predictions and the partition        */
 } alae_stats;
+
+/*
+ * Learned frontier ordering.  A chain item (a trie node with one text
+ * occurrence, walked along the text by one lane or one wave) is described by
+ * ALAE_MLP_FEATURES numbers: log2(1 + depth) / 8, log2(1 + live entries) / 10,
+ * max M / H, log2(1 + sum of M) / 20, max G_a / H, log2(1 + column span) / 16,
+ * (columns left after the best entry) / L_max, the walker (0: one lane,
+ * 1: one wave), and the fraction of positive substitution scores between the
+ * next 32 (then 128) text characters the chain will read and the query
+ * characters after its best entry.  Its measured work is DP entries computed
+ * plus rows stepped, including the work of its continuation when a lane walk
+ * is handed to the wave walker.
+ * A trace records (features, work) for every item of a search; an alae_mlp
+ * trained on log2(1 + work) orders the walkers' queues by predicted work,
+ * largest first.  Ordering never changes the hit set.
+ */
+#define ALAE_MLP_FEATURES 10
+#define ALAE_MLP_HIDDEN 32
+#define ALAE_MLP_PARAMS (ALAE_MLP_HIDDEN * ALAE_MLP_FEATURES + ALAE_MLP_HIDDEN + \
+                         ALAE_MLP_HIDDEN * ALAE_MLP_HIDDEN + ALAE_MLP_HIDDEN + ALAE_MLP_HIDDEN + 1)
+
+typedef struct alae_mlp alae_mlp;
+
+typedef struct {
+    float *features;   /* capacity * ALAE_MLP_FEATURES, caller-owned host memory */
+    float *work;       /* capacity                                               */
+    size_t capacity;
+    size_t count;      /* out: items recorded (at most capacity)                 */
+    size_t total;      /* out: items seen                                        */
+} alae_trace;
 
 /* Search options; pass NULL for the defaults. */
 typedef struct {
@@ -129,10 +162,15 @@ typedef struct {
     int32_t use_score_filter;  /* Theorem 2 (default 1)                                     */
     int32_t use_qprefix;       /* Theorem 3 q-prefix seeding (default 1)                    */
     int32_t use_reuse;         /* Section 4 reuse of duplicate forks (default 0)             */
-    int32_t reserved1;
+    int32_t order_queues;      /* with order_model: 1 = lane-walker queue, 2 = wave-walker queue,
+                                  3 = both; 0 = the default (2)                              */
     uint64_t entry_capacity;   /* frontier entries per level buffer, 0 = automatic          */
     uint64_t hit_capacity;     /* emitted hit records, 0 = automatic                        */
     alae_stats *stats;         /* filled when not NULL                                      */
+    const alae_mlp *order_model; /* order the walkers' queues by predicted work (NULL: queue order) */
+    alae_trace *trace;         /* record (features, work) of every chain item when not NULL */
+    float partition_threshold; /* with order_model: predicted log2(1 + work) from which a lane-queue
+                                  chain is walked by the wave walker from its start (<= 0: never) */
 } alae_search_opts;
 
 /* Index options; pass NULL for the defaults. */
@@ -279,6 +317,28 @@ alae_status alae_server_submit(alae_server *srv, const char *query, size_t m, co
  * request with wait == 0 returns ALAE_OK with out->count == SIZE_MAX. */
 alae_status alae_server_poll(alae_server *srv, uint64_t req_id, int wait, alae_hits *out);
 void alae_server_destroy(alae_server *srv);
+
+/*
+ * The work predictor (feature layout above).  Parameters are fp32, laid out
+ * as W1[32][F] (row = output unit), b1[32], W2[32][32], b2[32], W3[32], b3;
+ * hidden units use ReLU.  All computation runs in the library's own HIP
+ * kernels on `device`.  The loss is 0.5 * mean over samples of
+ * (prediction - target)^2.
+ *   create: He-uniform weights from seed, zero biases.
+ *   predict: y[i] for the n feature rows x (host arrays).
+ *   loss_grad: the loss and its gradient with respect to every parameter.
+ *   train: epochs of Adam (beta 0.9 / 0.999) over shuffled minibatches;
+ *          final_loss (nullable) gets the loss over all samples afterwards.
+ * A model must not be used by two threads at once.
+ */
+alae_status alae_mlp_create(int device, uint64_t seed, alae_mlp **out);
+void alae_mlp_free(alae_mlp *net);
+alae_status alae_mlp_get_params(const alae_mlp *net, float *params);
+alae_status alae_mlp_set_params(alae_mlp *net, const float *params);
+alae_status alae_mlp_predict(alae_mlp *net, const float *x, size_t n, float *y);
+alae_status alae_mlp_loss_grad(alae_mlp *net, const float *x, const float *t, size_t n, double *loss, float *grad);
+alae_status alae_mlp_train(alae_mlp *net, const float *x, const float *t, size_t n, uint32_t epochs,
+                           uint32_t batch, float lr, uint64_t seed, double *final_loss);
 
 /* Message for the last failing call on this thread. */
 const char *alae_last_error(void);

@@ -63,7 +63,8 @@ class Stats(ctypes.Structure):
                 ("general_ms", ctypes.c_double), ("wide_ms", ctypes.c_double), ("chain_steps", ctypes.c_uint64),
                 ("wide_steps", ctypes.c_uint64), ("promoted", ctypes.c_uint64),
                 ("dominated_gapped", ctypes.c_uint64), ("chain_bytes", ctypes.c_uint64),
-                ("merge_ms", ctypes.c_double), ("reused", ctypes.c_uint64), ("replay_chains", ctypes.c_uint64)]
+                ("merge_ms", ctypes.c_double), ("reused", ctypes.c_uint64), ("replay_chains", ctypes.c_uint64),
+                ("partitioned", ctypes.c_uint64), ("leftover", ctypes.c_uint64), ("order_ms", ctypes.c_double)]
 
     def reusing_ratio(self) -> float:
         """Equation 6: reused entries over accessed (reused + computed) entries."""
@@ -79,12 +80,23 @@ class Stats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+MLP_FEATURES = 10
+MLP_HIDDEN = 32
+MLP_PARAMS = MLP_HIDDEN * MLP_FEATURES + MLP_HIDDEN + MLP_HIDDEN * MLP_HIDDEN + MLP_HIDDEN + MLP_HIDDEN + 1
+
+
+class TraceStruct(ctypes.Structure):
+    _fields_ = [("features", ctypes.POINTER(ctypes.c_float)), ("work", ctypes.POINTER(ctypes.c_float)),
+                ("capacity", ctypes.c_size_t), ("count", ctypes.c_size_t), ("total", ctypes.c_size_t)]
+
+
 class SearchOpts(ctypes.Structure):
     _fields_ = [("score_bits", ctypes.c_int32), ("use_domination", ctypes.c_int32),
                 ("use_score_filter", ctypes.c_int32), ("use_qprefix", ctypes.c_int32),
-                ("use_reuse", ctypes.c_int32), ("reserved1", ctypes.c_int32),
+                ("use_reuse", ctypes.c_int32), ("order_queues", ctypes.c_int32),
                 ("entry_capacity", ctypes.c_uint64), ("hit_capacity", ctypes.c_uint64),
-                ("stats", ctypes.POINTER(Stats))]
+                ("stats", ctypes.POINTER(Stats)), ("order_model", ctypes.c_void_p),
+                ("trace", ctypes.POINTER(TraceStruct)), ("partition_threshold", ctypes.c_float)]
 
 
 class IndexOpts(ctypes.Structure):
@@ -135,6 +147,15 @@ _sig("alae_search_device", _st, _vp, _vp, ctypes.c_size_t, ctypes.POINTER(Scorin
 _sig("alae_search_device_batch", _st, _vp, _vp, ctypes.POINTER(ctypes.c_size_t), ctypes.c_size_t,
      ctypes.POINTER(Scoring), ctypes.c_int32, ctypes.POINTER(SearchOpts), _vp, ctypes.POINTER(ctypes.c_size_t))
 _sig("alae_workspace_batch_offsets", _st, _vp, ctypes.POINTER(ctypes.c_size_t), ctypes.c_size_t)
+_fp = ctypes.POINTER(ctypes.c_float)
+_sig("alae_mlp_create", _st, ctypes.c_int, ctypes.c_uint64, ctypes.POINTER(_vp))
+_sig("alae_mlp_free", None, _vp)
+_sig("alae_mlp_get_params", _st, _vp, _fp)
+_sig("alae_mlp_set_params", _st, _vp, _fp)
+_sig("alae_mlp_predict", _st, _vp, _fp, ctypes.c_size_t, _fp)
+_sig("alae_mlp_loss_grad", _st, _vp, _fp, _fp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_double), _fp)
+_sig("alae_mlp_train", _st, _vp, _fp, _fp, ctypes.c_size_t, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_float,
+     ctypes.c_uint64, ctypes.POINTER(ctypes.c_double))
 _sig("alae_workspace_result", _st, _vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(ctypes.c_size_t))
 _sig("alae_workspace_copy_result", _st, _vp, _vp, _vp, _vp)
 
@@ -164,9 +185,14 @@ def make_scoring(sa=1, sb=-3, sg=-5, ss=-2, matrix=None):
 
 
 def make_opts(stats: Stats | None = None, use_domination=True, use_score_filter=True, use_qprefix=True,
-              entry_capacity=0, hit_capacity=0, score_bits=0, use_reuse=False):
+              entry_capacity=0, hit_capacity=0, score_bits=0, use_reuse=False, order_model=None, trace=None,
+              order_queues=0, partition_threshold=0.0):
     o = SearchOpts()
+    o.partition_threshold = float(partition_threshold)
+    o.order_queues = int(order_queues)
     o.use_reuse = 1 if use_reuse else 0
+    o.order_model = order_model._h.value if order_model is not None else None
+    o.trace = ctypes.pointer(trace._s) if trace is not None else None
     o.score_bits = int(score_bits)
     o.use_domination = 1 if use_domination else 0
     o.use_score_filter = 1 if use_score_filter else 0
@@ -372,6 +398,88 @@ class Workspace:
     def free(self):
         if self._h:
             _lib.alae_workspace_free(self._h)
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def _f32(a):
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+
+class Trace:
+    """Per-chain-item (features, measured work) of one search, for training the work predictor."""
+
+    def __init__(self, capacity: int = 1 << 20):
+        self.features = np.zeros((capacity, MLP_FEATURES), dtype=np.float32)
+        self.work = np.zeros(capacity, dtype=np.float32)
+        self._s = TraceStruct()
+        self._s.features = self.features.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+        self._s.work = self.work.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+        self._s.capacity = capacity
+
+    @property
+    def count(self) -> int:
+        return int(self._s.count)
+
+    @property
+    def total(self) -> int:
+        return int(self._s.total)
+
+    def arrays(self):
+        n = self.count
+        return self.features[:n].copy(), self.work[:n].copy()
+
+
+class MLP:
+    """The work predictor: forward, backward and Adam run in the library's HIP kernels."""
+
+    def __init__(self, seed: int = 0, device: int = 0):
+        self._h = _vp()
+        _check(_lib.alae_mlp_create(int(device), int(seed), ctypes.byref(self._h)), "alae_mlp_create")
+
+    def get_params(self) -> np.ndarray:
+        p = np.zeros(MLP_PARAMS, dtype=np.float32)
+        _check(_lib.alae_mlp_get_params(self._h, p.ctypes.data_as(_fp)), "alae_mlp_get_params")
+        return p
+
+    def set_params(self, p):
+        arr, ptr = _f32(p)
+        assert arr.shape == (MLP_PARAMS,)
+        _check(_lib.alae_mlp_set_params(self._h, ptr), "alae_mlp_set_params")
+
+    def predict(self, x) -> np.ndarray:
+        arr, ptr = _f32(x)
+        n = arr.shape[0]
+        y = np.zeros(n, dtype=np.float32)
+        _check(_lib.alae_mlp_predict(self._h, ptr, n, y.ctypes.data_as(_fp)), "alae_mlp_predict")
+        return y
+
+    def loss_grad(self, x, t):
+        xa, xp = _f32(x)
+        ta, tp = _f32(t)
+        g = np.zeros(MLP_PARAMS, dtype=np.float32)
+        loss = ctypes.c_double()
+        _check(_lib.alae_mlp_loss_grad(self._h, xp, tp, xa.shape[0], ctypes.byref(loss), g.ctypes.data_as(_fp)),
+               "alae_mlp_loss_grad")
+        return float(loss.value), g
+
+    def train(self, x, t, epochs=20, batch=1024, lr=1e-3, seed=0) -> float:
+        xa, xp = _f32(x)
+        ta, tp = _f32(t)
+        loss = ctypes.c_double()
+        _check(_lib.alae_mlp_train(self._h, xp, tp, xa.shape[0], int(epochs), int(batch), float(lr), int(seed),
+                                   ctypes.byref(loss)), "alae_mlp_train")
+        return float(loss.value)
+
+    def free(self):
+        if self._h:
+            _lib.alae_mlp_free(self._h)
             self._h = _vp()
 
     def __del__(self):

@@ -81,8 +81,10 @@ __device__ uint32_t prune_dominated(const SearchArgs &a, Entry *row, uint32_t le
 __device__ inline Entry *queue_alloc(Counters *cnt, unsigned long long *nodes_ctr, unsigned long long *ent_ctr,
                                      unsigned long long node_cap, unsigned long long ent_cap,
                                      unsigned long long ov_nodes, unsigned long long ov_ent, Node *qnodes,
-                                     Entry *qents, uint32_t len, uint32_t e_end, int32_t depth) {
+                                     Entry *qents, uint32_t len, uint32_t e_end, int32_t depth,
+                                     uint32_t *slot_out = nullptr) {
     const unsigned long long slot = atomicAdd(nodes_ctr, 1ull);
+    if (slot_out) *slot_out = (uint32_t)slot;
     const unsigned long long off = atomicAdd(ent_ctr, (unsigned long long)len);
     if (slot >= node_cap || off + len > ent_cap) {
         atomicOr(&cnt->overflow, slot >= node_cap ? ov_nodes : ov_ent);
@@ -97,20 +99,34 @@ __device__ inline Entry *queue_alloc(Counters *cnt, unsigned long long *nodes_ct
     return qents + off;
 }
 
-// Queue a row for the wave walkers after the gapped domination test.
+// Queue a row for the wave walkers after the gapped domination test; wsrc
+// (nullable) records the lane-queue item src the row continues.
+// ready (nullable) publishes the item to a concurrently running wave walker:
+// 1 once the row is written, 2 if the slot stays empty (capacity overflow).
 __device__ void push_wide(const SearchArgs &a, Entry *row, uint32_t len, uint32_t e_end, int32_t depth,
-                          Node *witems, Entry *went, Caps caps, Counters *cnt, unsigned long long &dom_count) {
+                          Node *witems, Entry *went, Caps caps, Counters *cnt, unsigned long long &dom_count,
+                          uint32_t src = 0, uint32_t *wsrc = nullptr, uint32_t *ready = nullptr) {
     uint32_t keep = len;
     if (a.use_domination) keep = prune_dominated(a, row, len, e_end, depth, dom_count);
     if (keep == 0) return;
+    uint32_t slot = 0;
     Entry *dst = queue_alloc(cnt, &cnt->wnodes, &cnt->wentries, caps.wnodes, caps.wentries, kOvWideNodes,
-                             kOvWideEntries, witems, went, keep, e_end, depth);
-    if (!dst) return;
+                             kOvWideEntries, witems, went, keep, e_end, depth, &slot);
+    if (!dst) {
+        if (ready && slot < caps.wnodes) __hip_atomic_store(&ready[slot], 2u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        return;
+    }
+    if (wsrc) wsrc[slot] = src;
     uint32_t w = 0;
     for (uint32_t k = 0; k < len; ++k) {
         const Entry e = row[k];
         if (e.M <= 0 && e.Ga <= 0) continue;
         dst[w++] = e;
+    }
+    if (ready) {
+        __threadfence();
+        __hip_atomic_store(&ready[slot], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        atomicMin(&cnt->t_push0, (unsigned long long)__builtin_amdgcn_s_memrealtime());
     }
 }
 
@@ -347,15 +363,21 @@ __global__ void __launch_bounds__(256) k_chain_start(SearchArgs a, SubTable subt
 // k_chain_general: one lane per chain with gap states; idle lanes take the
 // next queue items.  A row wider than kNarrowRow goes to the wave walkers.
 // ---------------------------------------------------------------------------
+// order (nullable) gives the sequence in which queue items are taken;
+// trace_work (nullable) receives each item's work (entries computed + rows).
 __global__ void __launch_bounds__(256) k_chain_general(SearchArgs a, const Node *items, uint32_t nitems,
                                                        const Entry *ient, Node *witems, Entry *went,
                                                        uint64_t *hkeys, uint32_t *hscores, Caps caps,
-                                                       Counters *cnt) {
+                                                       Counters *cnt, const uint32_t *order, float *trace_work,
+                                                       uint32_t *wsrc, uint32_t *ready) {
     const int lane = threadIdx.x & 63;
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    if (lane == 0) atomicMin(&cnt->t_gen0, (unsigned long long)__builtin_amdgcn_s_memrealtime());
     Entry rows[2][kNarrowRow];
     int cur = 0;
     bool active = false;
+    uint32_t my_item = 0;
+    float my_work = 0.f;
     uint32_t e_end = 0, len = 0;
     int32_t depth = 0;
     bool exhausted = false;
@@ -372,7 +394,9 @@ __global__ void __launch_bounds__(256) k_chain_general(SearchArgs a, const Node 
             if (!active) {
                 const unsigned long long it = first + (unsigned long long)__popcll(idle & below);
                 if (it < nitems) {
-                    const Node nd = items[it];
+                    my_item = order ? order[it] : (uint32_t)it;
+                    my_work = 0.f;
+                    const Node nd = items[my_item];
                     e_end = nd.lo & ~kUniqueBit;
                     depth = (int32_t)nd.hi;
                     len = nd.len;
@@ -394,6 +418,7 @@ __global__ void __launch_bounds__(256) k_chain_general(SearchArgs a, const Node 
             if (d1 > a.lmax || (uint64_t)e_end + 1 >= a.n) {
                 active = false;
             } else {
+                my_work += 1.f;
                 const int c = a.text[e_end + 1];
                 RowSink s;
                 sink_init(s);
@@ -404,8 +429,9 @@ __global__ void __launch_bounds__(256) k_chain_general(SearchArgs a, const Node 
                 s.e_end = e_end + 1;
                 child_row<true>(a, rows[cur], len, c, d1, false, 0, s);
                 ++n_steps;
+                my_work += (float)s.n_entries;
                 if (s.n_entries > (uint32_t)kNarrowRow) {
-                    push_wide(a, rows[cur], len, e_end, depth, witems, went, caps, cnt, n_dom);
+                    push_wide(a, rows[cur], len, e_end, depth, witems, went, caps, cnt, n_dom, my_item, wsrc, ready);
                     ++n_prom;
                     active = false;
                 } else if (s.n_entries == 0) {
@@ -419,6 +445,10 @@ __global__ void __launch_bounds__(256) k_chain_general(SearchArgs a, const Node 
                     n_g3 += s.st_gap3;
                 }
             }
+        }
+        if (trace_work && !active && my_work > 0.f) {
+            trace_work[my_item] = my_work;
+            my_work = 0.f;
         }
         // hit records of the new rows (one atomic per wave)
         uint32_t nh = 0;
@@ -466,6 +496,10 @@ __global__ void __launch_bounds__(256) k_chain_general(SearchArgs a, const Node 
         atomicAdd(&cnt->st_chain_bytes, w_b);
         atomicAdd(&cnt->st_emitted, w_h);
         atomicAdd(&cnt->st_promoted, w_p);
+        // this wave pushes nothing more: tell a live wave walker
+        __threadfence();
+        atomicAdd(&cnt->gen_done, 1ull);
+        atomicMax(&cnt->t_gen1, (unsigned long long)__builtin_amdgcn_s_memrealtime());
     }
 }
 
@@ -701,10 +735,27 @@ __device__ inline void wide_stats_flush(Counters *cnt, const WideStats &w) {
 
 // Rows in LDS (one wave per block).  A row that outgrows kWideCap entries is
 // spilled to the global spill queue and continued by k_chain_wide_global.
-__global__ void __launch_bounds__(64) k_chain_wide_lds(SearchArgs a, const Node *witems, uint32_t nw,
-                                                       const Entry *went, Node *onodes, Entry *oents,
+// A wave-walker pass that runs while the lane walker still pushes items.
+struct LiveQueue {
+    const uint32_t *ready;  // per slot: 0 pending, 1 written, 2 never written (nullptr: static pass)
+    uint32_t nstatic;       // items 0 .. nstatic-1 were queued before the launch
+    uint32_t gen_waves;     // lane-walker waves whose end means no more items
+    uint32_t *missed;       // items claimed but given up (the next pass takes them)
+    uint64_t patience;      // ticks of the 100 MHz clock to wait without any progress
+};
+
+// Items first .. nw-1 of the queue (wide_head starts at first); order
+// (nullable) is a permutation of 0 .. nw-first-1 and trace_work is indexed
+// from first.  With a live queue, items are claimed in queue order as they
+// are published (order applies to the static part only), and the pass ends
+// when the lane walker has finished and every published item is taken; a
+// wave that sees no progress for `patience` gives its claimed item to the
+// next pass and stops, so the pass always ends.
+__global__ void __launch_bounds__(64) k_chain_wide_lds(SearchArgs a, const Node *witems, uint32_t first,
+                                                       uint32_t nw, const Entry *went, Node *onodes, Entry *oents,
                                                        uint64_t *hkeys, uint32_t *hscores, Caps caps,
-                                                       Counters *cnt) {
+                                                       Counters *cnt, const uint32_t *order, float *trace_work,
+                                                       LiveQueue live) {
     __shared__ uint32_t s_col[2][kWideCap];
     __shared__ int32_t s_M[2][kWideCap];
     __shared__ int32_t s_Ga[2][kWideCap];
@@ -712,15 +763,81 @@ __global__ void __launch_bounds__(64) k_chain_wide_lds(SearchArgs a, const Node 
     const int lane = threadIdx.x & 63;
     HitRes hr = {0, 0, 0};
     WideStats w = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    if (live.ready && lane == 0) atomicMin(&cnt->t_live0, (unsigned long long)__builtin_amdgcn_s_memrealtime());
     for (;;) {
         unsigned long long it = 0;
         if (lane == 0) it = atomicAdd(&cnt->wide_head, 1ull);
         it = __shfl(it, 0, 64);
-        if (it >= nw) break;
-        const Node nd = witems[it];
+        uint32_t item;
+        if (live.ready) {
+            // wait until slot `it` is published, the lane walker is done, or patience runs out
+            int state = 0;  // 1 take, 2 skip, 3 end, 4 give up
+            if (lane == 0) {
+                unsigned long long seen = ~0ull;
+                uint64_t since = __builtin_amdgcn_s_memrealtime();
+                for (uint32_t poll = 0;; ++poll) {
+                    if (it >= caps.wnodes) {
+                        state = 3;
+                        break;
+                    }
+                    // relaxed polls (an acquire load would invalidate the CU's L1 on every poll);
+                    // the fence after the loop orders the item's reads
+                    const uint32_t r = __hip_atomic_load(&live.ready[it], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    if (r == 1u) {
+                        state = 1;
+                        break;
+                    }
+                    if (r == 2u) {
+                        state = 2;
+                        break;
+                    }
+                    if (poll & 7u) {  // the shared counters are read on every eighth poll only
+                        __builtin_amdgcn_s_sleep(127);
+                        continue;
+                    }
+                    const unsigned long long done =
+                        __hip_atomic_load(&cnt->gen_done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    const unsigned long long made =
+                        __hip_atomic_load(&cnt->wnodes, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    if (done >= live.gen_waves) {
+                        // every push has been published; a slot past the end stays empty
+                        __atomic_thread_fence(__ATOMIC_ACQUIRE);
+                        const uint32_t r2 =
+                            __hip_atomic_load(&live.ready[it], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        state = r2 == 1u ? 1 : (it >= made ? 3 : 2);
+                        break;
+                    }
+                    const unsigned long long prog = done + (made << 20);
+                    const uint64_t now = __builtin_amdgcn_s_memrealtime();
+                    if (prog != seen) {
+                        seen = prog;
+                        since = now;
+                    } else if (now - since > live.patience) {
+                        state = 4;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(127);
+                }
+                if (state == 4) {
+                    const unsigned long long k = atomicAdd(&cnt->missed, 1ull);
+                    live.missed[k] = (uint32_t)it;
+                }
+            }
+            state = __shfl(state, 0, 64);
+            if (state == 2) continue;
+            if (state == 3 || state == 4) break;
+            __threadfence();
+            item = (it < live.nstatic && order) ? order[it] : (uint32_t)it;
+        } else {
+            if (it >= nw) break;
+            const uint32_t rel = (uint32_t)it - first;
+            item = first + (order ? order[rel] : rel);
+        }
+        const Node nd = witems[item];
         uint32_t e_end = nd.lo & ~kUniqueBit;
         int32_t depth = (int32_t)nd.hi;
         uint32_t len = nd.len;
+        const unsigned long long work0 = w.entries + w.steps;
         SoaRow cur{s_col[0], s_M[0], s_Ga[0]};
         SoaRow nxt{s_col[1], s_M[1], s_Ga[1]};
         bool done = true;
@@ -762,10 +879,144 @@ __global__ void __launch_bounds__(64) k_chain_wide_lds(SearchArgs a, const Node 
                 }
             }
         }
+        if (trace_work && lane == 0) trace_work[item - first] = (float)(w.entries + w.steps - work0);
         __syncthreads();
     }
     hit_release(hr, hkeys, hscores, caps.hits, cnt);
     wide_stats_flush(cnt, w);
+    if (live.ready && lane == 0) atomicMax(&cnt->t_live1, (unsigned long long)__builtin_amdgcn_s_memrealtime());
+}
+
+// Features of chain items (the layout documented with alae_mlp).
+__global__ void k_item_features(SearchArgs a, const Node *items, uint32_t n, const Entry *ents, float queue,
+                                float *feat) {
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const Node nd = items[t];
+    int32_t maxM = 0, maxGa = 0;
+    float sumM = 0.f;
+    uint32_t lo = 0xFFFFFFFFu, hi = 0, best = 0;
+    for (uint32_t k = 0; k < nd.len; ++k) {
+        const Entry e = ents[nd.off + k];
+        if (e.M > maxM) {
+            maxM = e.M;
+            best = e.col;
+        }
+        if (e.M > 0) sumM += (float)e.M;
+        maxGa = imax(maxGa, e.Ga);
+        lo = e.col < lo ? e.col : lo;
+        hi = e.col > hi ? e.col : hi;
+    }
+    const float lm = (float)a.lmax;
+    float *f = feat + (size_t)t * ALAE_MLP_FEATURES;
+    f[0] = log2f(1.f + (float)nd.hi) / 8.f;
+    f[1] = log2f(1.f + (float)nd.len) / 10.f;
+    f[2] = (float)maxM / (float)a.H;
+    f[3] = log2f(1.f + sumM) / 20.f;
+    f[4] = (float)maxGa / (float)a.H;
+    f[5] = nd.len ? log2f(1.f + (float)(hi - lo)) / 16.f : 0.f;
+    const float left = nd.len ? (float)(seg_end_of(a, best) - best) / lm : 0.f;
+    f[6] = left < 1.f ? left : 1.f;
+    f[7] = queue;
+    // look-ahead: positive substitution scores between the text the chain will
+    // read next and the query after the best entry, over characters 1-32 and
+    // 33-96 ahead (match/mismatch scoring: equal bytes, four per word)
+    uint32_t near = 0, far = 0;
+    if (nd.len) {
+        const uint64_t e = (uint64_t)(nd.lo & ~kUniqueBit);
+        const uint64_t qend = seg_end_of(a, best);
+        const uint64_t avail_t = a.n - 1 - e, avail_q = qend - 1 - best;
+        const uint32_t avail = (uint32_t)(avail_t < avail_q ? (avail_t < 96 ? avail_t : 96) : (avail_q < 96 ? avail_q : 96));
+        for (uint32_t w0 = 0; w0 < 96; w0 += 32) {
+            if (w0 >= avail) break;
+            uint32_t cnt32 = 0;
+            if (!a.matrix_mode) {
+                uint32_t tw[8], qw[8];
+                // window32 loads the 32 bytes ending before its position
+                load_window32(a.text, (int64_t)(e + 1 + w0 + 32), tw);
+                load_window32(a.query, (int64_t)(best + 1 + w0 + 32), qw);
+                for (int i = 0; i < 8; ++i) {
+                    const uint32_t v = tw[i] ^ qw[i];
+                    uint32_t z = (v & 0x7F7F7F7Fu) + 0x7F7F7F7Fu;
+                    z = ~(z | v | 0x7F7F7F7Fu);  // 0x80 in every byte where v is zero
+                    const uint32_t valid = avail - w0 >= 32 ? 8u : ((avail - w0) + 3) / 4;
+                    uint32_t mask = 0x80808080u;
+                    if ((uint32_t)i >= valid) mask = 0;
+                    else if ((uint32_t)i == valid - 1 && avail - w0 < 32 && ((avail - w0) & 3))
+                        mask = 0x80808080u >> (8 * (4 - ((avail - w0) & 3)));
+                    cnt32 += __popc(z & mask);
+                }
+            } else {
+                for (uint32_t k = 1 + w0; k <= w0 + 32 && k <= avail; ++k)
+                    cnt32 += a.prof[(size_t)a.text[e + k] * a.m + best + k] > 0;
+            }
+            if (w0 == 0)
+                near = cnt32;
+            else
+                far += cnt32;
+        }
+    }
+    f[8] = (float)near / 32.f;
+    f[9] = (float)far / 64.f;
+}
+
+// Partition of the lane-walker queue by predicted work: heavy[i] = 1 for
+// items predicted at or above the threshold, ent[i] = their entry count.
+__global__ void k_partition_flags(const float *pred, const Node *items, uint32_t n, float thresh, uint32_t *heavy,
+                                  uint32_t *ent) {
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t > n) return;
+    const bool h = t < n && pred[t] >= thresh && items[t].len > 0;
+    heavy[t] = h ? 1u : 0u;
+    ent[t] = h ? items[t].len : 0u;
+}
+
+// Move the flagged items to the wave-walker queue (slots wbase + pos, entries
+// at ebase + epos), after the gapped domination test every row gets on its
+// way to the wave walkers, and leave an empty row in their lane-walker slot.
+__global__ void k_partition_move(SearchArgs a, Node *items, Entry *ents, uint32_t n, const uint32_t *heavy,
+                                 const uint32_t *pos, const uint32_t *epos, Node *witems, Entry *went, uint32_t wbase,
+                                 uint32_t ebase, Counters *cnt) {
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n || !heavy[t]) return;
+    Node nd = items[t];
+    Entry *row = ents + nd.off;
+    unsigned long long dom = 0;
+    if (a.use_domination) prune_dominated(a, row, nd.len, nd.lo & ~kUniqueBit, (int32_t)nd.hi, dom);
+    if (dom) atomicAdd(&cnt->st_dominated_gapped, dom);
+    const uint32_t off = ebase + epos[t];
+    uint32_t w = 0;
+    for (uint32_t k = 0; k < nd.len; ++k) {
+        const Entry e = row[k];
+        if (e.M <= 0 && e.Ga <= 0) continue;
+        went[off + w++] = e;
+    }
+    Node wn = nd;
+    wn.off = off;
+    wn.len = w;  // an empty row ends its walk at once
+    witems[wbase + pos[t]] = wn;
+    nd.len = 0;
+    items[t] = nd;
+}
+
+// A trace charges the work of a promoted chain's wave-walker continuation
+// (items first .. first+n-1 of the wave queue) to its lane-queue item.
+__global__ void k_link_work(const uint32_t *wsrc, uint32_t first, uint32_t n, const float *wwork, float *gwork,
+                            uint32_t ng) {
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const uint32_t g = wsrc[first + t];
+    if (g < ng) atomicAdd(&gwork[g], wwork[t]);
+}
+
+// Sort keys that put the largest predicted work first.
+__global__ void k_order_keys(const float *pred, uint32_t n, uint64_t *keys, uint32_t *vals) {
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    float p = pred[t];
+    p = p > 0.f ? (p < 100.f ? p : 100.f) : 0.f;  // NaN maps to 0
+    keys[t] = 0xFFFFFFFFull - (uint64_t)(p * 33554432.f);
+    vals[t] = t;
 }
 
 // Rows in global memory: two buffers of caps.wrow entries per block.

@@ -207,6 +207,11 @@ struct Counters {
     unsigned long long stage_need;      // longest row that did not fit a level-wide staging buffer
     unsigned long long st_reused;       // entries replayed from an identical fork instead of computed
     unsigned long long st_replay;       // chains recognised as copies of one fork
+    unsigned long long gen_done;        // lane-walker waves that have finished
+    unsigned long long missed;          // wave-queue items a live consumer left for the next pass
+    unsigned long long t_gen0, t_gen1;  // first start / last end of lane-walker waves (100 MHz clock)
+    unsigned long long t_live0, t_live1;  // same for the live wave pass
+    unsigned long long t_push0;         // first item published to the live pass
 };
 
 // Key of an unused hit slot: sorts after every real (column, text end) key.

@@ -32,6 +32,7 @@
 #include "row_update.h"
 #include "level_kernels.h"
 #include "chain_kernels.h"
+#include "mlp_internal.h"
 
 namespace alae {
 
@@ -328,6 +329,25 @@ static alae_status grow_pair(uint64_t *&keys, uint32_t *&vals, uint64_t &cap, ui
 
 using namespace alae;
 
+struct QueueBufs {
+    float *feat = nullptr;
+    uint64_t feat_cap = 0;
+    float *pred = nullptr;
+    uint64_t pred_cap = 0;
+    float *twork = nullptr;
+    uint64_t twork_cap = 0;
+    uint64_t *okeys = nullptr;
+    uint32_t *ovals = nullptr;
+    uint64_t o_cap = 0;
+    uint64_t *okeys_alt = nullptr;
+    uint32_t *ovals_alt = nullptr;
+    uint64_t o_alt_cap = 0;
+    uint32_t *part = nullptr;  // partition: heavy flags, positions, entry counts, entry positions
+    uint64_t part_cap = 0;
+    uint32_t *scratch = nullptr;
+    uint64_t scratch_cap = 0;
+};
+
 struct alae_workspace {
     const alae_index *idx = nullptr;
     int device = 0;
@@ -395,6 +415,19 @@ struct alae_workspace {
     Entry *rowbuf = nullptr;
     uint64_t rowbuf_cap = 0;
     uint64_t wrow_cap = 0;
+    // learned ordering, partition and traces of the walkers' queues (one set
+    // per queue that can be in flight at once)
+    QueueBufs qb[2];
+    uint32_t *wsrc = nullptr;  // lane-queue origin of promoted wave-queue items (traces)
+    uint64_t wsrc_cap = 0;
+    uint32_t *ready = nullptr;  // publication flags of wave-queue slots (live pass)
+    uint64_t ready_cap = 0;
+    uint32_t *missed = nullptr;  // items the live pass gave up
+    uint64_t missed_cap = 0;
+    uint32_t *left = nullptr;  // items of the pass after it
+    uint64_t left_cap = 0;
+    hipStream_t s2 = nullptr;  // the concurrent wave-walker pass
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     // batch segments
     uint32_t *qord = nullptr;
     uint64_t qord_cap = 0;
@@ -450,6 +483,25 @@ static void ws_release(alae_workspace *ws) {
     hipFree(ws->wnodes);
     hipFree(ws->wents);
     hipFree(ws->rowbuf);
+    for (int i = 0; i < 2; ++i) {
+        QueueBufs &q = ws->qb[i];
+        hipFree(q.feat);
+        hipFree(q.pred);
+        hipFree(q.twork);
+        hipFree(q.okeys);
+        hipFree(q.ovals);
+        hipFree(q.okeys_alt);
+        hipFree(q.ovals_alt);
+        hipFree(q.part);
+        hipFree(q.scratch);
+    }
+    hipFree(ws->wsrc);
+    hipFree(ws->ready);
+    hipFree(ws->missed);
+    hipFree(ws->left);
+    if (ws->s2) hipStreamDestroy(ws->s2);
+    if (ws->ev_fork) hipEventDestroy(ws->ev_fork);
+    if (ws->ev_join) hipEventDestroy(ws->ev_join);
     hipFree(ws->qord);
     hipFree(ws->segbeg);
     hipFree(ws->d_off);
@@ -538,6 +590,73 @@ static int bit_length(uint64_t v) {
         v >>= 1;
     }
     return b;
+}
+
+__global__ void k_fill_u32(uint32_t *p, uint32_t v, uint64_t n) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ void k_zero_f32(float *p, uint64_t n) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0.f;
+}
+
+// Before a walker drains a queue of n items: features (for a model or a
+// trace), predictions, the order by predicted work (largest first) and a
+// zeroed work record.  Buffers come from qb; everything runs on stream s.
+struct QueuePrep {
+    const float *pred = nullptr;
+    const uint32_t *order = nullptr;
+    float *twork = nullptr;
+};
+
+static alae_status prepare_queue(QueueBufs &q, const SearchArgs &a, const Node *items, const Entry *ents, uint64_t n,
+                                 float queue, const alae_mlp *model, bool want_order, bool trace, hipStream_t s,
+                                 QueuePrep &out) {
+    out = QueuePrep();
+    if (n == 0 || (!model && !trace)) return ALAE_OK;
+    alae_status st;
+    if ((st = grow(q.feat, q.feat_cap, n * ALAE_MLP_FEATURES, false, 0, s)) != ALAE_OK) return st;
+    const uint32_t blocks = (uint32_t)((n + 255) / 256);
+    k_item_features<<<blocks, 256, 0, s>>>(a, items, (uint32_t)n, ents, queue, q.feat);
+    HIP_TRY(hipGetLastError());
+    if (trace) {
+        if ((st = grow(q.twork, q.twork_cap, n, false, 0, s)) != ALAE_OK) return st;
+        k_zero_f32<<<blocks, 256, 0, s>>>(q.twork, n);
+        out.twork = q.twork;
+    }
+    if (model) {
+        if ((st = grow(q.pred, q.pred_cap, n, false, 0, s)) != ALAE_OK) return st;
+        if ((st = mlp_predict_device(model, q.feat, (uint32_t)n, q.pred, s)) != ALAE_OK) return st;
+        out.pred = q.pred;
+    }
+    if (model && want_order) {
+        if ((st = grow_pair(q.okeys, q.ovals, q.o_cap, n, 0, s)) != ALAE_OK) return st;
+        if ((st = grow_pair(q.okeys_alt, q.ovals_alt, q.o_alt_cap, n, 0, s)) != ALAE_OK) return st;
+        if ((st = grow(q.scratch, q.scratch_cap, radix_scratch_words(n), false, 0, s)) != ALAE_OK) return st;
+        k_order_keys<<<blocks, 256, 0, s>>>(q.pred, (uint32_t)n, q.okeys, q.ovals);
+        bool in_alt = false;
+        HIP_TRY(radix_sort_pairs(q.okeys, q.ovals, q.okeys_alt, q.ovals_alt, n, 32, q.scratch, &in_alt, s));
+        out.order = in_alt ? q.ovals_alt : q.ovals;
+    }
+    return ALAE_OK;
+}
+
+// Append a drained queue's (features, work) to the caller's trace.
+static alae_status record_trace(const QueueBufs &q, uint64_t n, alae_trace *tr, hipStream_t s) {
+    if (!tr || n == 0) return ALAE_OK;
+    const uint64_t room = tr->capacity > tr->count ? tr->capacity - tr->count : 0;
+    const uint64_t take = std::min<uint64_t>(room, n);
+    if (take && tr->features && tr->work) {
+        HIP_TRY(hipMemcpyAsync(tr->features + tr->count * ALAE_MLP_FEATURES, q.feat,
+                               take * ALAE_MLP_FEATURES * sizeof(float), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(tr->work + tr->count, q.twork, take * sizeof(float), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        tr->count += take;
+    }
+    tr->total += n;
+    return ALAE_OK;
 }
 
 // Batches are at most this many queries (their ordinals are folded into the
@@ -850,8 +969,10 @@ static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64
         if ((c.overflow & kOvWideEntries) &&
             (g = grow(ws->wents, ws->went_cap, c.wentries, true, keep.wentries, s)))
             return g;
-        if ((c.overflow & kOvSpillNodes) && (g = grow(ws->onodes, ws->onode_cap, c.onodes, false, 0, s))) return g;
-        if ((c.overflow & kOvSpillEntries) && (g = grow(ws->oents, ws->oent_cap, c.oentries, false, 0, s)))
+        if ((c.overflow & kOvSpillNodes) && (g = grow(ws->onodes, ws->onode_cap, c.onodes, true, keep.onodes, s)))
+            return g;
+        if ((c.overflow & kOvSpillEntries) &&
+            (g = grow(ws->oents, ws->oent_cap, c.oentries, true, keep.oentries, s)))
             return g;
         if ((c.overflow & kOvHits) && (g = grow_pair(ws->hkeys, ws->hscores, ws->hit_cap, c.hits, keep.hits, s)))
             return g;
@@ -942,20 +1063,130 @@ static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64
         if (nn || nlw || nc) max_depth = (uint64_t)d1;
     }
 
-    // chains with gap states: one lane each
+    const alae_mlp *model = opts ? opts->order_model : nullptr;
+    const int order_queues = (opts && opts->order_queues) ? opts->order_queues : 2;
+    // predicted log2(1 + work) at which a lane-queue chain joins the first wave pass
+    const float part_thresh = (!opts || opts->partition_threshold <= 0.f) ? -3.0e38f : opts->partition_threshold;
+    uint64_t partitioned = 0, leftover = 0;
+    alae_trace *trace_out = opts ? opts->trace : nullptr;
+    if (trace_out) trace_out->count = trace_out->total = 0;
+    if (model && model->device != ws->device) {
+        set_error("the ordering model lives on device %d, the search on device %d", model->device, ws->device);
+        return ALAE_E_ARG;
+    }
+    // ---- chains ----------------------------------------------------------------
+    // The lane walker (chains with gap states) and a first pass of the wave
+    // walker (chains already too wide for a lane, plus lane-queue chains the
+    // work predictor marks heavy) run concurrently on two streams; a second
+    // wave pass then takes the chains the lane walker promoted.
     const uint64_t ng = ws->h_cnt->gnodes;
-    if (ng > 0) {
+    const bool tracing = trace_out != nullptr;
+    double order_ms = 0.0;
+    HIP_TRY(hipEventRecord(ws->evk0, s));
+    QueuePrep gq;
+    if ((st = prepare_queue(ws->qb[0], a, ws->gnodes, ws->gents, ng, 0.f, model, (order_queues & 1) != 0, tracing,
+                            s, gq)) != ALAE_OK)
+        return st;
+    uint64_t moved = 0;
+    if (gq.pred && part_thresh > -1e30f && ng > 0) {
+        // partition: heavy lane-queue chains go to the first wave pass
+        QueueBufs &q = ws->qb[0];
+        const uint64_t n1 = ng + 1;
+        if ((st = grow(q.part, q.part_cap, 4 * n1, false, 0, s)) != ALAE_OK) return st;
+        if ((st = grow(q.scratch, q.scratch_cap, scan_scratch_words(n1), false, 0, s)) != ALAE_OK) return st;
+        uint32_t *heavy = q.part, *hpos = q.part + n1, *ent = q.part + 2 * n1, *epos = q.part + 3 * n1;
+        k_partition_flags<<<(uint32_t)((n1 + 255) / 256), 256, 0, s>>>(gq.pred, ws->gnodes, (uint32_t)ng,
+                                                                        part_thresh, heavy, ent);
+        HIP_TRY(scan_exclusive_u32(heavy, hpos, n1, q.scratch, s));
+        HIP_TRY(scan_exclusive_u32(ent, epos, n1, q.scratch, s));
+        uint32_t tot[2] = {0, 0};
+        HIP_TRY(hipMemcpyAsync(&tot[0], hpos + ng, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(&tot[1], epos + ng, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (tot[0] > 0) {
+            Counters c = *ws->h_cnt;
+            if ((st = grow(ws->wnodes, ws->wnode_cap, c.wnodes + tot[0], true, c.wnodes, s)) != ALAE_OK) return st;
+            if ((st = grow(ws->wents, ws->went_cap, c.wentries + tot[1], true, c.wentries, s)) != ALAE_OK) return st;
+            k_partition_move<<<(uint32_t)((ng + 255) / 256), 256, 0, s>>>(a, ws->gnodes, ws->gents, (uint32_t)ng,
+                                                                           heavy, hpos, epos, ws->wnodes, ws->wents,
+                                                                           (uint32_t)c.wnodes, (uint32_t)c.wentries,
+                                                                           ws->d_cnt);
+            HIP_TRY(hipGetLastError());
+            c.wnodes += tot[0];
+            c.wentries += tot[1];
+            *ws->h_cnt = c;
+            HIP_TRY(hipMemcpyAsync(ws->d_cnt, ws->h_cnt, sizeof(Counters), hipMemcpyHostToDevice, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            moved = tot[0];
+        }
+    }
+    // Wave-walker queue: items 0 .. nw1-1 are queued now; the lane walker
+    // appends the chains it hands over.  A live pass on the second stream
+    // takes items as they are published, concurrently with the lane walker.
+    const uint64_t nw1 = ws->h_cnt->wnodes;
+    QueuePrep wq;
+    if ((st = prepare_queue(ws->qb[1], a, ws->wnodes, ws->wents, nw1, 1.f, model, (order_queues & 2) != 0, false, s,
+                            wq)) != ALAE_OK)
+        return st;
+    if (model || tracing) {
+        HIP_TRY(hipEventRecord(ws->evk1, s));
+        HIP_TRY(hipEventSynchronize(ws->evk1));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, ws->evk0, ws->evk1));
+        order_ms = ms;
+    }
+    const uint32_t live_blocks = (uint32_t)cus * 2u;
+    if (ng > 0 || nw1 > 0) {
         const Counters before = *ws->h_cnt;
         for (;;) {
             Counters z = before;
             z.general_head = 0;
+            z.wide_head = 0;
+            z.gen_done = 0;
+            z.missed = 0;
+            z.t_gen0 = z.t_live0 = z.t_push0 = ~0ull;
+            z.t_gen1 = z.t_live1 = 0;
             z.overflow = 0;
+            if (tracing && ng > 0) {
+                if ((st = grow(ws->wsrc, ws->wsrc_cap, ws->wnode_cap, false, 0, s)) != ALAE_OK) return st;
+                k_fill_u32<<<(uint32_t)((ws->wnode_cap + 255) / 256), 256, 0, s>>>(ws->wsrc, 0xFFFFFFFFu,
+                                                                                 ws->wnode_cap);
+            }
+            if (tracing) {
+                if ((st = grow(ws->qb[1].twork, ws->qb[1].twork_cap, ws->wnode_cap, false, 0, s)) != ALAE_OK)
+                    return st;
+                k_zero_f32<<<(uint32_t)((ws->wnode_cap + 255) / 256), 256, 0, s>>>(ws->qb[1].twork, ws->wnode_cap);
+            }
+            if ((st = grow(ws->ready, ws->ready_cap, ws->wnode_cap, false, 0, s)) != ALAE_OK) return st;
+            if ((st = grow(ws->missed, ws->missed_cap, live_blocks, false, 0, s)) != ALAE_OK) return st;
+            k_fill_u32<<<(uint32_t)((nw1 + 255) / 256 + 1), 256, 0, s>>>(ws->ready, 1u, nw1);
+            k_fill_u32<<<(uint32_t)((ws->wnode_cap - nw1 + 255) / 256 + 1), 256, 0, s>>>(ws->ready + nw1, 0u,
+                                                                                      ws->wnode_cap - nw1);
             HIP_TRY(hipMemcpyAsync(ws->d_cnt, &z, sizeof(Counters), hipMemcpyHostToDevice, s));
             set_caps(cur);
             const uint32_t waves = (uint32_t)std::min<uint64_t>((ng + 63) / 64, max_waves);
+            const uint32_t gblocks = (waves + 3) / 4;
+            LiveQueue lq;
+            lq.ready = ws->ready;
+            lq.nstatic = (uint32_t)nw1;
+            lq.gen_waves = ng > 0 ? gblocks * 4u : 0u;
+            lq.missed = ws->missed;
+            lq.patience = 20000000;  // 200 ms of the 100 MHz clock without any progress
             HIP_TRY(hipEventRecord(ws->evk0, s));
-            k_chain_general<<<(waves + 3) / 4, 256, 0, s>>>(a, ws->gnodes, (uint32_t)ng, ws->gents, ws->wnodes,
-                                                            ws->wents, ws->hkeys, ws->hscores, caps, ws->d_cnt);
+            // the second stream waits for the set-up above, not for the lane walker
+            HIP_TRY(hipEventRecord(ws->ev_fork, s));
+            HIP_TRY(hipStreamWaitEvent(ws->s2, ws->ev_fork, 0));
+            if (ng > 0)
+                k_chain_general<<<gblocks, 256, 0, s>>>(a, ws->gnodes, (uint32_t)ng, ws->gents, ws->wnodes, ws->wents,
+                                                        ws->hkeys, ws->hscores, caps, ws->d_cnt, gq.order, gq.twork,
+                                                        tracing ? ws->wsrc : nullptr, ws->ready);
+            HIP_TRY(hipGetLastError());
+            k_chain_wide_lds<<<live_blocks, 64, 0, ws->s2>>>(a, ws->wnodes, 0, 0xFFFFFFFFu, ws->wents, ws->onodes,
+                                                             ws->oents, ws->hkeys, ws->hscores, caps, ws->d_cnt,
+                                                             wq.order, tracing ? ws->qb[1].twork : nullptr, lq);
+            HIP_TRY(hipGetLastError());
+            HIP_TRY(hipEventRecord(ws->ev_join, ws->s2));
+            HIP_TRY(hipStreamWaitEvent(s, ws->ev_join, 0));
             if ((st = timed(general_ms)) != ALAE_OK) return st;
             const Counters &c = *ws->h_cnt;
             if (!c.overflow) break;
@@ -963,28 +1194,71 @@ static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64
             if ((st = grow_overflowed(c, before, cur)) != ALAE_OK) return st;
         }
     }
-    // chains whose rows are too wide for a lane: one wave each, rows in LDS
-    const uint64_t nw = ws->h_cnt->wnodes;
-    if (nw > 0) {
-        const Counters before = *ws->h_cnt;
-        const uint32_t blocks = (uint32_t)std::min<uint64_t>(nw, (uint64_t)cus * 24u);
-        for (;;) {
-            Counters z = before;
-            z.wide_head = 0;
-            z.onodes = z.oentries = 0;
-            z.overflow = 0;
-            HIP_TRY(hipMemcpyAsync(ws->d_cnt, &z, sizeof(Counters), hipMemcpyHostToDevice, s));
-            set_caps(cur);
-            HIP_TRY(hipEventRecord(ws->evk0, s));
-            k_chain_wide_lds<<<blocks, 64, 0, s>>>(a, ws->wnodes, (uint32_t)nw, ws->wents, ws->onodes, ws->oents,
-                                                   ws->hkeys, ws->hscores, caps, ws->d_cnt);
-            if ((st = timed(wide_ms)) != ALAE_OK) return st;
-            const Counters &c = *ws->h_cnt;
-            if (!c.overflow) break;
-            ++retries;
-            if ((st = grow_overflowed(c, before, cur)) != ALAE_OK) return st;
+    // items the live pass did not take: given-up claims, then the unclaimed tail
+    {
+        const Counters c0 = *ws->h_cnt;
+        if (trace && (ng > 0 || nw1 > 0)) {
+            const double t0 = (double)std::min(c0.t_gen0, c0.t_live0);
+            fprintf(stderr,
+                    "[alae] chains: lane walker %.3f-%.3f ms, live wave pass %.3f-%.3f ms, first push %.3f ms, "
+                    "missed %llu, pushed %llu (static %llu)\n",
+                    (c0.t_gen0 - t0) * 1e-5, (c0.t_gen1 - t0) * 1e-5, (c0.t_live0 - t0) * 1e-5,
+                    (c0.t_live1 - t0) * 1e-5, c0.t_push0 == ~0ull ? -1.0 : (c0.t_push0 - t0) * 1e-5,
+                    (unsigned long long)c0.missed, (unsigned long long)c0.wnodes, (unsigned long long)nw1);
         }
+        const uint64_t made = c0.wnodes;
+        const uint64_t head = std::min<uint64_t>(c0.wide_head, made);
+        // given-up claims past the last pushed item name no item
+        std::vector<uint32_t> miss(std::min<uint64_t>(c0.missed, live_blocks));
+        if (!miss.empty()) {
+            HIP_TRY(hipMemcpyAsync(miss.data(), ws->missed, miss.size() * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+        }
+        std::vector<uint32_t> lst;
+        for (uint32_t v : miss)
+            if (v < made) lst.push_back(v);
+        for (uint64_t i = head; i < made; ++i) lst.push_back((uint32_t)i);
+        const uint64_t nleft = lst.size();
+        if (nleft > 0) {
+            if ((st = grow(ws->left, ws->left_cap, nleft, false, 0, s)) != ALAE_OK) return st;
+            HIP_TRY(hipMemcpyAsync(ws->left, lst.data(), nleft * sizeof(uint32_t), hipMemcpyHostToDevice, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            const Counters before = *ws->h_cnt;
+            const uint32_t blocks = (uint32_t)std::min<uint64_t>(nleft, (uint64_t)cus * 24u);
+            LiveQueue none;
+            memset(&none, 0, sizeof(none));
+            for (;;) {
+                Counters z = before;
+                z.wide_head = 0;
+                z.overflow = 0;
+                HIP_TRY(hipMemcpyAsync(ws->d_cnt, &z, sizeof(Counters), hipMemcpyHostToDevice, s));
+                set_caps(cur);
+                HIP_TRY(hipEventRecord(ws->evk0, s));
+                k_chain_wide_lds<<<blocks, 64, 0, s>>>(a, ws->wnodes, 0, (uint32_t)nleft, ws->wents, ws->onodes,
+                                                       ws->oents, ws->hkeys, ws->hscores, caps, ws->d_cnt, ws->left,
+                                                       tracing ? ws->qb[1].twork : nullptr, none);
+                if ((st = timed(wide_ms)) != ALAE_OK) return st;
+                const Counters &c = *ws->h_cnt;
+                if (!c.overflow) break;
+                ++retries;
+                if ((st = grow_overflowed(c, before, cur)) != ALAE_OK) return st;
+            }
+        }
+        leftover = nleft;
+        if (tracing && made > 0) {
+            QueueBufs &q = ws->qb[1];
+            if ((st = grow(q.feat, q.feat_cap, made * ALAE_MLP_FEATURES, false, 0, s)) != ALAE_OK) return st;
+            k_item_features<<<(uint32_t)((made + 255) / 256), 256, 0, s>>>(a, ws->wnodes, (uint32_t)made, ws->wents,
+                                                                            1.f, q.feat);
+            if (ng > 0)
+                k_link_work<<<(uint32_t)((made + 255) / 256), 256, 0, s>>>(ws->wsrc, 0, (uint32_t)made, q.twork,
+                                                                            ws->qb[0].twork, (uint32_t)ng);
+            HIP_TRY(hipGetLastError());
+            if ((st = record_trace(q, made, trace_out, s)) != ALAE_OK) return st;
+        }
+        if ((st = record_trace(ws->qb[0], ng, trace_out, s)) != ALAE_OK) return st;
     }
+    partitioned = moved;
     // rows that outgrew LDS: one wave each, rows in global memory
     const uint64_t no = ws->h_cnt->onodes;
     if (no > 0) {
@@ -1094,6 +1368,9 @@ static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64
         o->dominated_gapped = c.st_dominated_gapped;
         o->chain_bytes = c.st_chain_bytes;
         o->merge_ms = merge_ms;
+        o->partitioned = partitioned;
+        o->order_ms = order_ms;
+        o->leftover = leftover;
         o->reused = c.st_reused;
         o->replay_chains = c.st_replay;
     }
@@ -1125,6 +1402,9 @@ alae_status alae_workspace_create(const alae_index *index, alae_workspace **out)
     HIP_TRY(hipEventCreate(&ws->ev1));
     HIP_TRY(hipEventCreate(&ws->evk0));
     HIP_TRY(hipEventCreate(&ws->evk1));
+    HIP_TRY(hipEventCreateWithFlags(&ws->ev_fork, hipEventDisableTiming));
+    HIP_TRY(hipEventCreateWithFlags(&ws->ev_join, hipEventDisableTiming));
+    HIP_TRY(hipStreamCreateWithFlags(&ws->s2, hipStreamNonBlocking));
     *out = ws.release();
     return ALAE_OK;
 }
