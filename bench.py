@@ -82,6 +82,93 @@ def cpu_baseline(w, budget_s: float):
                       f"host has {cores} cores"}
 
 
+def learned_scheduling(alae, ws, dq, H, sc, steps, plain_ms):
+    """Trace one search, train the work predictor on the GPU, then time the
+    search with the learned order + partition of the walkers' queues."""
+    import torch
+
+    t0 = time.perf_counter()
+    tr = alae.Trace(1 << 23)
+    ws.search_device(dq, H, sc, trace=tr)
+    X, W = tr.arrays()
+    y = np.log2(1.0 + W)
+    rng = np.random.default_rng(0)
+    perm = rng.permutation(len(y))
+    ntr = int(0.8 * len(y))
+    wide = np.where(X[perm[:ntr], 7] == 1)[0]
+    sel = np.concatenate([perm[:ntr], np.repeat(perm[:ntr][wide], 50)])  # the wave queue is 1000x smaller
+    net = alae.MLP(seed=1)
+    t1 = time.perf_counter()
+    loss = net.train(X[sel], y[sel], epochs=8, batch=4096, lr=2e-3)
+    train_s = time.perf_counter() - t1
+    pred = net.predict(X[perm[ntr:]])
+    from scipy.stats import spearmanr
+
+    rho = float(spearmanr(pred, y[perm[ntr:]]).correlation)
+    out = {"trace_items": int(tr.count), "train_samples": int(len(sel)), "train_s": train_s, "train_loss": loss,
+           "heldout_spearman": rho, "plain_ms": plain_ms}
+    for name, kw in (("order_ms", dict(order_model=net, order_queues=2)),
+                     ("order_partition_ms", dict(order_model=net, order_queues=2, partition_threshold=9.0))):
+        times = []
+        for _ in range(steps):
+            st = alae.Stats()
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            ws.search_device(dq, H, sc, stats=st, **kw)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t2)
+        out[name] = float(np.mean(times) * 1e3)
+        out[name.replace("_ms", "_moved")] = int(st.partitioned)
+    out["gain_order"] = plain_ms / out["order_ms"]
+    out["gain_order_partition"] = plain_ms / out["order_partition_ms"]
+    out["total_s"] = time.perf_counter() - t0
+    net.free()
+    return out
+
+
+def batched_vs_single(alae, k=64, n=100_000_000):
+    """The batched workload's shape on a smaller text: k independent DNA queries
+    (log-uniform lengths 500-50,000), each with 20 planted mutated segments
+    (200-2,000, 15% substitutions, 2% indels) in an i.i.d. text of n bases.
+    One batched search against k single-query searches on one workspace."""
+    import torch
+
+    from paper_1208_0274_amd import synth
+
+    w = synth.config4(n=n, k=k)
+    qs = w["queries"]
+    t0 = time.perf_counter()
+    idx = alae.Index.build(w["text"], "dna")
+    build_s = time.perf_counter() - t0
+    sc = alae.make_scoring(w["sa"], w["sb"], w["sg"], w["ss"])
+    ws = alae.Workspace(idx)
+    lens = [q.shape[0] for q in qs]
+    cat = torch.from_numpy(np.concatenate(qs)).to("cuda")
+    dqs = [torch.from_numpy(np.ascontiguousarray(q)).to("cuda") for q in qs]
+    ws.search_device_batch(cat, lens, w["H"], sc)  # warm-up
+    for d in dqs[:4]:
+        ws.search_device(d, w["H"], sc)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    nb = ws.search_device_batch(cat, lens, w["H"], sc)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    ns = 0
+    for d in dqs:
+        ns += ws.search_device(d, w["H"], sc)
+    torch.cuda.synchronize()
+    tsing = time.perf_counter() - t0
+    ws.free()
+    idx.free()
+    if nb != ns:
+        raise SystemExit(f"batched hits {nb} != single-query hits {ns}")
+    return {"workload": f"{k} queries, log-uniform 500-50,000, 20 planted copies each, text {n:.0e}",
+            "queries": k, "sum_m": int(sum(lens)), "index_build_s": build_s, "batched_ms": tb * 1e3,
+            "single_ms": tsing * 1e3, "speedup": tsing / tb, "hits": int(nb),
+            "batched_cells_per_s": float(sum(lens)) * n / tb}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -89,6 +176,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the learned-scheduling and batching legs")
     ap.add_argument("--cpu-seconds", type=float, default=30.0)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -161,6 +249,11 @@ def main():
                      "alg_bytes_per_launch": alg_bytes / launches, "avg_launch_ms": level_ms / launches,
                      "launches_per_step": int(st.level_launches)},
     }
+    if not args.no_extras:
+        log("learned scheduling: trace, train, timed searches")
+        out["learned_scheduling"] = learned_scheduling(alae, ws, dq, H, sc, args.steps, ms)
+        log("batched search against single-query searches")
+        out["batched"] = batched_vs_single(alae)
     if not args.no_cpu:
         log("timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
