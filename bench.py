@@ -169,6 +169,47 @@ def batched_vs_single(alae, k=64, n=100_000_000):
             "batched_cells_per_s": float(sum(lens)) * n / tb}
 
 
+def serving(alae, idx, T, rates=(10.0, 100.0, 1000.0), count=48):
+    """Poisson arrivals of queries with log-uniform lengths 100-100,000 (half
+    carrying a mutated 200-2,000 text segment) against the resident index;
+    per rate: completed requests per second and submit-to-completion p50/p99."""
+    import threading
+
+    from paper_1208_0274_amd import synth
+
+    sc = alae.make_scoring()
+    out = []
+    srv = alae.Server(idx, slots=4, max_batch=16)
+    qs = synth.serving_queries(T, count)
+    for rate in rates:
+        arrivals = synth.poisson_arrivals(rate, count)
+        srv.reset_stats()
+        ids = [None] * count
+
+        def client():
+            t0 = time.perf_counter()
+            for k, t in enumerate(arrivals):
+                d = t - (time.perf_counter() - t0)
+                if d > 0:
+                    time.sleep(d)
+                ids[k] = srv.submit(qs[k], 30, sc)
+
+        th = threading.Thread(target=client)
+        t0 = time.perf_counter()
+        th.start()
+        th.join()
+        for i in ids:
+            srv.poll(i)
+        wall = time.perf_counter() - t0
+        st = srv.stats()
+        out.append({"rate_qps": rate, "requests": count, "throughput_qps": count / wall, "p50_ms": st["p50_ms"],
+                    "p99_ms": st["p99_ms"], "mean_batch": st["mean_batch"], "searches": st["batches"],
+                    "mean_m": float(np.mean([q.shape[0] for q in qs]))})
+        log(f"serving at {rate} q/s: {out[-1]}")
+    srv.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -252,6 +293,8 @@ def main():
     if not args.no_extras:
         log("learned scheduling: trace, train, timed searches")
         out["learned_scheduling"] = learned_scheduling(alae, ws, dq, H, sc, args.steps, ms)
+        log("serving: Poisson arrivals")
+        out["serving"] = serving(alae, idx, T)
         log("batched search against single-query searches")
         out["batched"] = batched_vs_single(alae)
     if not args.no_cpu:

@@ -297,25 +297,47 @@ alae_status alae_workspace_result(const alae_workspace *ws, const uint64_t **d_k
 alae_status alae_workspace_copy_result(const alae_workspace *ws, uint64_t *d_keys, int32_t *d_scores, void *stream);
 
 /*
- * Serving: a request loop that keeps the index resident, admits requests by
- * the device memory their rows need, runs admitted requests together and
- * retires each as soon as it is done.  submit copies the query and returns
- * an id; poll returns ALAE_OK with the result once the request is complete
- * (wait != 0 blocks), ALAE_E_BUSY-like ALAE_E_NOT_FOUND for an unknown id,
- * and ALAE_E_ADMISSION if the request can never fit the budget.
+ * Serving with continuous batching.  The server keeps the index resident and
+ * runs max_inflight slots (a workspace, a HIP stream and a worker thread
+ * each) at once, so the kernels of different requests overlap on the device.
+ * A request is admitted when a slot is free and the device-memory budget has
+ * room for its estimated rows (64 rows of m 20-byte entries plus the
+ * profile); requests are admitted in arrival order, and a slot takes the head
+ * of the queue together with the requests right behind it that share its
+ * scoring and threshold (up to max_batch requests and 2^20 query columns),
+ * running them as one batched search.  Every request's result is exactly
+ * what alae_search returns for it alone.
+ *   submit: copies the query; *req_id identifies it.  ALAE_E_ADMISSION if
+ *           its estimate exceeds the whole budget (it could never run).
+ *   poll:   ALAE_OK with the result (library-allocated, free with
+ *           alae_hits_free) once done; with wait == 0 a pending request
+ *           gives ALAE_OK and out->count == SIZE_MAX; ALAE_E_NOT_FOUND for
+ *           an unknown or already collected id; a failed search returns
+ *           its own status.
+ *   get_stats: counts and latency percentiles (submit to completion) of the
+ *           requests completed since creation or the last reset_stats.
+ * destroy waits for the requests already admitted and drops the rest.
  */
 typedef struct {
-    uint64_t memory_budget;    /* device bytes for in-flight rows, 0 = automatic */
-    int32_t max_inflight;      /* requests on the device at once, 0 = automatic  */
-    int32_t reserved;
+    uint64_t memory_budget;    /* device bytes for in-flight rows, 0 = half the free memory */
+    int32_t max_inflight;      /* slots running at once (1..16), 0 = 4                      */
+    int32_t max_batch;         /* requests per batched search, 0 = 16                       */
 } alae_server_opts;
+
+typedef struct {
+    uint64_t submitted, completed, rejected, queued;
+    uint64_t batches;          /* searches run (a batch counts once)                 */
+    double mean_batch;         /* requests per search                                */
+    double p50_ms, p99_ms, mean_ms, max_ms;  /* submit-to-completion latency        */
+    double span_s;             /* first submit to last completion                    */
+} alae_server_stats;
 
 alae_status alae_server_create(const alae_index *index, const alae_server_opts *opts, alae_server **out);
 alae_status alae_server_submit(alae_server *srv, const char *query, size_t m, const alae_scoring *scoring,
                                int32_t H, uint64_t *req_id);
-/* Returns ALAE_OK and fills *out when done; ALAE_E_BUSY is not used: a pending
- * request with wait == 0 returns ALAE_OK with out->count == SIZE_MAX. */
 alae_status alae_server_poll(alae_server *srv, uint64_t req_id, int wait, alae_hits *out);
+alae_status alae_server_get_stats(alae_server *srv, alae_server_stats *out);
+void alae_server_reset_stats(alae_server *srv);
 void alae_server_destroy(alae_server *srv);
 
 /*

@@ -147,6 +147,24 @@ _sig("alae_search_device", _st, _vp, _vp, ctypes.c_size_t, ctypes.POINTER(Scorin
 _sig("alae_search_device_batch", _st, _vp, _vp, ctypes.POINTER(ctypes.c_size_t), ctypes.c_size_t,
      ctypes.POINTER(Scoring), ctypes.c_int32, ctypes.POINTER(SearchOpts), _vp, ctypes.POINTER(ctypes.c_size_t))
 _sig("alae_workspace_batch_offsets", _st, _vp, ctypes.POINTER(ctypes.c_size_t), ctypes.c_size_t)
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("memory_budget", ctypes.c_uint64), ("max_inflight", ctypes.c_int32), ("max_batch", ctypes.c_int32)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64), ("rejected", ctypes.c_uint64),
+                ("queued", ctypes.c_uint64), ("batches", ctypes.c_uint64), ("mean_batch", ctypes.c_double),
+                ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double), ("mean_ms", ctypes.c_double),
+                ("max_ms", ctypes.c_double), ("span_s", ctypes.c_double)]
+
+
+_sig("alae_server_create", _st, _vp, ctypes.POINTER(ServerOpts), ctypes.POINTER(_vp))
+_sig("alae_server_submit", _st, _vp, ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(Scoring), ctypes.c_int32,
+     ctypes.POINTER(ctypes.c_uint64))
+_sig("alae_server_poll", _st, _vp, ctypes.c_uint64, ctypes.c_int, ctypes.POINTER(Hits))
+_sig("alae_server_get_stats", _st, _vp, ctypes.POINTER(ServerStats))
+_sig("alae_server_reset_stats", None, _vp)
+_sig("alae_server_destroy", None, _vp)
 _fp = ctypes.POINTER(ctypes.c_float)
 _sig("alae_mlp_create", _st, ctypes.c_int, ctypes.c_uint64, ctypes.POINTER(_vp))
 _sig("alae_mlp_free", None, _vp)
@@ -485,5 +503,55 @@ class MLP:
     def __del__(self):
         try:
             self.free()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous-batching request loop over a resident index."""
+
+    def __init__(self, index: Index, memory_budget: int = 0, slots: int = 0, max_batch: int = 0):
+        self.index = index
+        o = ServerOpts()
+        o.memory_budget, o.max_inflight, o.max_batch = int(memory_budget), int(slots), int(max_batch)
+        self._h = _vp()
+        _check(_lib.alae_server_create(index._h, ctypes.byref(o), ctypes.byref(self._h)), "alae_server_create")
+        self._scorings = {}
+
+    def submit(self, query, H: int, scoring: Scoring | None = None) -> int:
+        sc = scoring if scoring is not None else make_scoring()
+        q = _query_bytes(query, self.index.alphabet)
+        rid = ctypes.c_uint64()
+        _check(_lib.alae_server_submit(self._h, q, len(q), ctypes.byref(sc), int(H), ctypes.byref(rid)),
+               "alae_server_submit")
+        return int(rid.value)
+
+    def poll(self, rid: int, wait: bool = True):
+        """The result as (query_end, text_end, score), or None while pending (wait=False)."""
+        h = Hits()
+        _check(_lib.alae_server_poll(self._h, int(rid), 1 if wait else 0, ctypes.byref(h)), "alae_server_poll")
+        if h.count == ctypes.c_size_t(-1).value:
+            return None
+        try:
+            return _hits_to_numpy(h)
+        finally:
+            _lib.alae_hits_free(ctypes.byref(h))
+
+    def stats(self) -> dict:
+        s = ServerStats()
+        _check(_lib.alae_server_get_stats(self._h, ctypes.byref(s)), "alae_server_get_stats")
+        return {k: getattr(s, k) for k, _ in s._fields_}
+
+    def reset_stats(self):
+        _lib.alae_server_reset_stats(self._h)
+
+    def close(self):
+        if self._h:
+            _lib.alae_server_destroy(self._h)
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
         except Exception:
             pass

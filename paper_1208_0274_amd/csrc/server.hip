@@ -1,11 +1,16 @@
-// Request loop that keeps the index resident on the device.
+// Request loop with continuous batching over a resident index.
 //
-// Requests are admitted by the device memory their frontier rows are
-// expected to need (a bound from the query length), queued, and run by a
-// worker thread on one workspace; each request retires as soon as its result
-// is on the host.  Polling returns the result and releases it.
+// Several slots (a workspace, a stream and a worker thread each) run searches
+// at the same time, so the kernels of different requests overlap on the
+// device.  A free slot admits the requests at the head of the queue while the
+// device-memory budget allows: consecutive requests with the same scoring and
+// threshold are taken together and run as one batched search (their queries
+// end to end, split again afterwards), so requests that arrive while others
+// are on the device join the next batch as soon as a slot and memory free up.
+// Each request retires as soon as its own batch is done.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <condition_variable>
 #include <cstdlib>
@@ -27,12 +32,16 @@ using namespace alae;
 
 namespace {
 
+using Clock = std::chrono::steady_clock;
+
 struct Request {
     uint64_t id = 0;
     std::vector<uint8_t> codes;
     alae_scoring scoring{};
     std::vector<int8_t> matrix;
     int32_t H = 0;
+    uint64_t need = 0;  // admission estimate (device bytes)
+    Clock::time_point t_submit;
     bool done = false;
     alae_status status = ALAE_OK;
     alae_hits result{};
@@ -40,21 +49,36 @@ struct Request {
 };
 
 // Device bytes a request's search is expected to hold at its widest level:
-// entries of about 20 bytes for a few rows of width m, plus the query
-// profile.  Used only for admission.
+// about 64 live rows of m entries of 20 bytes, the profile and the query.
 uint64_t row_memory_estimate(uint64_t m, int sigma) {
     return 64ull * m * 20ull + (uint64_t)sigma * m + 16ull * m;
 }
+
+bool same_scheme(const Request &a, const Request &b) {
+    if (a.H != b.H || a.scoring.use_matrix != b.scoring.use_matrix || a.scoring.sg != b.scoring.sg ||
+        a.scoring.ss != b.scoring.ss)
+        return false;
+    if (a.scoring.use_matrix) return a.matrix == b.matrix;
+    return a.scoring.sa == b.scoring.sa && a.scoring.sb == b.scoring.sb;
+}
+
+struct Slot {
+    alae_workspace *ws = nullptr;
+    hipStream_t stream = nullptr;
+    uint8_t *d_query = nullptr;
+    uint64_t cap = 0;
+    std::thread th;
+};
+
+constexpr uint64_t kBatchColumns = 1ull << 20;  // query columns of one batched search
 
 }  // namespace
 
 struct alae_server {
     const alae_index *idx = nullptr;
     uint64_t budget = 0;
-    int max_inflight = 1;
-    alae_workspace *ws = nullptr;
-    uint8_t *d_query = nullptr;
-    uint64_t d_query_cap = 0;
+    int max_batch = 16;
+    std::vector<Slot> slots;
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
     std::deque<std::shared_ptr<Request>> queue;
@@ -62,49 +86,152 @@ struct alae_server {
     uint64_t next_id = 1;
     uint64_t reserved_bytes = 0;
     bool stop = false;
-    std::thread worker;
+    // statistics
+    uint64_t submitted = 0, completed = 0, batches = 0, batched = 0, rejected = 0;
+    std::vector<double> latencies_ms;
+    Clock::time_point t_first{}, t_last{};
 };
 
-static void server_loop(alae_server *srv) {
+// Run one batch on a slot; fills each request's result and status.
+static void run_batch(alae_server *srv, Slot &slot, std::vector<std::shared_ptr<Request>> &batch) {
+    alae_status st = ALAE_OK;
+    uint64_t m = 0;
+    for (auto &r : batch) m += r->codes.size();
+    if (m > slot.cap) {
+        if (slot.d_query) hipFree(slot.d_query);
+        slot.d_query = nullptr;
+        slot.cap = 0;
+        if (hipMalloc(&slot.d_query, m) != hipSuccess) {
+            hipGetLastError();
+            set_error("device allocation of %llu query bytes failed", (unsigned long long)m);
+            st = ALAE_E_NOMEM;
+        } else {
+            slot.cap = m;
+        }
+    }
+    std::vector<uint8_t> cat;
+    std::vector<size_t> lens;
+    if (st == ALAE_OK) {
+        cat.reserve(m);
+        for (auto &r : batch) {
+            cat.insert(cat.end(), r->codes.begin(), r->codes.end());
+            lens.push_back(r->codes.size());
+        }
+        if (hipMemcpyAsync(slot.d_query, cat.data(), m, hipMemcpyHostToDevice, slot.stream) != hipSuccess ||
+            hipStreamSynchronize(slot.stream) != hipSuccess) {
+            set_error("query upload failed");
+            st = ALAE_E_DEVICE;
+        }
+    }
+    alae_scoring sc = batch[0]->scoring;
+    if (sc.use_matrix) sc.matrix = batch[0]->matrix.data();
+    alae_hits all{};
+    std::vector<size_t> off(batch.size() + 1, 0);
+    if (st == ALAE_OK) {
+        size_t cnt = 0;
+        if (batch.size() == 1) {
+            st = alae_search_device(slot.ws, slot.d_query, m, &sc, batch[0]->H, nullptr, slot.stream, &cnt);
+            off[1] = cnt;
+        } else {
+            st = alae_search_device_batch(slot.ws, slot.d_query, lens.data(), lens.size(), &sc, batch[0]->H, nullptr,
+                                          slot.stream, &cnt);
+            if (st == ALAE_OK) st = alae_workspace_batch_offsets(slot.ws, off.data(), batch.size());
+        }
+        if (st == ALAE_OK) st = download_hits(slot.ws, slot.stream, &all);
+    }
+    const std::string err = st == ALAE_OK ? std::string() : std::string(alae_last_error());
+    for (size_t i = 0; i < batch.size(); ++i) {
+        Request &r = *batch[i];
+        r.status = st;
+        if (st != ALAE_OK) {
+            r.error = err;
+            continue;
+        }
+        const size_t n = off[i + 1] - off[i], alloc = n ? n : 1;
+        alae_hits h{};
+        h.count = n;
+        h.query_end = (uint32_t *)malloc(alloc * sizeof(uint32_t));
+        h.text_end = (uint64_t *)malloc(alloc * sizeof(uint64_t));
+        h.score = (int32_t *)malloc(alloc * sizeof(int32_t));
+        if (!h.query_end || !h.text_end || !h.score) {
+            alae_hits_free(&h);
+            r.status = ALAE_E_NOMEM;
+            r.error = "out of host memory for a result";
+            continue;
+        }
+        if (n) {
+            memcpy(h.query_end, all.query_end + off[i], n * sizeof(uint32_t));
+            memcpy(h.text_end, all.text_end + off[i], n * sizeof(uint64_t));
+            memcpy(h.score, all.score + off[i], n * sizeof(int32_t));
+        }
+        r.result = h;
+    }
+    alae_hits_free(&all);
+}
+
+static void worker_loop(alae_server *srv, size_t si) {
+    Slot &slot = srv->slots[si];
+    hipSetDevice(srv->idx->device);
     for (;;) {
-        std::shared_ptr<Request> req;
+        std::vector<std::shared_ptr<Request>> batch;
+        uint64_t need = 0;
         {
             std::unique_lock<std::mutex> lk(srv->mu);
-            srv->cv_work.wait(lk, [&] { return srv->stop || !srv->queue.empty(); });
+            // the head request waits until the budget has room for it (no overtaking, so a
+            // large request is never starved by small ones)
+            srv->cv_work.wait(lk, [&] {
+                return srv->stop ||
+                       (!srv->queue.empty() && srv->reserved_bytes + srv->queue.front()->need <= srv->budget);
+            });
             if (srv->stop && srv->queue.empty()) return;
-            req = srv->queue.front();
-            srv->queue.pop_front();
-        }
-        alae_status st = ALAE_OK;
-        const uint64_t m = req->codes.size();
-        if (m > srv->d_query_cap) {
-            if (srv->d_query) hipFree(srv->d_query);
-            srv->d_query = nullptr;
-            srv->d_query_cap = 0;
-            if (hipMalloc(&srv->d_query, m) != hipSuccess) {
-                st = ALAE_E_NOMEM;
-            } else {
-                srv->d_query_cap = m;
+            uint64_t cols = 0;
+            while (!srv->queue.empty() && (int)batch.size() < srv->max_batch) {
+                auto &r = srv->queue.front();
+                if (!batch.empty() && (!same_scheme(*batch[0], *r) || cols + r->codes.size() > kBatchColumns ||
+                                       srv->reserved_bytes + need + r->need > srv->budget))
+                    break;
+                cols += r->codes.size();
+                need += r->need;
+                batch.push_back(r);
+                srv->queue.pop_front();
             }
+            srv->reserved_bytes += need;
+            srv->batches += 1;
+            srv->batched += batch.size();
         }
-        if (st == ALAE_OK && hipMemcpy(srv->d_query, req->codes.data(), m, hipMemcpyHostToDevice) != hipSuccess)
-            st = ALAE_E_DEVICE;
-        if (st == ALAE_OK) {
-            alae_scoring sc = req->scoring;
-            if (sc.use_matrix) sc.matrix = req->matrix.data();
-            size_t cnt = 0;
-            st = alae_search_device(srv->ws, srv->d_query, m, &sc, req->H, nullptr, nullptr, &cnt);
-            if (st == ALAE_OK) st = download_hits(srv->ws, nullptr, &req->result);
-        }
+        run_batch(srv, slot, batch);
         {
             std::lock_guard<std::mutex> lk(srv->mu);
-            req->status = st;
-            if (st != ALAE_OK) req->error = alae_last_error();
-            req->done = true;
-            srv->reserved_bytes -= row_memory_estimate(m, srv->idx->sigma);
+            const auto now = Clock::now();
+            for (auto &r : batch) {
+                r->done = true;
+                srv->completed += 1;
+                srv->latencies_ms.push_back(std::chrono::duration<double, std::milli>(now - r->t_submit).count());
+            }
+            srv->t_last = now;
+            srv->reserved_bytes -= need;
         }
         srv->cv_done.notify_all();
+        srv->cv_work.notify_all();
     }
+}
+
+static void destroy_server(alae_server *srv) {
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        srv->stop = true;
+    }
+    srv->cv_work.notify_all();
+    for (auto &s : srv->slots)
+        if (s.th.joinable()) s.th.join();
+    for (auto &kv : srv->requests) alae_hits_free(&kv.second->result);
+    hipSetDevice(srv->idx->device);
+    for (auto &s : srv->slots) {
+        if (s.d_query) hipFree(s.d_query);
+        if (s.stream) hipStreamDestroy(s.stream);
+        alae_workspace_free(s.ws);
+    }
+    delete srv;
 }
 
 extern "C" {
@@ -114,20 +241,31 @@ alae_status alae_server_create(const alae_index *index, const alae_server_opts *
         set_error("alae_server_create: null argument");
         return ALAE_E_ARG;
     }
-    std::unique_ptr<alae_server> srv(new (std::nothrow) alae_server());
+    alae_server *srv = new (std::nothrow) alae_server();
     if (!srv) {
         set_error("out of host memory");
         return ALAE_E_NOMEM;
     }
     srv->idx = index;
-    alae_status st = alae_workspace_create(index, &srv->ws);
-    if (st != ALAE_OK) return st;
+    const int nslots = (opts && opts->max_inflight > 0) ? std::min(opts->max_inflight, 16) : 4;
+    srv->max_batch = (opts && opts->max_batch > 0) ? opts->max_batch : 16;
+    srv->slots.resize((size_t)nslots);
+    for (auto &s : srv->slots) {
+        alae_status st = alae_workspace_create(index, &s.ws);
+        if (st == ALAE_OK && hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking) != hipSuccess) {
+            set_error("stream creation failed");
+            st = ALAE_E_DEVICE;
+        }
+        if (st != ALAE_OK) {
+            destroy_server(srv);
+            return st;
+        }
+    }
     size_t free_b = 0, total_b = 0;
     hipMemGetInfo(&free_b, &total_b);
     srv->budget = (opts && opts->memory_budget) ? opts->memory_budget : (uint64_t)(free_b / 2);
-    srv->max_inflight = (opts && opts->max_inflight > 0) ? opts->max_inflight : 64;
-    srv->worker = std::thread(server_loop, srv.get());
-    *out = srv.release();
+    for (size_t i = 0; i < srv->slots.size(); ++i) srv->slots[i].th = std::thread(worker_loop, srv, i);
+    *out = srv;
     return ALAE_OK;
 }
 
@@ -159,19 +297,22 @@ alae_status alae_server_submit(alae_server *srv, const char *query, size_t m, co
     }
     req->scoring.matrix = nullptr;
     req->H = H;
-    const uint64_t need = row_memory_estimate(m, srv->idx->sigma);
+    req->need = row_memory_estimate(m, srv->idx->sigma);
+    req->t_submit = Clock::now();
     std::lock_guard<std::mutex> lk(srv->mu);
-    if (need > srv->budget) {
-        set_error("request needs about %llu device bytes, budget is %llu", (unsigned long long)need,
+    if (req->need > srv->budget) {
+        srv->rejected += 1;
+        set_error("request needs about %llu device bytes, budget is %llu", (unsigned long long)req->need,
                   (unsigned long long)srv->budget);
         return ALAE_E_ADMISSION;
     }
     req->id = srv->next_id++;
-    srv->reserved_bytes += need;
+    if (srv->submitted == 0) srv->t_first = req->t_submit;
+    srv->submitted += 1;
     srv->requests[req->id] = req;
     srv->queue.push_back(req);
     *req_id = req->id;
-    srv->cv_work.notify_one();
+    srv->cv_work.notify_all();
     return ALAE_OK;
 }
 
@@ -205,18 +346,44 @@ alae_status alae_server_poll(alae_server *srv, uint64_t req_id, int wait, alae_h
     return ALAE_OK;
 }
 
+alae_status alae_server_get_stats(alae_server *srv, alae_server_stats *out) {
+    if (!srv || !out) {
+        set_error("alae_server_get_stats: null argument");
+        return ALAE_E_ARG;
+    }
+    std::lock_guard<std::mutex> lk(srv->mu);
+    memset(out, 0, sizeof(*out));
+    out->submitted = srv->submitted;
+    out->completed = srv->completed;
+    out->rejected = srv->rejected;
+    out->batches = srv->batches;
+    out->mean_batch = srv->batches ? (double)srv->batched / (double)srv->batches : 0.0;
+    out->queued = srv->queue.size();
+    if (!srv->latencies_ms.empty()) {
+        std::vector<double> v = srv->latencies_ms;
+        std::sort(v.begin(), v.end());
+        auto pct = [&](double p) { return v[std::min(v.size() - 1, (size_t)(p * (double)(v.size() - 1) + 0.5))]; };
+        out->p50_ms = pct(0.50);
+        out->p99_ms = pct(0.99);
+        out->max_ms = v.back();
+        double s = 0;
+        for (double x : v) s += x;
+        out->mean_ms = s / (double)v.size();
+        out->span_s = std::chrono::duration<double>(srv->t_last - srv->t_first).count();
+    }
+    return ALAE_OK;
+}
+
+void alae_server_reset_stats(alae_server *srv) {
+    if (!srv) return;
+    std::lock_guard<std::mutex> lk(srv->mu);
+    srv->submitted = srv->completed = srv->batches = srv->batched = srv->rejected = 0;
+    srv->latencies_ms.clear();
+}
+
 void alae_server_destroy(alae_server *srv) {
     if (!srv) return;
-    {
-        std::lock_guard<std::mutex> lk(srv->mu);
-        srv->stop = true;
-    }
-    srv->cv_work.notify_all();
-    if (srv->worker.joinable()) srv->worker.join();
-    for (auto &kv : srv->requests) alae_hits_free(&kv.second->result);
-    if (srv->d_query) hipFree(srv->d_query);
-    alae_workspace_free(srv->ws);
-    delete srv;
+    destroy_server(srv);
 }
 
 }  // extern "C"
