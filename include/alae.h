@@ -123,6 +123,8 @@ typedef struct {
     uint64_t partitioned;    /* lane-queue chains the work predictor sent to the first wave pass */
     uint64_t leftover;       /* wave-queue chains walked after the concurrent pass            */
     double order_ms;         /* device time of features, predictions and the partition        */
+    double level_lane_ms;    /* device time of the one-lane-per-node level kernel alone       */
+    uint64_t level_lane_launches; /* its launches                                          */
 } alae_stats;
 
 /*

@@ -64,7 +64,8 @@ class Stats(ctypes.Structure):
                 ("wide_steps", ctypes.c_uint64), ("promoted", ctypes.c_uint64),
                 ("dominated_gapped", ctypes.c_uint64), ("chain_bytes", ctypes.c_uint64),
                 ("merge_ms", ctypes.c_double), ("reused", ctypes.c_uint64), ("replay_chains", ctypes.c_uint64),
-                ("partitioned", ctypes.c_uint64), ("leftover", ctypes.c_uint64), ("order_ms", ctypes.c_double)]
+                ("partitioned", ctypes.c_uint64), ("leftover", ctypes.c_uint64), ("order_ms", ctypes.c_double),
+                ("level_lane_ms", ctypes.c_double), ("level_lane_launches", ctypes.c_uint64)]
 
     def reusing_ratio(self) -> float:
         """Equation 6: reused entries over accessed (reused + computed) entries."""

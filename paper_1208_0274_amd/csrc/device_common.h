@@ -163,55 +163,58 @@ __device__ inline uint32_t occ1_gen(const SearchArgs &a, int c, int64_t i) {
 // Counters shared by the kernels of one search
 // ---------------------------------------------------------------------------
 
+// Device counters, each on its own 128-byte line: wave-level atomics on
+// different counters then go to different L2 lines instead of queueing on one.
+#define kCounter alignas(128) unsigned long long
 struct Counters {
-    unsigned long long nodes;     // child nodes allocated in the output level
-    unsigned long long entries;   // entries allocated in the output level
-    unsigned long long hits;      // hit records allocated in total
-    unsigned long long overflow;  // bit 0 nodes, bit 1 entries, bit 2 hits
+    kCounter nodes;     // child nodes allocated in the output level
+    kCounter entries;   // entries allocated in the output level
+    kCounter hits;      // hit records allocated in total
+    kCounter overflow;  // bit 0 nodes, bit 1 entries, bit 2 hits
     // statistics
-    unsigned long long st_nodes;
-    unsigned long long st_entries;
-    unsigned long long st_diag;
-    unsigned long long st_gap2;
-    unsigned long long st_gap3;
-    unsigned long long st_dominated;
-    unsigned long long st_emitted;
-    unsigned long long bad_query;
+    kCounter st_nodes;
+    kCounter st_entries;
+    kCounter st_diag;
+    kCounter st_gap2;
+    kCounter st_gap3;
+    kCounter st_dominated;
+    kCounter st_emitted;
+    kCounter bad_query;
     // random-access reads of the expansion kernel (64-byte granules)
-    unsigned long long st_occ_reads;
-    unsigned long long st_sa_reads;
-    unsigned long long st_text_reads;
+    kCounter st_occ_reads;
+    kCounter st_sa_reads;
+    kCounter st_text_reads;
     // frontier bytes read and written by the expansion kernel
-    unsigned long long st_frontier_bytes;
+    kCounter st_frontier_bytes;
     // chains: nodes with a single occurrence, walked along the text
-    unsigned long long cnodes;     // chain items allocated by the level kernel
-    unsigned long long centries;   // their row entries
-    unsigned long long chain_head; // next chain item to start (narrow chain kernel)
-    unsigned long long wnodes;     // wide chain items (rows too wide for one lane)
-    unsigned long long wentries;   // their row entries
-    unsigned long long wide_head;  // next wide item to start (wide chain kernel)
-    unsigned long long st_chain_steps;
-    unsigned long long st_wide_steps;
-    unsigned long long st_promoted;
-    unsigned long long st_dominated_gapped;
-    unsigned long long st_chain_bytes;  // row bytes moved by the chain kernels
-    unsigned long long hit_padding;     // reserved hit slots left unused (padding keys)
-    unsigned long long onodes;          // wide chains whose row outgrew the on-chip buffers
-    unsigned long long oentries;
-    unsigned long long overflow_head;
-    unsigned long long lwnodes;         // next-level nodes with rows too long for a lane
-    unsigned long long gnodes;          // chains with gaps, walked by the general lane kernel
-    unsigned long long gentries;
-    unsigned long long general_head;
-    unsigned long long st_ngr_steps;    // chain steps taken in the no-gap fast path
-    unsigned long long stage_need;      // longest row that did not fit a level-wide staging buffer
-    unsigned long long st_reused;       // entries replayed from an identical fork instead of computed
-    unsigned long long st_replay;       // chains recognised as copies of one fork
-    unsigned long long gen_done;        // lane-walker waves that have finished
-    unsigned long long missed;          // wave-queue items a live consumer left for the next pass
-    unsigned long long t_gen0, t_gen1;  // first start / last end of lane-walker waves (100 MHz clock)
-    unsigned long long t_live0, t_live1;  // same for the live wave pass
-    unsigned long long t_push0;         // first item published to the live pass
+    kCounter cnodes;     // chain items allocated by the level kernel
+    kCounter centries;   // their row entries
+    kCounter chain_head; // next chain item to start (narrow chain kernel)
+    kCounter wnodes;     // wide chain items (rows too wide for one lane)
+    kCounter wentries;   // their row entries
+    kCounter wide_head;  // next wide item to start (wide chain kernel)
+    kCounter st_chain_steps;
+    kCounter st_wide_steps;
+    kCounter st_promoted;
+    kCounter st_dominated_gapped;
+    kCounter st_chain_bytes;  // row bytes moved by the chain kernels
+    kCounter hit_padding;     // reserved hit slots left unused (padding keys)
+    kCounter onodes;          // wide chains whose row outgrew the on-chip buffers
+    kCounter oentries;
+    kCounter overflow_head;
+    kCounter lwnodes;         // next-level nodes with rows too long for a lane
+    kCounter gnodes;          // chains with gaps, walked by the general lane kernel
+    kCounter gentries;
+    kCounter general_head;
+    kCounter st_ngr_steps;    // chain steps taken in the no-gap fast path
+    kCounter stage_need;      // longest row that did not fit a level-wide staging buffer
+    kCounter st_reused;       // entries replayed from an identical fork instead of computed
+    kCounter st_replay;       // chains recognised as copies of one fork
+    kCounter gen_done;        // lane-walker waves that have finished
+    kCounter missed;          // wave-queue items a live consumer left for the next pass
+    kCounter t_gen0, t_gen1;  // first start / last end of lane-walker waves (100 MHz clock)
+    kCounter t_live0, t_live1;  // same for the live wave pass
+    kCounter t_push0;         // first item published to the live pass
 };
 
 // Key of an unused hit slot: sorts after every real (column, text end) key.

@@ -116,16 +116,106 @@ __device__ void expand_node(const SearchArgs &a, const Node &nd, const Entry *pr
     }
 }
 
-__global__ void __launch_bounds__(256) k_expand_level(SearchArgs a, const Node *nodes, uint32_t nn, const Entry *ent,
-                                                      int32_t d1, LevelOut o, Caps caps, Counters *cnt) {
+// Child rows of a node are computed once into a per-lane LDS stage of
+// kStage entries; the wave then allocates its outputs with one atomic per
+// buffer and each lane copies its stage out.  A node whose children do not
+// fit the stage is counted and written by two passes of expand_node instead.
+// A parent row of at most kParent entries is copied to LDS first, with its
+// loads issued together, so that the row updates read it at LDS latency.
+constexpr int kStage = 8;
+constexpr int kParent = 4;
+constexpr int kStageWords = (kStage + kParent) * 5 + 1;  // one pad word: lanes start in different banks
+constexpr int kLevelBlock = 128;
+
+__global__ void __launch_bounds__(kLevelBlock) k_expand_level(SearchArgs a, const Node *nodes, uint32_t nn,
+                                                              const Entry *ent, int32_t d1, LevelOut o, Caps caps,
+                                                              Counters *cnt) {
+    __shared__ uint32_t s_stage[kLevelBlock * kStageWords];
     const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
     const bool active = t < nn;
     Node nd;
     nd.lo = nd.hi = nd.off = nd.len = 0;
     if (active) nd = nodes[t];
+    Entry *stage = reinterpret_cast<Entry *>(s_stage + threadIdx.x * kStageWords);
+    Entry *parent = stage + kStage;
     LevelCounts n = {0, 0, 0, 0, 0, 0};
     uint32_t st[5] = {0, 0, 0, 0, 0};
-    if (active) expand_node<false>(a, nd, ent + nd.off, d1, n, o, caps, st);
+    // children: BWT range and staged entry count (entries 0 .. used-1 of the stage, in child order)
+    uint32_t ch_lo[4] = {0, 0, 0, 0}, ch_hi[4] = {0, 0, 0, 0}, ch_n[4] = {0, 0, 0, 0};
+    bool staged = false;
+    const Entry *use_prow = nullptr;  // parent row of the two-pass path (LDS copy or global)
+    if (active) {
+        const Entry *prow = ent + nd.off;
+        if (nd.len >= 1 && nd.len <= (uint32_t)kParent) {
+            // four independent loads (indexes clamped into the row), then the LDS copy
+            const uint32_t last = nd.len - 1;
+            const Entry e0 = prow[0];
+            const Entry e1 = prow[last < 1 ? last : 1];
+            const Entry e2 = prow[last < 2 ? last : 2];
+            const Entry e3 = prow[last < 3 ? last : 3];
+            parent[0] = e0;
+            parent[1] = e1;
+            parent[2] = e2;
+            parent[3] = e3;
+            prow = parent;
+        }
+        if (a.sigma == 4) {
+            uint32_t o_lo[4] = {0, 0, 0, 0}, o_hi[4] = {0, 0, 0, 0};
+            occ4_dna(a, (int64_t)nd.lo - 1, o_lo);
+            occ4_dna(a, (int64_t)nd.hi, o_hi);
+            const int64_t b0 = nd.lo == 0 ? -1 : ((int64_t)nd.lo - 1) / kDnaBlockChars;
+            const int64_t b1 = (int64_t)nd.hi / kDnaBlockChars;
+            st[3] += (b0 >= 0 && b0 != b1) ? 2u : 1u;
+            staged = true;
+            uint32_t used = 0;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const int64_t l = (int64_t)a.C[c] + o_lo[c];
+                const int64_t r = (int64_t)a.C[c] + o_hi[c] - 1;
+                ch_lo[c] = (uint32_t)l;
+                ch_hi[c] = (uint32_t)r;
+                if (!staged || l > r) continue;
+                RowSink s;
+                sink_init(s);
+                s.lo = (uint32_t)l;
+                s.hi = (uint32_t)r;
+                s.out = stage + used;
+                s.cap = (uint32_t)kStage - used;
+                s.hit_cap = 0;  // count hits now, write them after the allocation
+                const bool multi = l < r;
+                if (!multi) s.emit_hits = false;
+                child_row<true>(a, prow, nd.len, c, d1, false, 0, s);
+                if (s.n_entries > s.cap) {
+                    staged = false;
+                    continue;
+                }
+                st[0] += s.st_diag;
+                st[1] += s.st_gap2;
+                st[2] += s.st_gap3;
+                ch_n[c] = s.n_entries;
+                used += s.n_entries;
+                n.hits += s.n_hits;
+                if (s.n_entries == 0) continue;
+                if (multi) {
+                    if (s.n_entries > kLaneRow)
+                        n.wide++;
+                    else
+                        n.nodes++;
+                    n.entries += s.n_entries;
+                } else {
+                    n.chains++;
+                    n.centries += s.n_entries;
+                }
+            }
+        }
+        if (!staged) {  // the stage overflowed, or a protein alphabet: two passes
+            n = LevelCounts{0, 0, 0, 0, 0, 0};
+            st[0] = st[1] = st[2] = 0;
+            uint32_t dummy[5] = {0, 0, 0, 0, 0};
+            expand_node<false>(a, nd, prow, d1, n, o, caps, a.sigma == 4 ? dummy : st);
+            use_prow = prow;
+        }
+    }
     // allocate this wave's output with one atomic per buffer
     unsigned long long t_nodes, t_wide, t_ent, t_ch, t_ce, t_hits;
     const unsigned long long p_nodes = wave_excl_scan_u64(n.nodes, &t_nodes);
@@ -160,7 +250,6 @@ __global__ void __launch_bounds__(256) k_expand_level(SearchArgs a, const Node *
     b_hits = __shfl(b_hits, 0, 64);
     const bool fits = b_nodes + t_nodes <= caps.nodes && b_wide + t_wide <= caps.lwnodes &&
                       b_ent + t_ent <= caps.entries && b_ch + t_ch <= caps.cnodes && b_ce + t_ce <= caps.centries;
-    uint32_t st2[5] = {0, 0, 0, 0, 0};
     if (active && fits) {
         LevelOut w = o;
         w.node_base = b_nodes + p_nodes;
@@ -169,14 +258,59 @@ __global__ void __launch_bounds__(256) k_expand_level(SearchArgs a, const Node *
         w.chain_base = b_ch + p_ch;
         w.cent_base = b_ce + p_ce;
         w.hit_base = b_hits + p_hits;
-        LevelCounts n2;
-        expand_node<true>(a, nd, ent + nd.off, d1, n2, w, caps, st2);
+        if (staged) {
+            uint32_t used = 0, k_nodes = 0, k_wide = 0, k_ent = 0, k_ch = 0, k_ce = 0;
+            unsigned long long hslot = w.hit_base;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const uint32_t len = ch_n[c];
+                if (len == 0) continue;
+                const Entry *src = stage + used;
+                used += len;
+                const bool multi = ch_lo[c] < ch_hi[c];
+                Node cn;
+                Entry *dst;
+                if (multi) {
+                    cn.lo = ch_lo[c];
+                    cn.hi = ch_hi[c];
+                    cn.off = (uint32_t)(w.ent_base + k_ent);
+                    dst = o.oent + w.ent_base + k_ent;
+                    k_ent += len;
+                    if (len > kLaneRow)
+                        o.owide[w.wide_base + k_wide++] = Node{cn.lo, cn.hi, cn.off, len};
+                    else
+                        o.onodes[w.node_base + k_nodes++] = Node{cn.lo, cn.hi, cn.off, len};
+                } else {
+                    cn.lo = ch_lo[c];
+                    cn.hi = (uint32_t)d1;
+                    cn.off = (uint32_t)(w.cent_base + k_ce);
+                    dst = o.cent + w.cent_base + k_ce;
+                    k_ce += len;
+                    o.chains[w.chain_base + k_ch++] = Node{cn.lo, cn.hi, cn.off, len};
+                }
+                for (uint32_t k = 0; k < len; ++k) {
+                    const Entry e = src[k];
+                    dst[k] = e;
+                    if (multi && e.M >= a.H) {  // hits at every occurrence (chains emit their own)
+                        for (uint32_t h = ch_lo[c]; h <= ch_hi[c]; ++h, ++hslot) {
+                            if (hslot < caps.hits) {
+                                o.hkeys[hslot] = ((uint64_t)e.col << 32) | a.sa[h];
+                                o.hscores[hslot] = (uint32_t)e.M;
+                            }
+                        }
+                    }
+                }
+            }
+        } else {
+            LevelCounts n2;
+            expand_node<true>(a, nd, use_prow, d1, n2, w, caps, st);
+        }
     }
     const unsigned long long s_nodes = wave_sum_u64(active ? 1 : 0);
     const unsigned long long s_ent = wave_sum_u64(n.entries + n.centries);
-    const unsigned long long s_diag = wave_sum_u64(st2[0]);
-    const unsigned long long s_g2 = wave_sum_u64(st2[1]);
-    const unsigned long long s_g3 = wave_sum_u64(st2[2]);
+    const unsigned long long s_diag = wave_sum_u64(st[0]);
+    const unsigned long long s_g2 = wave_sum_u64(st[1]);
+    const unsigned long long s_g3 = wave_sum_u64(st[2]);
     const unsigned long long s_occ = wave_sum_u64(st[3]);
     const unsigned long long s_in =
         wave_sum_u64(active ? (unsigned long long)(sizeof(Node) + nd.len * sizeof(Entry)) : 0ull);

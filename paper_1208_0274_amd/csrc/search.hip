@@ -443,6 +443,7 @@ struct alae_workspace {
     Counters *h_cnt = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     hipEvent_t evk0 = nullptr, evk1 = nullptr;  // around each expansion launch
+    hipEvent_t evkm = nullptr;                  // after the lane kernel of a level
 };
 
 namespace alae {
@@ -511,6 +512,7 @@ static void ws_release(alae_workspace *ws) {
     if (ws->ev1) hipEventDestroy(ws->ev1);
     if (ws->evk0) hipEventDestroy(ws->evk0);
     if (ws->evk1) hipEventDestroy(ws->evk1);
+    if (ws->evkm) hipEventDestroy(ws->evkm);
 }
 
 struct Scheme {
@@ -883,7 +885,8 @@ static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64
 
     uint64_t levels = 0, retries = 0, max_depth = nn ? (uint64_t)seed_depth : 0;
     uint64_t launches = 0, level_launches = 0;  // launches counts every timed kernel
-    double expand_ms = 0.0, start_ms = 0.0, general_ms = 0.0, wide_ms = 0.0;
+    double expand_ms = 0.0, start_ms = 0.0, general_ms = 0.0, wide_ms = 0.0, lane_ms = 0.0;
+    uint64_t lane_launches = 0;
     int32_t depth = seed_depth;
     int cus = 256;
     hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ws->device);
@@ -1010,8 +1013,9 @@ static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64
             o.node_base = o.wide_base = o.ent_base = o.chain_base = o.cent_base = o.hit_base = 0;
             HIP_TRY(hipEventRecord(ws->evk0, s));
             if (nn > 0)
-                k_expand_level<<<(uint32_t)((nn + tb - 1) / tb), tb, 0, s>>>(a, ws->nodes[cur], (uint32_t)nn,
-                                                                            ws->ents[cur], d1, o, caps, ws->d_cnt);
+                k_expand_level<<<(uint32_t)((nn + kLevelBlock - 1) / kLevelBlock), kLevelBlock, 0, s>>>(
+                    a, ws->nodes[cur], (uint32_t)nn, ws->ents[cur], d1, o, caps, ws->d_cnt);
+            HIP_TRY(hipEventRecord(ws->evkm, s));
             if (nlw > 0) {
                 const uint32_t blocks =
                     (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>({nlw, 2048, stage_budget / srow}));
@@ -1021,6 +1025,12 @@ static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64
             }
             if ((st = timed(expand_ms)) != ALAE_OK) return st;
             ++level_launches;
+            if (nn > 0) {  // the lane kernel alone (the roofline's kernel)
+                float lms = 0.f;
+                HIP_TRY(hipEventElapsedTime(&lms, ws->evk0, ws->evkm));
+                lane_ms += lms;
+                ++lane_launches;
+            }
             const Counters &c = *ws->h_cnt;
             if (!c.overflow) break;
             ++retries;
@@ -1370,6 +1380,8 @@ static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64
         o->merge_ms = merge_ms;
         o->partitioned = partitioned;
         o->order_ms = order_ms;
+        o->level_lane_ms = lane_ms;
+        o->level_lane_launches = lane_launches;
         o->leftover = leftover;
         o->reused = c.st_reused;
         o->replay_chains = c.st_replay;
@@ -1402,6 +1414,7 @@ alae_status alae_workspace_create(const alae_index *index, alae_workspace **out)
     HIP_TRY(hipEventCreate(&ws->ev1));
     HIP_TRY(hipEventCreate(&ws->evk0));
     HIP_TRY(hipEventCreate(&ws->evk1));
+    HIP_TRY(hipEventCreate(&ws->evkm));
     HIP_TRY(hipEventCreateWithFlags(&ws->ev_fork, hipEventDisableTiming));
     HIP_TRY(hipEventCreateWithFlags(&ws->ev_join, hipEventDisableTiming));
     HIP_TRY(hipStreamCreateWithFlags(&ws->s2, hipStreamNonBlocking));
