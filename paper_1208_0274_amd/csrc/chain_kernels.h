@@ -150,199 +150,309 @@ struct ChainQueues {
     uint32_t *hscores;
 };
 
+// Hit slots of one lane, reserved eight at a time (lanes walk independently);
+// slots left over are padded with kPadKey.
+constexpr unsigned long long kLaneHitChunk = 8;
+struct LaneHits {
+    unsigned long long base, left, pad;
+};
+
+__device__ inline void lane_hit_put(LaneHits &h, Counters *cnt, uint64_t *hkeys, uint32_t *hscores, Caps caps,
+                                    uint32_t col, uint32_t e_end, int32_t M) {
+    if (h.left == 0) {
+        h.base = atomicAdd(&cnt->hits, kLaneHitChunk);
+        h.left = kLaneHitChunk;
+        if (h.base + kLaneHitChunk > caps.hits) atomicOr(&cnt->overflow, kOvHits);
+    }
+    if (h.base < caps.hits) {
+        hkeys[h.base] = ((uint64_t)col << 32) | e_end;
+        hscores[h.base] = (uint32_t)M;
+    }
+    ++h.base;
+    --h.left;
+}
+
+__device__ inline void lane_hit_release(LaneHits &h, uint64_t *hkeys, uint32_t *hscores, Caps caps) {
+    for (; h.left; --h.left, ++h.base, ++h.pad) {
+        if (h.base < caps.hits) {
+            hkeys[h.base] = kPadKey;
+            hscores[h.base] = 0;
+        }
+    }
+}
+
+// Wave-aggregated reservation of `nodes` queue records and `ents` entries per
+// lane; returns false (and raises the overflow bits) when the queue is full.
+__device__ inline bool wave_queue_alloc(Counters *cnt, unsigned long long *nodes_ctr, unsigned long long *ent_ctr,
+                                        unsigned long long node_cap, unsigned long long ent_cap,
+                                        unsigned long long ov_nodes, unsigned long long ov_ent, uint32_t nodes,
+                                        uint32_t ents, unsigned long long &slot, unsigned long long &off) {
+    const int lane = threadIdx.x & 63;
+    uint32_t tn, te;
+    const uint32_t pn = wave_excl_scan_u32(nodes, &tn);
+    const uint32_t pe = wave_excl_scan_u32(ents, &te);
+    unsigned long long bn = 0, be = 0;
+    if (lane == 0 && tn) {
+        bn = atomicAdd(nodes_ctr, (unsigned long long)tn);
+        be = atomicAdd(ent_ctr, (unsigned long long)te);
+        if (bn + tn > node_cap) atomicOr(&cnt->overflow, ov_nodes);
+        if (be + te > ent_cap) atomicOr(&cnt->overflow, ov_ent);
+    }
+    bn = __shfl(bn, 0, 64);
+    be = __shfl(be, 0, 64);
+    slot = bn + pn;
+    off = be + pe;
+    return bn + tn <= node_cap && be + te <= ent_cap;
+}
+
 // ---------------------------------------------------------------------------
-// k_chain_start: one lane per chain created by a level
+// k_chain_start: one lane per chain created by a level.  Queue records and
+// hit slots are reserved once per wave where every lane takes part; the
+// no-gap walk reserves its hit slots per lane in small chunks.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_chain_start(SearchArgs a, SubTable subt, const Node *items, uint32_t nitems,
                                                      const Entry *ient, ChainQueues q, Caps caps, Counters *cnt) {
     __shared__ int8_t sub[20 * 20];
     for (int i = threadIdx.x; i < a.sigma * a.sigma; i += blockDim.x) sub[i] = subt.s[i];
     __syncthreads();
+    const int lane = threadIdx.x & 63;
     const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
     const int32_t open = a.sg + a.ss;
-    unsigned long long n_dom = 0, n_steps = 0, n_entries = 0, n_hits = 0, n_general = 0, n_wide = 0;
+    unsigned long long n_dom = 0, n_steps = 0, n_entries = 0, n_hits = 0, n_wide = 0;
+    // phase 1: locate, test the states (ungapped domination), classify
+    enum { kNone = 0, kWide = 1, kGeneral = 2, kNgr = 3 };
+    int path = kNone;
+    uint32_t e_end = 0, len = 0, killM = 0, killGa = 0, live = 0, nh = 0;
+    int32_t depth = 0;
+    const Entry *row = nullptr;
+    int64_t x = 0;
     if (t < nitems) {
         const Node it = items[t];
-        uint32_t e_end = a.sa[it.lo];
-        int32_t depth = (int32_t)it.hi;
-        const uint32_t len = it.len;
-        const Entry *row = ient + it.off;
-        const int64_t x = (int64_t)e_end - depth + 1;
-        if (len > (uint32_t)kNarrowRow) {
-            // long row (repeats, or wide gap shadows at the first unique depth): both
-            // domination tests, then the wave walkers
-            Entry *dst = queue_alloc(cnt, &cnt->wnodes, &cnt->wentries, caps.wnodes, caps.wentries, kOvWideNodes,
-                                     kOvWideEntries, q.wnodes, q.wents, len, e_end, depth);
-            if (dst) {
-                for (uint32_t k = 0; k < len; ++k) {
-                    Entry e = row[k];
-                    if (a.use_domination) {
-                        if (e.M > 0 && dominated(a, sub, x, e.yM)) {
-                            e.M = kNeg;
-                            ++n_dom;
-                        }
-                        if (e.Ga > 0 && dominated(a, sub, x, e.yGa)) {
-                            e.Ga = kNeg;
-                            ++n_dom;
-                        }
+        e_end = a.sa[it.lo];
+        depth = (int32_t)it.hi;
+        len = it.len;
+        row = ient + it.off;
+        x = (int64_t)e_end - depth + 1;
+        bool ngr = true;
+        for (uint32_t k = 0; k < len; ++k) {
+            const Entry e = row[k];
+            bool aM = e.M > 0, aG = e.Ga > 0;
+            if (a.use_domination) {
+                if (aM && dominated(a, sub, x, e.yM)) {
+                    aM = false;
+                    if (k < 32) killM |= 1u << k;
+                    ++n_dom;
+                }
+                if (aG && dominated(a, sub, x, e.yGa)) {
+                    aG = false;
+                    if (k < 32) killGa |= 1u << k;
+                    ++n_dom;
+                }
+            }
+            if (aM && e.M >= a.H) ++nh;
+            if (aM || aG) ++live;
+            if (aG || (aM && e.M > -open)) ngr = false;
+        }
+        if (len > (uint32_t)kNarrowRow)
+            path = kWide;  // long row: both domination tests, then the wave walkers
+        else if (live > 0 && (!ngr || live > (uint32_t)kNgrSlots || !a.ngr_walk))
+            path = kGeneral;  // gap states (or many entries): the general lane walker
+        else if (live > 0)
+            path = kNgr;  // no-gap region: walk in registers, diagonal steps only (Eq. 3)
+    }
+    // domination verdicts of phase 1: bit masks for rows of up to 32 entries,
+    // recomputed for longer rows
+    auto deadM = [&](uint32_t k, const Entry &e) {
+        return len <= 32u ? ((killM >> k) & 1u) != 0 : (a.use_domination && e.M > 0 && dominated(a, sub, x, e.yM));
+    };
+    auto deadGa = [&](uint32_t k, const Entry &e) {
+        return len <= 32u ? ((killGa >> k) & 1u) != 0
+                          : (a.use_domination && e.Ga > 0 && dominated(a, sub, x, e.yGa));
+    };
+    // phase 2: one reservation per wave for the first row's hits and the queue records
+    {
+        uint32_t ht;
+        const uint32_t hp = wave_excl_scan_u32(nh, &ht);
+        unsigned long long hb = 0;
+        if (lane == 0 && ht) {
+            hb = atomicAdd(&cnt->hits, (unsigned long long)ht);
+            if (hb + ht > caps.hits) atomicOr(&cnt->overflow, kOvHits);
+        }
+        hb = __shfl(hb, 0, 64) + hp;
+        if (nh) {
+            for (uint32_t k = 0; k < len; ++k) {
+                const Entry e = row[k];
+                if (e.M <= 0 || e.M < a.H || deadM(k, e)) continue;
+                if (hb < caps.hits) {
+                    q.hkeys[hb] = ((uint64_t)e.col << 32) | e_end;
+                    q.hscores[hb] = (uint32_t)e.M;
+                }
+                ++hb;
+            }
+            n_hits += nh;
+        }
+    }
+    {
+        unsigned long long slot, off;
+        const bool ok = wave_queue_alloc(cnt, &cnt->wnodes, &cnt->wentries, caps.wnodes, caps.wentries, kOvWideNodes,
+                                         kOvWideEntries, path == kWide ? 1u : 0u, path == kWide ? len : 0u, slot, off);
+        if (path == kWide && ok) {
+            Entry *dst = q.wents + off;
+            for (uint32_t k = 0; k < len; ++k) {
+                Entry e = row[k];
+                if (deadM(k, e)) e.M = kNeg;
+                if (deadGa(k, e)) e.Ga = kNeg;
+                dst[k] = e;
+            }
+            if (a.use_domination) prune_dominated(a, dst, len, e_end, depth, n_dom);
+            Node nd;
+            nd.lo = kUniqueBit | e_end;
+            nd.hi = (uint32_t)depth;
+            nd.off = (uint32_t)off;
+            nd.len = len;
+            q.wnodes[slot] = nd;
+            ++n_wide;
+        }
+    }
+    {
+        unsigned long long slot, off;
+        const bool ok = wave_queue_alloc(cnt, &cnt->gnodes, &cnt->gentries, caps.gnodes, caps.gentries,
+                                         kOvGeneralNodes, kOvGeneralEntries, path == kGeneral ? 1u : 0u,
+                                         path == kGeneral ? live : 0u, slot, off);
+        if (path == kGeneral && ok) {
+            Entry *dst = q.gents + off;
+            uint32_t w = 0;
+            for (uint32_t k = 0; k < len; ++k) {
+                Entry e = row[k];
+                if (deadM(k, e)) e.M = kNeg;
+                if (deadGa(k, e)) e.Ga = kNeg;
+                if (e.M <= 0 && e.Ga <= 0) continue;
+                dst[w++] = e;
+            }
+            Node nd;
+            nd.lo = kUniqueBit | e_end;
+            nd.hi = (uint32_t)depth;
+            nd.off = (uint32_t)off;
+            nd.len = live;
+            q.gnodes[slot] = nd;
+        }
+    }
+    // phase 3: the no-gap walk
+    uint32_t col[kNgrSlots], y[kNgrSlots], send[kNgrSlots];
+    int32_t M[kNgrSlots];
+#pragma unroll
+    for (int s2 = 0; s2 < kNgrSlots; ++s2) {
+        col[s2] = 0;
+        y[s2] = 0;
+        send[s2] = 0;
+        M[s2] = kNeg;
+    }
+    uint32_t alive = 0;
+    bool handoff = false;
+    LaneHits lh = {0, 0, 0};
+    if (path == kNgr) {
+        {
+            int sidx = 0;
+            for (uint32_t k = 0; k < len; ++k) {
+                const Entry e = row[k];
+                if (e.M <= 0 || deadM(k, e)) continue;
+#pragma unroll
+                for (int s2 = 0; s2 < kNgrSlots; ++s2) {
+                    if (s2 == sidx) {
+                        col[s2] = e.col;
+                        M[s2] = e.M;
+                        y[s2] = e.yM;
+                        send[s2] = seg_end_of(a, e.col);
                     }
-                    dst[k] = e;
-                    if (e.M >= a.H) {
-                        emit_hit_lane(cnt, q.hkeys, q.hscores, caps, e.col, e_end, e.M);
+                }
+                alive |= 1u << sidx;
+                ++sidx;
+            }
+        }
+        uint64_t tw = 0, qw[kNgrSlots];
+        int tpos = 8;
+        for (;;) {
+            const int32_t d1 = depth + 1;
+            if (d1 > a.lmax || (uint64_t)e_end + 1 >= a.n) break;
+            if (tpos == 8) {
+                tw = load8(a.text, (int64_t)e_end + 1);
+#pragma unroll
+                for (int s2 = 0; s2 < kNgrSlots; ++s2)
+                    qw[s2] = (alive & (1u << s2)) ? load8(a.query, (int64_t)col[s2] + 1) : 0ull;
+                tpos = 0;
+            }
+            const uint32_t c = (uint32_t)(tw >> (8 * tpos)) & 0xFFu;
+            const int32_t rowgain = a.smax * (a.lmax - d1);
+            uint32_t nalive = 0;
+            bool fgoe = false;
+            int32_t nM[kNgrSlots];
+#pragma unroll
+            for (int s2 = 0; s2 < kNgrSlots; ++s2) {
+                const uint32_t ncol = col[s2] + 1;
+                const uint32_t pc = (uint32_t)(qw[s2] >> (8 * tpos)) & 0xFFu;
+                const int32_t v = M[s2] + score_of(a, sub, c, pc);
+                const bool ok = ((alive >> s2) & 1u) && ncol < send[s2] && keep_state(a, v, ncol, rowgain);
+                nM[s2] = ok ? v : kNeg;
+                nalive |= ok ? (1u << s2) : 0u;
+                fgoe |= ok && v > -open;
+            }
+            if (fgoe) {  // a gap can open below this row: the general walker takes the current row
+                handoff = true;
+                break;
+            }
+            ++n_steps;
+            if (!nalive) break;
+#pragma unroll
+            for (int s2 = 0; s2 < kNgrSlots; ++s2) {
+                if (nalive & (1u << s2)) {
+                    col[s2] += 1;
+                    M[s2] = nM[s2];
+                    ++n_entries;
+                    if (M[s2] >= a.H) {
+                        lane_hit_put(lh, cnt, q.hkeys, q.hscores, caps, col[s2], e_end + 1, M[s2]);
                         ++n_hits;
                     }
                 }
-                if (a.use_domination) prune_dominated(a, dst, len, e_end, depth, n_dom);
-                ++n_wide;
             }
-        } else {
-            // ungapped domination test of every state (Section 3.2)
-            uint32_t killM = 0, killGa = 0, live = 0;
-            bool ngr = true;
-            for (uint32_t k = 0; k < len; ++k) {
-                const Entry e = row[k];
-                bool aM = e.M > 0, aG = e.Ga > 0;
-                if (a.use_domination) {
-                    if (aM && dominated(a, sub, x, e.yM)) {
-                        aM = false;
-                        killM |= 1u << k;
-                        ++n_dom;
-                    }
-                    if (aG && dominated(a, sub, x, e.yGa)) {
-                        aG = false;
-                        killGa |= 1u << k;
-                        ++n_dom;
-                    }
-                }
-                if (aM && e.M >= a.H) {
-                    emit_hit_lane(cnt, q.hkeys, q.hscores, caps, e.col, e_end, e.M);
-                    ++n_hits;
-                }
-                if (aM || aG) ++live;
-                if (aG || (aM && e.M > -open)) ngr = false;
-            }
-            if (live > 0 && (!ngr || live > (uint32_t)kNgrSlots || !a.ngr_walk)) {
-                // gap states (or many entries): the general lane walker takes it
-                Entry *dst = queue_alloc(cnt, &cnt->gnodes, &cnt->gentries, caps.gnodes, caps.gentries,
-                                         kOvGeneralNodes, kOvGeneralEntries, q.gnodes, q.gents, live, e_end, depth);
-                if (dst) {
-                    uint32_t w = 0;
-                    for (uint32_t k = 0; k < len; ++k) {
-                        Entry e = row[k];
-                        if (killM & (1u << k)) e.M = kNeg;
-                        if (killGa & (1u << k)) e.Ga = kNeg;
-                        if (e.M <= 0 && e.Ga <= 0) continue;
-                        dst[w++] = e;
-                    }
-                }
-                ++n_general;
-            } else if (live > 0) {
-                // no-gap region: walk in registers, diagonal steps only (Eq. 3)
-                uint32_t col[kNgrSlots], y[kNgrSlots], send[kNgrSlots];
-                int32_t M[kNgrSlots];
+            alive = nalive;
+            e_end += 1;
+            depth = d1;
+            ++tpos;
+        }
+        lane_hit_release(lh, q.hkeys, q.hscores, caps);
+    }
+    // phase 4: hand-offs to the general walker, one reservation per wave
+    {
+        const uint32_t cntlive = handoff ? (uint32_t)__popc(alive) : 0u;
+        unsigned long long slot, off;
+        const bool ok = wave_queue_alloc(cnt, &cnt->gnodes, &cnt->gentries, caps.gnodes, caps.gentries,
+                                         kOvGeneralNodes, kOvGeneralEntries, handoff ? 1u : 0u, cntlive, slot, off);
+        if (handoff && ok) {
+            Entry *dst = q.gents + off;
+            uint32_t w = 0;
 #pragma unroll
-                for (int s2 = 0; s2 < kNgrSlots; ++s2) {
-                    col[s2] = 0;
-                    y[s2] = 0;
-                    send[s2] = 0;
-                    M[s2] = kNeg;
-                }
-                uint32_t alive = 0;
-                {
-                    int sidx = 0;
-                    for (uint32_t k = 0; k < len; ++k) {
-                        const Entry e = row[k];
-                        if ((killM & (1u << k)) || e.M <= 0) continue;
-#pragma unroll
-                        for (int s2 = 0; s2 < kNgrSlots; ++s2) {
-                            if (s2 == sidx) {
-                                col[s2] = e.col;
-                                M[s2] = e.M;
-                                y[s2] = e.yM;
-                                send[s2] = seg_end_of(a, e.col);
-                            }
-                        }
-                        alive |= 1u << sidx;
-                        ++sidx;
-                    }
-                }
-                uint64_t tw = 0, qw[kNgrSlots];
-                int tpos = 8;
-                for (;;) {
-                    const int32_t d1 = depth + 1;
-                    if (d1 > a.lmax || (uint64_t)e_end + 1 >= a.n) break;
-                    if (tpos == 8) {
-                        tw = load8(a.text, (int64_t)e_end + 1);
-#pragma unroll
-                        for (int s2 = 0; s2 < kNgrSlots; ++s2)
-                            qw[s2] = (alive & (1u << s2)) ? load8(a.query, (int64_t)col[s2] + 1) : 0ull;
-                        tpos = 0;
-                    }
-                    const uint32_t c = (uint32_t)(tw >> (8 * tpos)) & 0xFFu;
-                    const int32_t rowgain = a.smax * (a.lmax - d1);
-                    uint32_t nalive = 0;
-                    bool fgoe = false;
-                    int32_t nM[kNgrSlots];
-#pragma unroll
-                    for (int s2 = 0; s2 < kNgrSlots; ++s2) {
-                        const uint32_t ncol = col[s2] + 1;
-                        const uint32_t pc = (uint32_t)(qw[s2] >> (8 * tpos)) & 0xFFu;
-                        const int32_t v = M[s2] + score_of(a, sub, c, pc);
-                        const bool ok = ((alive >> s2) & 1u) && ncol < send[s2] && keep_state(a, v, ncol, rowgain);
-                        nM[s2] = ok ? v : kNeg;
-                        nalive |= ok ? (1u << s2) : 0u;
-                        fgoe |= ok && v > -open;
-                    }
-                    if (fgoe) {
-                        // a gap can open below this row: hand the current row to the general walker
-                        uint32_t cntlive = __popc(alive);
-                        Entry *dst = queue_alloc(cnt, &cnt->gnodes, &cnt->gentries, caps.gnodes, caps.gentries,
-                                                 kOvGeneralNodes, kOvGeneralEntries, q.gnodes, q.gents, cntlive,
-                                                 e_end, depth);
-                        if (dst) {
-                            uint32_t w = 0;
-#pragma unroll
-                            for (int s2 = 0; s2 < kNgrSlots; ++s2) {
-                                if (alive & (1u << s2)) {
-                                    Entry e;
-                                    e.col = col[s2];
-                                    e.M = M[s2];
-                                    e.Ga = kNeg;
-                                    e.yM = y[s2];
-                                    e.yGa = 0;
-                                    dst[w++] = e;
-                                }
-                            }
-                        }
-                        ++n_general;
-                        break;
-                    }
-                    ++n_steps;
-                    if (!nalive) break;
-#pragma unroll
-                    for (int s2 = 0; s2 < kNgrSlots; ++s2) {
-                        if (nalive & (1u << s2)) {
-                            col[s2] += 1;
-                            M[s2] = nM[s2];
-                            ++n_entries;
-                            if (M[s2] >= a.H) {
-                                emit_hit_lane(cnt, q.hkeys, q.hscores, caps, col[s2], e_end + 1, M[s2]);
-                                ++n_hits;
-                            }
-                        }
-                    }
-                    alive = nalive;
-                    e_end += 1;
-                    depth = d1;
-                    ++tpos;
+            for (int s2 = 0; s2 < kNgrSlots; ++s2) {
+                if (alive & (1u << s2)) {
+                    Entry e;
+                    e.col = col[s2];
+                    e.M = M[s2];
+                    e.Ga = kNeg;
+                    e.yM = y[s2];
+                    e.yGa = 0;
+                    dst[w++] = e;
                 }
             }
+            Node nd;
+            nd.lo = kUniqueBit | e_end;
+            nd.hi = (uint32_t)depth;
+            nd.off = (uint32_t)off;
+            nd.len = cntlive;
+            q.gnodes[slot] = nd;
         }
     }
-    const int lane = threadIdx.x & 63;
     const unsigned long long w_dom = wave_sum_u64(n_dom), w_steps = wave_sum_u64(n_steps),
                              w_ent = wave_sum_u64(n_entries), w_hits = wave_sum_u64(n_hits),
-                             w_gen = wave_sum_u64(n_general), w_wide = wave_sum_u64(n_wide),
+                             w_wide = wave_sum_u64(n_wide), w_pad = wave_sum_u64(lh.pad),
                              w_items = wave_sum_u64(t < nitems ? 1ull : 0ull);
     if (lane == 0) {
         if (w_dom) atomicAdd(&cnt->st_dominated, w_dom);
@@ -351,11 +461,11 @@ __global__ void __launch_bounds__(256) k_chain_start(SearchArgs a, SubTable subt
         if (w_ent) atomicAdd(&cnt->st_diag, w_ent);
         if (w_hits) atomicAdd(&cnt->st_emitted, w_hits);
         if (w_wide) atomicAdd(&cnt->st_promoted, w_wide);
+        if (w_pad) atomicAdd(&cnt->hit_padding, w_pad);
         if (w_items) {
             atomicAdd(&cnt->st_sa_reads, w_items);
             atomicAdd(&cnt->st_text_reads, w_items + w_steps / 8);
         }
-        (void)w_gen;
     }
 }
 
@@ -373,6 +483,7 @@ __global__ void __launch_bounds__(256) k_chain_general(SearchArgs a, const Node 
     const int lane = threadIdx.x & 63;
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     if (lane == 0) atomicMin(&cnt->t_gen0, (unsigned long long)__builtin_amdgcn_s_memrealtime());
+    HitRes hr = {0, 0, 0};
     Entry rows[2][kNarrowRow];
     int cur = 0;
     bool active = false;
@@ -450,17 +561,17 @@ __global__ void __launch_bounds__(256) k_chain_general(SearchArgs a, const Node 
             trace_work[my_item] = my_work;
             my_work = 0.f;
         }
-        // hit records of the new rows (one atomic per wave)
+        // hit records of the new rows (slots reserved by the wave in chunks)
         uint32_t nh = 0;
         if (stepped)
             for (uint32_t k = 0; k < nlen; ++k) nh += rows[cur ^ 1][k].M >= a.H ? 1u : 0u;
         uint32_t htot;
         const uint32_t hpre = wave_excl_scan_u32(nh, &htot);
         if (htot) {
-            unsigned long long hb = 0;
-            if (lane == 0) hb = atomicAdd(&cnt->hits, (unsigned long long)htot);
-            hb = __shfl(hb, 0, 64);
-            if (lane == 0 && hb + htot > caps.hits) atomicOr(&cnt->overflow, kOvHits);
+            hit_reserve(hr, htot, hkeys, hscores, caps.hits, cnt);
+            const unsigned long long hb = hr.base;
+            hr.base += htot;
+            hr.left -= htot;
             if (nh) {
                 unsigned long long slot = hb + hpre;
                 for (uint32_t k = 0; k < nlen; ++k) {
@@ -482,6 +593,7 @@ __global__ void __launch_bounds__(256) k_chain_general(SearchArgs a, const Node 
             depth += 1;
         }
     }
+    hit_release(hr, hkeys, hscores, caps.hits, cnt);
     const unsigned long long w_steps = wave_sum_u64(n_steps), w_ent = wave_sum_u64(n_entries),
                              w_dom = wave_sum_u64(n_dom), w_d = wave_sum_u64(n_diag), w_2 = wave_sum_u64(n_g2),
                              w_3 = wave_sum_u64(n_g3), w_b = wave_sum_u64(n_bytes), w_h = wave_sum_u64(n_hits),
