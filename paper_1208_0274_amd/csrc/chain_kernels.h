@@ -832,13 +832,15 @@ __device__ bool walk_wide(const SearchArgs &a, Row &cur, Row &nxt, uint32_t &len
     }
 }
 
+// w.diag, w.gap2 and w.gap3 are per-lane partial counts; the rest is wave-uniform.
 __device__ inline void wide_stats_flush(Counters *cnt, const WideStats &w) {
+    const unsigned long long d = wave_sum_u64(w.diag), g2 = wave_sum_u64(w.gap2), g3 = wave_sum_u64(w.gap3);
     if ((threadIdx.x & 63) != 0) return;
     atomicAdd(&cnt->st_wide_steps, w.steps);
     atomicAdd(&cnt->st_entries, w.entries);
-    atomicAdd(&cnt->st_diag, w.diag);
-    atomicAdd(&cnt->st_gap2, w.gap2);
-    atomicAdd(&cnt->st_gap3, w.gap3);
+    atomicAdd(&cnt->st_diag, d);
+    atomicAdd(&cnt->st_gap2, g2);
+    atomicAdd(&cnt->st_gap3, g3);
     atomicAdd(&cnt->st_emitted, w.hits);
     atomicAdd(&cnt->st_chain_bytes, w.bytes);
     if (w.reused) atomicAdd(&cnt->st_reused, w.reused);

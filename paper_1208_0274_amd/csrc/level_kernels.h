@@ -451,6 +451,9 @@ __global__ void __launch_bounds__(64) k_expand_level_wide(SearchArgs a, const No
         }
     }
     hit_release(hr, o.hkeys, o.hscores, caps.hits, cnt);
+    diag = wave_sum_u64(diag);  // per-lane partial counts of the row updates
+    gap2 = wave_sum_u64(gap2);
+    gap3 = wave_sum_u64(gap3);
     if (lane == 0) {
         atomicAdd(&cnt->st_nodes, (unsigned long long)((nw > blockIdx.x) ? (nw - 1 - blockIdx.x) / gridDim.x + 1 : 0));
         atomicAdd(&cnt->st_entries, entries);

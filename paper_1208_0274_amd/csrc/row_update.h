@@ -323,6 +323,34 @@ __device__ void child_row(const SearchArgs &a, const Entry *prow, uint32_t plen,
 // Wave helpers (wave64)
 // ---------------------------------------------------------------------------
 
+// Cross-lane moves through DPP (no LDS round trip).  Row ops act within
+// each 16-lane row; a lane with no source keeps `old`.
+constexpr int kDppWaveShl1 = 0x130;   // lane L reads lane L+1
+constexpr int kDppWaveShr1 = 0x138;   // lane L reads lane L-1
+constexpr int kDppRowShr = 0x110;     // + n: lane L reads lane L-n of its row
+constexpr int kDppRowBcast15 = 0x142; // lane 15 of a row to the next row
+constexpr int kDppRowBcast31 = 0x143; // lane 31 to rows 2 and 3
+
+template <int CTRL, int ROW_MASK = 0xF>
+__device__ inline uint32_t dpp(uint32_t old, uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)v, CTRL, ROW_MASK, 0xF, false);
+}
+
+__device__ inline uint32_t lane_up1(uint32_t v) { return dpp<kDppWaveShr1>(v, v); }    // lane 0 keeps its own
+__device__ inline uint32_t lane_down1(uint32_t v) { return dpp<kDppWaveShl1>(v, v); }  // lane 63 keeps its own
+__device__ inline int32_t lane_up1(int32_t v) { return (int32_t)lane_up1((uint32_t)v); }
+
+// Inclusive prefix sum over the 64 lanes.
+__device__ inline uint32_t wave_incl_add_u32(uint32_t v) {
+    v += dpp<kDppRowShr + 1>(0u, v);
+    v += dpp<kDppRowShr + 2>(0u, v);
+    v += dpp<kDppRowShr + 4>(0u, v);
+    v += dpp<kDppRowShr + 8>(0u, v);
+    v += dpp<kDppRowBcast15, 0xA>(0u, v);
+    v += dpp<kDppRowBcast31, 0xC>(0u, v);
+    return v;
+}
+
 __device__ inline unsigned long long wave_excl_scan_u64(unsigned long long v, unsigned long long *total) {
     const int lane = threadIdx.x & 63;
     unsigned long long inc = v;
@@ -336,14 +364,8 @@ __device__ inline unsigned long long wave_excl_scan_u64(unsigned long long v, un
 }
 
 __device__ inline uint32_t wave_excl_scan_u32(uint32_t v, uint32_t *total) {
-    const int lane = threadIdx.x & 63;
-    uint32_t inc = v;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const uint32_t o = __shfl_up(inc, d, 64);
-        if (lane >= d) inc += o;
-    }
-    *total = __shfl(inc, 63, 64);
+    const uint32_t inc = wave_incl_add_u32(v);
+    *total = (uint32_t)__builtin_amdgcn_readlane((int)inc, 63);
     return inc - v;
 }
 
@@ -355,28 +377,48 @@ __device__ inline unsigned long long wave_sum_u64(unsigned long long v) {
 
 // Exclusive max-scan of (key, tag) over the lanes of a wave; ties keep the
 // lower lane.  ex: max over lanes below (kNegKey if none); all: over all lanes.
+// The key moves as two 32-bit halves; kNegKey is the identity.
 __device__ inline void wave_excl_max(int64_t key, uint32_t tag, int64_t &ex_key, uint32_t &ex_tag, int64_t &all_key,
                                      uint32_t &all_tag) {
-    const int lane = threadIdx.x & 63;
-    int64_t k = key;
-    uint32_t t = tag;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const int64_t ok = __shfl_up(k, d, 64);
-        const uint32_t ot = __shfl_up(t, d, 64);
-        if (lane >= d && ok >= k) {
+    const uint32_t nlo = (uint32_t)(uint64_t)kNegKey, nhi = (uint32_t)((uint64_t)kNegKey >> 32);
+    auto join = [](uint32_t lo, uint32_t hi) { return (int64_t)(((uint64_t)hi << 32) | lo); };
+    // shift by one lane: lane L starts from lane L-1's value (lane 0 from the identity)
+    uint32_t lo = dpp<kDppWaveShr1>(nlo, (uint32_t)(uint64_t)key);
+    uint32_t hi = dpp<kDppWaveShr1>(nhi, (uint32_t)((uint64_t)key >> 32));
+    uint32_t tg = dpp<kDppWaveShr1>(0u, tag);
+    int64_t k = join(lo, hi);
+    auto step = [&](uint32_t olo, uint32_t ohi, uint32_t otg) {
+        const int64_t ok = join(olo, ohi);
+        if (ok >= k) {  // the incoming value comes from lower lanes: it wins ties
             k = ok;
-            t = ot;
+            tg = otg;
         }
+    };
+#define ALAE_MAX_STEP(CTRL, MASK)                                                          \
+    {                                                                                      \
+        const uint32_t klo = (uint32_t)(uint64_t)k, khi = (uint32_t)((uint64_t)k >> 32);   \
+        step(dpp<CTRL, MASK>(nlo, klo), dpp<CTRL, MASK>(nhi, khi), dpp<CTRL, MASK>(0u, tg)); \
     }
-    all_key = __shfl(k, 63, 64);
-    all_tag = __shfl(t, 63, 64);
-    ex_key = __shfl_up(k, 1, 64);
-    ex_tag = __shfl_up(t, 1, 64);
-    if (lane == 0) {
-        ex_key = kNegKey;
-        ex_tag = 0;
+    ALAE_MAX_STEP(kDppRowShr + 1, 0xF)
+    ALAE_MAX_STEP(kDppRowShr + 2, 0xF)
+    ALAE_MAX_STEP(kDppRowShr + 4, 0xF)
+    ALAE_MAX_STEP(kDppRowShr + 8, 0xF)
+    ALAE_MAX_STEP(kDppRowBcast15, 0xA)
+    ALAE_MAX_STEP(kDppRowBcast31, 0xC)
+#undef ALAE_MAX_STEP
+    ex_key = k;
+    ex_tag = tg;
+    // over all lanes: lane 63's exclusive value against its own
+    int64_t a63 = k;
+    uint32_t t63 = tg;
+    if (!(k >= key)) {
+        a63 = key;
+        t63 = tag;
     }
+    const uint32_t alo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(uint64_t)a63, 63);
+    const uint32_t ahi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)a63 >> 32), 63);
+    all_key = join(alo, ahi);
+    all_tag = (uint32_t)__builtin_amdgcn_readlane((int)t63, 63);
 }
 
 // ---------------------------------------------------------------------------
@@ -515,15 +557,15 @@ __device__ inline void wide_child_row(const SearchArgs &a, const Row cur, uint32
             e.yM = 0;
             e.yGa = 0;
         }
-        uint32_t pcol = __shfl_up(e.col, 1, 64);
-        int32_t pM = __shfl_up(e.M, 1, 64);
-        uint32_t pyM = __shfl_up(e.yM, 1, 64);
+        uint32_t pcol = lane_up1(e.col);
+        int32_t pM = lane_up1(e.M);
+        uint32_t pyM = lane_up1(e.yM);
         if (lane == 0) {
             pcol = c_pcol;
             pM = c_pM;
             pyM = c_pyM;
         }
-        uint32_t ncol = __shfl_down(e.col, 1, 64);
+        uint32_t ncol = lane_down1(e.col);
         if (lane == 63) ncol = (k + 1 < len) ? cur.load(k + 1).col : kNone;
         if (k + 1 >= len) ncol = kNone;
         // column A = e.col: diagonal from the previous entry and G_a
@@ -710,14 +752,14 @@ __device__ inline void wide_child_row(const SearchArgs &a, const Row cur, uint32
             else
                 ++c1;
         }
-        diag += wave_sum_u64(c1);
-        gap2 += wave_sum_u64(c2);
-        gap3 += wave_sum_u64(c3);
+        diag += c1;  // per lane; the callers reduce over the wave
+        gap2 += c2;
+        gap3 += c3;
         // carries for the next round
         const int lastlane = (int)((len - base - 1) < 63u ? (len - base - 1) : 63u);
-        c_pcol = __shfl(e.col, lastlane, 64);
-        c_pM = __shfl(e.M, lastlane, 64);
-        c_pyM = __shfl(e.yM, lastlane, 64);
+        c_pcol = (uint32_t)__builtin_amdgcn_readlane((int)e.col, lastlane);
+        c_pM = __builtin_amdgcn_readlane(e.M, lastlane);
+        c_pyM = (uint32_t)__builtin_amdgcn_readlane((int)e.yM, lastlane);
         if (allk > c_key) {
             c_key = allk;
             c_tag = allt;
