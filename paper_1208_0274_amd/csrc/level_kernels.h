@@ -216,14 +216,16 @@ __global__ void __launch_bounds__(kLevelBlock) k_expand_level(SearchArgs a, cons
             use_prow = prow;
         }
     }
-    // allocate this wave's output with one atomic per buffer
-    unsigned long long t_nodes, t_wide, t_ent, t_ch, t_ce, t_hits;
-    const unsigned long long p_nodes = wave_excl_scan_u64(n.nodes, &t_nodes);
-    const unsigned long long p_wide = wave_excl_scan_u64(n.wide, &t_wide);
-    const unsigned long long p_ent = wave_excl_scan_u64(n.entries, &t_ent);
-    const unsigned long long p_ch = wave_excl_scan_u64(n.chains, &t_ch);
-    const unsigned long long p_ce = wave_excl_scan_u64(n.centries, &t_ce);
-    const unsigned long long p_hits = wave_excl_scan_u64(n.hits, &t_hits);
+    // allocate this wave's output with one atomic per buffer (per-wave counts fit 32 bits)
+    uint32_t u_nodes, u_wide, u_ent, u_ch, u_ce, u_hits;
+    const unsigned long long p_nodes = wave_excl_scan_u32(n.nodes, &u_nodes);
+    const unsigned long long p_wide = wave_excl_scan_u32(n.wide, &u_wide);
+    const unsigned long long p_ent = wave_excl_scan_u32(n.entries, &u_ent);
+    const unsigned long long p_ch = wave_excl_scan_u32(n.chains, &u_ch);
+    const unsigned long long p_ce = wave_excl_scan_u32(n.centries, &u_ce);
+    const unsigned long long p_hits = wave_excl_scan_u32(n.hits, &u_hits);
+    const unsigned long long t_nodes = u_nodes, t_wide = u_wide, t_ent = u_ent, t_ch = u_ch, t_ce = u_ce,
+                             t_hits = u_hits;
     const int lane = threadIdx.x & 63;
     unsigned long long b_nodes = 0, b_wide = 0, b_ent = 0, b_ch = 0, b_ce = 0, b_hits = 0;
     if (lane == 0) {
@@ -242,12 +244,12 @@ __global__ void __launch_bounds__(kLevelBlock) k_expand_level(SearchArgs a, cons
         if (b_hits + t_hits > caps.hits) of |= kOvHits;
         if (of) atomicOr(&cnt->overflow, of);
     }
-    b_nodes = __shfl(b_nodes, 0, 64);
-    b_wide = __shfl(b_wide, 0, 64);
-    b_ent = __shfl(b_ent, 0, 64);
-    b_ch = __shfl(b_ch, 0, 64);
-    b_ce = __shfl(b_ce, 0, 64);
-    b_hits = __shfl(b_hits, 0, 64);
+    b_nodes = bcast0_u64(b_nodes);
+    b_wide = bcast0_u64(b_wide);
+    b_ent = bcast0_u64(b_ent);
+    b_ch = bcast0_u64(b_ch);
+    b_ce = bcast0_u64(b_ce);
+    b_hits = bcast0_u64(b_hits);
     const bool fits = b_nodes + t_nodes <= caps.nodes && b_wide + t_wide <= caps.lwnodes &&
                       b_ent + t_ent <= caps.entries && b_ch + t_ch <= caps.cnodes && b_ce + t_ce <= caps.centries;
     if (active && fits) {
@@ -306,14 +308,14 @@ __global__ void __launch_bounds__(kLevelBlock) k_expand_level(SearchArgs a, cons
             expand_node<true>(a, nd, use_prow, d1, n2, w, caps, st);
         }
     }
-    const unsigned long long s_nodes = wave_sum_u64(active ? 1 : 0);
-    const unsigned long long s_ent = wave_sum_u64(n.entries + n.centries);
-    const unsigned long long s_diag = wave_sum_u64(st[0]);
-    const unsigned long long s_g2 = wave_sum_u64(st[1]);
-    const unsigned long long s_g3 = wave_sum_u64(st[2]);
-    const unsigned long long s_occ = wave_sum_u64(st[3]);
+    const unsigned long long s_nodes = wave_sum_u32(active ? 1u : 0u);
+    const unsigned long long s_ent = wave_sum_u32(n.entries + n.centries);
+    const unsigned long long s_diag = wave_sum_u32(st[0]);
+    const unsigned long long s_g2 = wave_sum_u32(st[1]);
+    const unsigned long long s_g3 = wave_sum_u32(st[2]);
+    const unsigned long long s_occ = wave_sum_u32(st[3]);
     const unsigned long long s_in =
-        wave_sum_u64(active ? (unsigned long long)(sizeof(Node) + nd.len * sizeof(Entry)) : 0ull);
+        wave_sum_u32(active ? (uint32_t)(sizeof(Node) + nd.len * sizeof(Entry)) : 0u);
     if (lane == 0) {
         if (s_nodes) atomicAdd(&cnt->st_nodes, s_nodes);
         if (s_ent) atomicAdd(&cnt->st_entries, s_ent);

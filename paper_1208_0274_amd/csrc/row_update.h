@@ -351,6 +351,17 @@ __device__ inline uint32_t wave_incl_add_u32(uint32_t v) {
     return v;
 }
 
+__device__ inline uint32_t wave_sum_u32(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_add_u32(v), 63);
+}
+
+// Lane 0's value in every lane.
+__device__ inline unsigned long long bcast0_u64(unsigned long long v) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, 0);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), 0);
+    return ((unsigned long long)hi << 32) | lo;
+}
+
 __device__ inline unsigned long long wave_excl_scan_u64(unsigned long long v, unsigned long long *total) {
     const int lane = threadIdx.x & 63;
     unsigned long long inc = v;
