@@ -144,6 +144,7 @@ __global__ void __launch_bounds__(kLevelBlock) k_expand_level(SearchArgs a, cons
     uint32_t ch_lo[4] = {0, 0, 0, 0}, ch_hi[4] = {0, 0, 0, 0}, ch_n[4] = {0, 0, 0, 0};
     bool staged = false;
     const Entry *use_prow = nullptr;  // parent row of the two-pass path (LDS copy or global)
+    uint32_t nxt4 = kNoNext;
     if (active) {
         const Entry *prow = ent + nd.off;
         if (nd.len >= 1 && nd.len <= (uint32_t)kParent) {
@@ -158,6 +159,9 @@ __global__ void __launch_bounds__(kLevelBlock) k_expand_level(SearchArgs a, cons
             parent[2] = e2;
             parent[3] = e3;
             prow = parent;
+            // query codes after each entry's column (the query has readable slack at its end)
+            nxt4 = (uint32_t)a.query[e0.col + 1] | ((uint32_t)a.query[e1.col + 1] << 8) |
+                   ((uint32_t)a.query[e2.col + 1] << 16) | ((uint32_t)a.query[e3.col + 1] << 24);
         }
         if (a.sigma == 4) {
             uint32_t o_lo[4] = {0, 0, 0, 0}, o_hi[4] = {0, 0, 0, 0};
@@ -184,7 +188,7 @@ __global__ void __launch_bounds__(kLevelBlock) k_expand_level(SearchArgs a, cons
                 s.hit_cap = 0;  // count hits now, write them after the allocation
                 const bool multi = l < r;
                 if (!multi) s.emit_hits = false;
-                child_row<true>(a, prow, nd.len, c, d1, false, 0, s);
+                child_row<true>(a, prow, nd.len, c, d1, false, 0, s, nullptr, nxt4);
                 if (s.n_entries > s.cap) {
                     staged = false;
                     continue;
