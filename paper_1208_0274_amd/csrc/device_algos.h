@@ -25,8 +25,13 @@ hipError_t radix_sort_pairs(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, 
 // Given hit records sorted by key, keep one record per key with the largest
 // score (Algorithm 1's "keep the larger score").  flags/pos hold n+1 words
 // each, tmp scan_scratch_words(n+1).  *count_dev receives the distinct count.
+// Hit keys (query end << 32) | text end become (query end << low_bits) | text
+// end, and the padding key ~0 becomes 2^total_bits - 1 (above every real key),
+// so that the sort reads total_bits bits only.
+hipError_t repack_hit_keys(uint64_t *keys, uint64_t n, int low_bits, int total_bits, hipStream_t s);
+// low_bits > 0: the keys are repacked and are written back in the unpacked form.
 hipError_t max_merge_sorted(const uint64_t *keys, const uint32_t *scores, uint64_t n, uint64_t *out_keys,
                             uint32_t *out_scores, uint32_t *flags, uint32_t *pos, uint32_t *tmp,
-                            hipStream_t s);
+                            hipStream_t s, int low_bits = 0);
 
 }  // namespace alae

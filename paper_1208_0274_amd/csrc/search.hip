@@ -1315,7 +1315,12 @@ static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64
         if ((st = grow_pair(ws->hkeys_alt, ws->hscores_alt, ws->alt_cap, emitted, 0, s)) != ALAE_OK) return st;
         uint64_t need = std::max(radix_scratch_words(emitted), scan_scratch_words(emitted + 1));
         if ((st = grow(ws->scratch, ws->scratch_cap, need, false, 0, s)) != ALAE_OK) return st;
-        const int bits = 32 + std::max(1, bit_length(m - 1));
+        // sort on (query end, text end) packed into as few bits as the sizes need
+        const int tb = std::max(1, bit_length(idx->n - 1));  // text ends are below n
+        const int qb = std::max(1, bit_length(m - 1));
+        int bits = qb + tb;
+        if ((m - 1) == (1ull << qb) - 1 && (idx->n - 1) == (1ull << tb) - 1) ++bits;  // keep the padding key on top
+        HIP_TRY(repack_hit_keys(ws->hkeys, emitted, tb, bits, s));
         bool in_alt = false;
         HIP_TRY(radix_sort_pairs(ws->hkeys, ws->hscores, ws->hkeys_alt, ws->hscores_alt, emitted, bits, ws->scratch,
                                  &in_alt, s));
@@ -1325,7 +1330,7 @@ static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64
         if ((st = grow(ws->pos, ws->pos_cap, emitted + 1, false, 0, s)) != ALAE_OK) return st;
         if ((st = grow_pair(ws->res_keys, ws->res_scores, ws->res_cap, emitted, 0, s)) != ALAE_OK) return st;
         const uint64_t valid = emitted - padding;
-        HIP_TRY(max_merge_sorted(k, v, valid, ws->res_keys, ws->res_scores, ws->flags, ws->pos, ws->scratch, s));
+        HIP_TRY(max_merge_sorted(k, v, valid, ws->res_keys, ws->res_scores, ws->flags, ws->pos, ws->scratch, s, tb));
         uint32_t cnt32 = 0;
         HIP_TRY(hipEventRecord(ws->evk1, s));
         HIP_TRY(hipMemcpyAsync(&cnt32, ws->pos + valid, sizeof(uint32_t), hipMemcpyDeviceToHost, s));

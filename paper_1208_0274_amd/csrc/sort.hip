@@ -76,19 +76,26 @@ __global__ void __launch_bounds__(kThreads) scan_add(uint32_t *out, uint64_t n, 
     }
 }
 
-__global__ void __launch_bounds__(kThreads) radix_hist(const uint64_t *keys, uint64_t n, int shift,
-                                                       uint32_t *hist, uint32_t nblocks) {
-    __shared__ uint32_t cnt[256];
-    cnt[threadIdx.x] = 0;
+// LSD radix sort with 11-bit digits (2048 bins): a block ranks a tile of
+// kSortTile keys; ranks within a wave come from ballots, and only the bins a
+// round touches are updated (by one leader lane per bin and wave).
+constexpr int kDigit = 11;
+constexpr int kBins = 1 << kDigit;
+constexpr int kSortItems = 64;
+constexpr int kSortTile = kThreads * kSortItems;
+
+__global__ void __launch_bounds__(kThreads) radix_hist(const uint64_t *keys, uint64_t n, int shift, uint32_t *hist,
+                                                       uint32_t nblocks) {
+    __shared__ uint32_t cnt[kBins];
+    for (int b = threadIdx.x; b < kBins; b += kThreads) cnt[b] = 0;
     __syncthreads();
-    const uint64_t base = (uint64_t)blockIdx.x * kTile;
-#pragma unroll
-    for (int r = 0; r < kItems; ++r) {
-        uint64_t i = base + (uint64_t)r * kThreads + threadIdx.x;
-        if (i < n) atomicAdd(&cnt[(keys[i] >> shift) & 255u], 1u);
+    const uint64_t base = (uint64_t)blockIdx.x * kSortTile;
+    for (int r = 0; r < kSortItems; ++r) {
+        const uint64_t i = base + (uint64_t)r * kThreads + threadIdx.x;
+        if (i < n) atomicAdd(&cnt[(keys[i] >> shift) & (kBins - 1)], 1u);
     }
     __syncthreads();
-    hist[(uint64_t)threadIdx.x * nblocks + blockIdx.x] = cnt[threadIdx.x];
+    for (int b = threadIdx.x; b < kBins; b += kThreads) hist[(uint64_t)b * nblocks + blockIdx.x] = cnt[b];
 }
 
 // Stable scatter: elements of a tile are ranked in index order (round, wave,
@@ -96,32 +103,36 @@ __global__ void __launch_bounds__(kThreads) radix_hist(const uint64_t *keys, uin
 __global__ void __launch_bounds__(kThreads) radix_scatter(const uint64_t *kin, const uint32_t *vin, uint64_t *kout,
                                                           uint32_t *vout, uint64_t n, int shift,
                                                           const uint32_t *offs, uint32_t nblocks) {
-    __shared__ uint32_t run[256];
-    __shared__ uint32_t wcnt[kWaves][256];
+    __shared__ uint32_t run[kBins];
+    __shared__ uint32_t wcnt[kWaves][kBins];
     const int tid = threadIdx.x;
     const int wave = tid >> 6;
     const int lane = tid & 63;
-    run[tid] = offs[(uint64_t)tid * nblocks + blockIdx.x];
+    for (int b = tid; b < kBins; b += kThreads) {
+        run[b] = offs[(uint64_t)b * nblocks + blockIdx.x];
 #pragma unroll
-    for (int w = 0; w < kWaves; ++w) wcnt[w][tid] = 0;
+        for (int w = 0; w < kWaves; ++w) wcnt[w][b] = 0;
+    }
     __syncthreads();
-    const uint64_t base = (uint64_t)blockIdx.x * kTile;
+    const uint64_t base = (uint64_t)blockIdx.x * kSortTile;
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    for (int r = 0; r < kItems; ++r) {
+    for (int r = 0; r < kSortItems; ++r) {
         const uint64_t i = base + (uint64_t)r * kThreads + tid;
         const bool valid = i < n;
         const uint64_t k = valid ? kin[i] : 0ull;
         const uint32_t v = valid ? vin[i] : 0u;
-        const uint32_t d = (uint32_t)(k >> shift) & 255u;
+        const uint32_t d = (uint32_t)(k >> shift) & (kBins - 1);
         uint64_t peers = __ballot(valid);
 #pragma unroll
-        for (int b = 0; b < 8; ++b) {
+        for (int b = 0; b < kDigit; ++b) {
             const bool bit = (d >> b) & 1u;
             const uint64_t bal = __ballot(bit);
             peers &= bit ? bal : ~bal;
         }
         const uint32_t rank = (uint32_t)__popcll(peers & below);
-        if (valid && rank == 0) wcnt[wave][d] = (uint32_t)__popcll(peers);
+        const uint32_t same = (uint32_t)__popcll(peers);
+        const bool leader = valid && rank == 0;
+        if (leader) wcnt[wave][d] = same;
         __syncthreads();
         if (valid) {
             uint32_t pos = run[d] + rank;
@@ -130,13 +141,10 @@ __global__ void __launch_bounds__(kThreads) radix_scatter(const uint64_t *kin, c
             vout[pos] = v;
         }
         __syncthreads();
-        uint32_t add = 0;
-#pragma unroll
-        for (int w = 0; w < kWaves; ++w) {
-            add += wcnt[w][tid];
-            wcnt[w][tid] = 0;
+        if (leader) {
+            atomicAdd(&run[d], same);
+            wcnt[wave][d] = 0;
         }
-        run[tid] += add;
         __syncthreads();
     }
 }
@@ -148,7 +156,7 @@ __global__ void merge_flags(const uint64_t *keys, uint64_t n, uint32_t *flags) {
 }
 
 __global__ void merge_write(const uint64_t *keys, const uint32_t *scores, uint64_t n, const uint32_t *flags,
-                            const uint32_t *pos, uint64_t *out_keys, uint32_t *out_scores) {
+                            const uint32_t *pos, uint64_t *out_keys, uint32_t *out_scores, int low_bits) {
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n || !flags[i]) return;
     const uint64_t key = keys[i];
@@ -157,8 +165,17 @@ __global__ void merge_write(const uint64_t *keys, const uint32_t *scores, uint64
         int32_t s = (int32_t)scores[j];
         best = s > best ? s : best;
     }
-    out_keys[pos[i]] = key;
+    // packed keys (high part << low_bits | low part) go back to (high << 32) | low
+    const uint64_t out = low_bits ? ((key >> low_bits) << 32) | (key & ((1ull << low_bits) - 1)) : key;
+    out_keys[pos[i]] = out;
     out_scores[pos[i]] = (uint32_t)best;
+}
+
+__global__ void repack_keys(uint64_t *keys, uint64_t n, int low_bits, uint64_t pad) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint64_t k = keys[i];
+    keys[i] = k == ~0ull ? pad : ((k >> 32) << low_bits) | (k & 0xFFFFFFFFull);
 }
 
 uint64_t ceil_div(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
@@ -188,8 +205,8 @@ hipError_t scan_exclusive_u32(const uint32_t *in, uint32_t *out, uint64_t n, uin
 }
 
 uint64_t radix_scratch_words(uint64_t n) {
-    const uint64_t blocks = ceil_div(n ? n : 1, kTile);
-    const uint64_t hist = 256 * blocks;
+    const uint64_t blocks = ceil_div(n ? n : 1, kSortTile);
+    const uint64_t hist = (uint64_t)kBins * blocks;
     return hist + scan_scratch_words(hist);
 }
 
@@ -197,17 +214,17 @@ hipError_t radix_sort_pairs(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, 
                             int bits, uint32_t *scratch, bool *result_in_alt, hipStream_t s) {
     *result_in_alt = false;
     if (n <= 1 || bits <= 0) return hipSuccess;
-    const uint32_t blocks = (uint32_t)ceil_div(n, kTile);
+    const uint32_t blocks = (uint32_t)ceil_div(n, kSortTile);
     uint32_t *hist = scratch;
-    uint32_t *tmp = scratch + 256ull * blocks;
+    uint32_t *tmp = scratch + (uint64_t)kBins * blocks;
     uint64_t *kin = keys, *kout = keys_alt;
     uint32_t *vin = vals, *vout = vals_alt;
     bool alt = false;
-    for (int shift = 0; shift < bits; shift += 8) {
+    for (int shift = 0; shift < bits; shift += kDigit) {
         radix_hist<<<blocks, kThreads, 0, s>>>(kin, n, shift, hist, blocks);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        e = scan_exclusive_u32(hist, hist, 256ull * blocks, tmp, s);
+        e = scan_exclusive_u32(hist, hist, (uint64_t)kBins * blocks, tmp, s);
         if (e != hipSuccess) return e;
         radix_scatter<<<blocks, kThreads, 0, s>>>(kin, vin, kout, vout, n, shift, hist, blocks);
         e = hipGetLastError();
@@ -220,9 +237,16 @@ hipError_t radix_sort_pairs(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, 
     return hipSuccess;
 }
 
+hipError_t repack_hit_keys(uint64_t *keys, uint64_t n, int low_bits, int total_bits, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    const uint64_t pad = total_bits >= 64 ? ~0ull : ((1ull << total_bits) - 1);
+    repack_keys<<<(uint32_t)ceil_div(n, 256), 256, 0, s>>>(keys, n, low_bits, pad);
+    return hipGetLastError();
+}
+
 hipError_t max_merge_sorted(const uint64_t *keys, const uint32_t *scores, uint64_t n, uint64_t *out_keys,
                             uint32_t *out_scores, uint32_t *flags, uint32_t *pos, uint32_t *tmp,
-                            hipStream_t s) {
+                            hipStream_t s, int low_bits) {
     const uint32_t threads = 256;
     const uint32_t grid = (uint32_t)ceil_div(n + 1, threads);
     merge_flags<<<grid, threads, 0, s>>>(keys, n, flags);
@@ -232,7 +256,7 @@ hipError_t max_merge_sorted(const uint64_t *keys, const uint32_t *scores, uint64
     if (e != hipSuccess) return e;
     if (n == 0) return hipSuccess;
     merge_write<<<(uint32_t)ceil_div(n, threads), threads, 0, s>>>(keys, scores, n, flags, pos, out_keys,
-                                                                   out_scores);
+                                                                   out_scores, low_bits);
     return hipGetLastError();
 }
 
