@@ -82,6 +82,29 @@ def cpu_baseline(w, budget_s: float):
                       f"host has {cores} cores"}
 
 
+def measured_traffic():
+    """HBM bytes per launch of k_expand_level from the committed rocprofv3
+    counter summary (FETCH_SIZE and WRITE_SIZE scaled by a device-copy
+    calibration), or None when the kernel sources changed since it was taken."""
+    import hashlib
+    import re
+
+    path = os.path.join(ROOT, "profiles", "k_expand_level_traffic.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m_b = re.search(r"traffic_bytes_per_launch: (\d+)", text)
+    m_h = re.search(r"source_hash: ([0-9a-f]+)", text)
+    if not m_b or not m_h:
+        return None
+    h = hashlib.sha256()
+    for f in ("level_kernels.h", "row_update.h", "device_common.h"):
+        h.update(open(os.path.join(ROOT, "paper_1208_0274_amd", "csrc", f), "rb").read())
+    if h.hexdigest()[:16] != m_h.group(1):
+        return None
+    return int(m_b.group(1))
+
+
 def learned_scheduling(alae, ws, dq, H, sc, steps, plain_ms):
     """Trace one search, train the work predictor on the GPU, then time the
     search with the learned order + partition of the walkers' queues."""
@@ -262,6 +285,7 @@ def main():
     launches = max(1, st.level_lane_launches)
     alg_bytes = st.level_alg_bytes()
     achieved = alg_bytes / (level_ms * 1e-3) / 1e9 if level_ms > 0 else 0.0
+    traffic = measured_traffic()  # HBM bytes per launch, rocprofv3 counters
     out = {
         "metric": METRIC,
         "value": m * n / (ms * 1e-3),
@@ -287,7 +311,8 @@ def main():
                        "sort_merge": float(np.mean([s.merge_ms for s in stats]))},
         "search_stats": {k: (float(v) if isinstance(v, float) else int(v)) for k, v in st.as_dict().items()},
         "roofline": {"kernel": "k_expand_level", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "traffic_GBps": (traffic / (level_ms / launches * 1e-3) / 1e9) if traffic else None,
                      "alg_bytes_per_launch": alg_bytes / launches, "avg_launch_ms": level_ms / launches,
                      "launches_per_step": int(st.level_lane_launches)},
     }
