@@ -63,35 +63,72 @@ __device__ inline bool dominated(const SearchArgs &a, const int8_t *sub, int64_t
     return dom;
 }
 
-// Gapped form: the local alignment score ending at (x-1, y-1) computed inside
-// the window T[x-K..x-1] x P[y-K..y-1] (a lower bound of the true one).
+// Gapped form: the best local alignment score ending exactly at (x-1, y-1),
+// computed inside the window T[x-K..x-1] x P[y-K..y-1] and within a band of
+// kGapBand diagonals on either side of the one through (x-1, y-1) (a lower
+// bound of the true score, so the test stays sufficient).  Band cell k of
+// window row i is column j = i + off + k; the band's H and vertical-gap
+// values live in registers, updated in place with k ascending (cell k reads
+// the previous row at k and k+1 and this row at k-1).
+constexpr int kGapBand = 8;
+
 __device__ inline bool dominated_gapped(const SearchArgs &a, int64_t x, int64_t y) {
+    constexpr int W = kGapBand, B = 2 * kGapBand + 1;
     const int64_t yl = y - (int64_t)seg_beg_of(a, (uint32_t)y);
-    const int rows = (int)(x < kGapWindow ? x : kGapWindow);
-    const int cols = (int)(yl < kGapWindow ? yl : kGapWindow);
-    if (rows == 0 || cols == 0) return false;
+    const int R = (int)(x < kGapWindow ? x : kGapWindow);
+    const int C = (int)(yl < kGapWindow ? yl : kGapWindow);
+    if (R == 0 || C == 0) return false;
     const int32_t open = a.sg + a.ss;
-    int32_t Hr[kGapWindow + 1], Er[kGapWindow + 1];
-    for (int j = 0; j <= cols; ++j) {
-        Hr[j] = 0;
-        Er[j] = kNeg;
+    const int off = C - R;           // column of band cell 0 in row i is i + off
+    const int64_t q0 = y - C;        // query index of window column 0
+    int32_t Hb[B], Eb[B];
+    uint32_t qc[B];                  // query code of each band cell's column in the current row
+#pragma unroll
+    for (int k = 0; k < B; ++k) {
+        Hb[k] = 0;  // the row above the window: local-alignment boundary
+        Eb[k] = kNeg;
+        const int j = off + k - W - 1;  // columns of row -1; shifted in before row 0
+        const bool in = j >= 0 && j < C;
+        const uint32_t v = a.query[q0 + (in ? j : 0)];  // the index stays inside the window
+        qc[k] = in ? v : 0xFFu;
     }
-    for (int i = 1; i <= rows; ++i) {
-        const int tc = a.text[x - rows + i - 1];
-        const int8_t *pc = a.prof + (size_t)tc * a.m + (y - cols);
-        int32_t Hleft = 0, F = kNeg, Hdiag = 0;
-        for (int j = 1; j <= cols; ++j) {
-            const int32_t E = imax(Er[j] + a.ss, Hr[j] + open);
+    for (int i = 0; i < R; ++i) {
+        // slide the band one column to the right
+#pragma unroll
+        for (int k = 0; k < B - 1; ++k) qc[k] = qc[k + 1];
+        {
+            const int j = i + off + W;
+            const bool in = j >= 0 && j < C;
+            const uint32_t v = a.query[q0 + (in ? j : 0)];
+            qc[B - 1] = in ? v : 0xFFu;
+        }
+        const uint32_t tc = a.text[x - R + i];
+        const int8_t *prow = a.prof + (size_t)tc * a.m;
+        int32_t Hleft = kNeg, F = kNeg;
+#pragma unroll
+        for (int k = 0; k < B; ++k) {
+            const int j = i + off + k - W;
+            const bool inside = j >= 0 && j < C;
+            const int32_t upH = k + 1 < B ? Hb[k + 1] : kNeg;
+            const int32_t upE = k + 1 < B ? Eb[k + 1] : kNeg;
+            const int32_t E = imax(upE + a.ss, upH + open);
             F = imax(F + a.ss, Hleft + open);
-            int32_t h = imax(Hdiag + pc[j - 1], imax(E, F));
+            int32_t s;
+            if (a.matrix_mode)
+                s = (int32_t)prow[q0 + (inside ? j : 0)];
+            else
+                s = tc == qc[k] ? a.s_match : a.s_mismatch;
+            int32_t h = imax(Hb[k] + s, imax(E, F));
             h = imax(h, 0);
-            Hdiag = Hr[j];
-            Hr[j] = h;
-            Er[j] = E;
-            Hleft = h;
+            if (j < 0) h = 0;             // left of the window: where alignments start
+            const bool live = inside || j < 0;
+            Hb[k] = live ? h : kNeg;     // right of the window: never part of an alignment to the corner
+            Eb[k] = inside ? E : kNeg;
+            Hleft = Hb[k];
+            if (!inside) F = kNeg;
         }
     }
-    return Hr[cols] > 0;
+    return Hb[W] > 0;  // band cell W of the last row is column C-1
 }
 
 // ---------------------------------------------------------------------------
