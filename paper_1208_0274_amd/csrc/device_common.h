@@ -215,6 +215,7 @@ struct Counters {
     kCounter t_gen0, t_gen1;  // first start / last end of lane-walker waves (100 MHz clock)
     kCounter t_live0, t_live1;  // same for the live wave pass
     kCounter t_push0;         // first item published to the live pass
+    kCounter tasks;           // child tasks of the current level (node phase)
 };
 
 // Key of an unused hit slot: sorts after every real (column, text end) key.
@@ -224,7 +225,8 @@ constexpr uint64_t kPadKey = ~0ull;
 constexpr unsigned long long kOvNodes = 1, kOvEntries = 2, kOvHits = 4, kOvChainNodes = 8, kOvChainEntries = 16,
                              kOvWideNodes = 32, kOvWideEntries = 64, kOvWideRow = 128, kOvSpillNodes = 256,
                              kOvSpillEntries = 512, kOvLevelWide = 1024, kOvGeneralNodes = 2048,
-                             kOvGeneralEntries = 4096, kOvStageRow = 8192;
+                             kOvGeneralEntries = 4096, kOvStageRow = 8192,
+                             kOvTasks = 16384;
 
 struct Caps {
     unsigned long long nodes;
@@ -241,6 +243,7 @@ struct Caps {
     unsigned long long gnodes;    // general chain queue
     unsigned long long gentries;
     unsigned long long srow;      // entries per staging buffer of the level-wide kernel
+    unsigned long long tasks;     // child tasks of one level
 };
 
 struct SubTable {

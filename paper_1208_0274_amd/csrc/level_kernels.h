@@ -32,220 +32,155 @@ struct LevelOut {
     unsigned long long node_base, wide_base, ent_base, chain_base, cent_base, hit_base;
 };
 
-struct LevelCounts {
-    uint32_t nodes, wide, entries, chains, centries, hits;
-};
+// Child rows are computed into a per-lane LDS stage of kStage entries; the
+// wave then allocates its outputs with one atomic per buffer and each lane
+// copies its stage out.  A longer child row is counted first and computed
+// again straight into its allocated place.
+constexpr int kStage = 8;
+constexpr int kStageWords = kStage * 5 + 1;  // one pad word: lanes start in different banks
+constexpr int kLevelBlock = 128;
 
-// WRITE == false counts what the node will write; WRITE == true writes it at
-// the bases the wave allocated.
-template <bool WRITE>
-__device__ void expand_node(const SearchArgs &a, const Node &nd, const Entry *prow, int32_t d1, LevelCounts &n,
-                            const LevelOut &o, Caps caps, uint32_t st[5]) {
-    n.nodes = n.wide = n.entries = n.chains = n.centries = n.hits = 0;
+// ---------------------------------------------------------------------------
+// Two phases per level: the node phase turns every node (one lane each) into
+// child tasks (node, c, BWT range) for its non-empty children; the child
+// phase computes one child row per lane.  A wave of the child phase then runs
+// one row update for 64 children instead of four (mostly empty) child passes
+// for 64 nodes.
+// ---------------------------------------------------------------------------
+struct ChildTask {
+    uint32_t node;  // index in the level's node list
+    uint32_t c;     // character appended
+    uint32_t lo, hi;
+};
+static_assert(sizeof(ChildTask) == 16, "child task is 16 bytes");
+
+__global__ void __launch_bounds__(256) k_level_tasks(SearchArgs a, const Node *nodes, uint32_t nn, ChildTask *tasks,
+                                                     Caps caps, Counters *cnt) {
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool active = t < nn;
+    uint32_t mask = 0, nocc = 0, nin = 0;
+    Node nd{0, 0, 0, 0};
     uint32_t o_lo[4] = {0, 0, 0, 0}, o_hi[4] = {0, 0, 0, 0};
-    if (a.sigma == 4) {
-        occ4_dna(a, (int64_t)nd.lo - 1, o_lo);
-        occ4_dna(a, (int64_t)nd.hi, o_hi);
-    }
-    if (!WRITE) {
-        const int bc = a.sigma == 4 ? kDnaBlockChars : kGenBlockChars;
-        const int64_t b0 = nd.lo == 0 ? -1 : ((int64_t)nd.lo - 1) / bc;
-        const int64_t b1 = (int64_t)nd.hi / bc;
-        st[3] += (b0 >= 0 && b0 != b1) ? 2u : 1u;
-    }
-    for (int c = 0; c < a.sigma; ++c) {
-        int64_t l, r;
+    if (active) {
+        nd = nodes[t];
+        nin = (uint32_t)(sizeof(Node) + nd.len * sizeof(Entry));
         if (a.sigma == 4) {
-            l = (int64_t)a.C[c] + o_lo[c];
-            r = (int64_t)a.C[c] + o_hi[c] - 1;
+            occ4_dna(a, (int64_t)nd.lo - 1, o_lo);
+            occ4_dna(a, (int64_t)nd.hi, o_hi);
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                if (o_hi[c] > o_lo[c]) mask |= 1u << c;
+            const int64_t b0 = nd.lo == 0 ? -1 : ((int64_t)nd.lo - 1) / kDnaBlockChars;
+            const int64_t b1 = (int64_t)nd.hi / kDnaBlockChars;
+            nocc = (b0 >= 0 && b0 != b1) ? 2u : 1u;
         } else {
-            l = (int64_t)a.C[c] + occ1_gen(a, c, (int64_t)nd.lo - 1);
-            r = (int64_t)a.C[c] + occ1_gen(a, c, (int64_t)nd.hi) - 1;
+            for (int c = 0; c < a.sigma; ++c)
+                if (occ1_gen(a, c, (int64_t)nd.hi) > occ1_gen(a, c, (int64_t)nd.lo - 1)) mask |= 1u << c;
+            const int64_t b0 = nd.lo == 0 ? -1 : ((int64_t)nd.lo - 1) / kGenBlockChars;
+            const int64_t b1 = (int64_t)nd.hi / kGenBlockChars;
+            nocc = (b0 >= 0 && b0 != b1) ? 4u : 2u;  // 128-byte blocks, two granules each
         }
-        if (l > r) continue;
-        RowSink s;
-        sink_init(s);
-        s.lo = (uint32_t)l;
-        s.hi = (uint32_t)r;
-        const bool multi = l < r;
-        if (!multi) s.emit_hits = false;  // located and emitted by the chain kernel
-        if (WRITE) {
-            s.out = multi ? o.oent + o.ent_base + n.entries : o.cent + o.cent_base + n.centries;
-            s.hkeys = o.hkeys;
-            s.hscores = o.hscores;
-            s.hit_base = o.hit_base + n.hits;
-            s.hit_cap = caps.hits;
+    }
+    const uint32_t ntask = (uint32_t)__popc(mask);
+    uint32_t tot;
+    const uint32_t pre = wave_excl_scan_u32(ntask, &tot);
+    unsigned long long base = 0;
+    const int lane = threadIdx.x & 63;
+    if (lane == 0 && tot) {
+        base = atomicAdd(&cnt->tasks, (unsigned long long)tot);
+        if (base + tot > caps.tasks) atomicOr(&cnt->overflow, kOvTasks);
+    }
+    base = bcast0_u64(base) + pre;
+    if (a.sigma == 4) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            if (!(mask & (1u << c))) continue;
+            if (base < caps.tasks) tasks[base] = ChildTask{t, (uint32_t)c, a.C[c] + o_lo[c], a.C[c] + o_hi[c] - 1};
+            ++base;
         }
-        child_row<WRITE>(a, prow, nd.len, c, d1, false, 0, s);
-        n.hits += s.n_hits;
-        if (WRITE) {
-            st[0] += s.st_diag;
-            st[1] += s.st_gap2;
-            st[2] += s.st_gap3;
+    } else {
+        for (uint32_t mm = mask; mm; mm &= mm - 1) {
+            const int c = __ffs(mm) - 1;
+            const uint32_t lo = a.C[c] + occ1_gen(a, c, (int64_t)nd.lo - 1);
+            const uint32_t hi = a.C[c] + occ1_gen(a, c, (int64_t)nd.hi) - 1;
+            if (base < caps.tasks) tasks[base] = ChildTask{t, (uint32_t)c, lo, hi};
+            ++base;
         }
-        if (s.n_entries == 0) continue;
-        if (multi) {
-            if (WRITE) {
-                Node cn;
-                cn.lo = s.lo;
-                cn.hi = s.hi;
-                cn.off = (uint32_t)(o.ent_base + n.entries);
-                cn.len = s.n_entries;
-                if (s.n_entries > kLaneRow)
-                    o.owide[o.wide_base + n.wide] = cn;
-                else
-                    o.onodes[o.node_base + n.nodes] = cn;
-            }
-            if (s.n_entries > kLaneRow)
-                n.wide++;
-            else
-                n.nodes++;
-            n.entries += s.n_entries;
-        } else {
-            if (WRITE) {
-                Node cn;
-                cn.lo = (uint32_t)l;
-                cn.hi = (uint32_t)d1;
-                cn.off = (uint32_t)(o.cent_base + n.centries);
-                cn.len = s.n_entries;
-                o.chains[o.chain_base + n.chains] = cn;
-            }
-            n.chains++;
-            n.centries += s.n_entries;
-        }
+    }
+    const uint32_t s_occ = wave_sum_u32(nocc), s_nodes = wave_sum_u32(active ? 1u : 0u), s_in = wave_sum_u32(nin);
+    if (lane == 0) {
+        if (s_occ) atomicAdd(&cnt->st_occ_reads, (unsigned long long)s_occ);
+        if (s_nodes) atomicAdd(&cnt->st_nodes, (unsigned long long)s_nodes);
+        if (s_in) atomicAdd(&cnt->st_frontier_bytes, (unsigned long long)s_in);
     }
 }
 
-// Child rows of a node are computed once into a per-lane LDS stage of
-// kStage entries; the wave then allocates its outputs with one atomic per
-// buffer and each lane copies its stage out.  A node whose children do not
-// fit the stage is counted and written by two passes of expand_node instead.
-// A parent row of at most kParent entries is copied to LDS first, with its
-// loads issued together, so that the row updates read it at LDS latency.
-constexpr int kStage = 8;
-constexpr int kParent = 4;
-constexpr int kStageWords = (kStage + kParent) * 5 + 1;  // one pad word: lanes start in different banks
-constexpr int kLevelBlock = 128;
-
-__global__ void __launch_bounds__(kLevelBlock) k_expand_level(SearchArgs a, const Node *nodes, uint32_t nn,
-                                                              const Entry *ent, int32_t d1, LevelOut o, Caps caps,
-                                                              Counters *cnt) {
+// One child row per lane, staged in LDS.
+__global__ void __launch_bounds__(kLevelBlock) k_expand_children(SearchArgs a, const Node *nodes, const Entry *ent,
+                                                                 const ChildTask *tasks, int32_t d1, LevelOut o,
+                                                                 Caps caps, Counters *cnt) {
     __shared__ uint32_t s_stage[kLevelBlock * kStageWords];
+    const uint64_t ntasks = cnt->tasks;  // written by the node phase before this launch
     const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-    const bool active = t < nn;
-    Node nd;
-    nd.lo = nd.hi = nd.off = nd.len = 0;
-    if (active) nd = nodes[t];
+    if ((uint64_t)blockIdx.x * blockDim.x >= ntasks) return;  // whole block past the end
+    const bool active = t < ntasks && t < caps.tasks;
     Entry *stage = reinterpret_cast<Entry *>(s_stage + threadIdx.x * kStageWords);
-    Entry *parent = stage + kStage;
-    LevelCounts n = {0, 0, 0, 0, 0, 0};
-    uint32_t st[5] = {0, 0, 0, 0, 0};
-    // children: BWT range and staged entry count (entries 0 .. used-1 of the stage, in child order)
-    uint32_t ch_lo[4] = {0, 0, 0, 0}, ch_hi[4] = {0, 0, 0, 0}, ch_n[4] = {0, 0, 0, 0};
-    bool staged = false;
-    const Entry *use_prow = nullptr;  // parent row of the two-pass path (LDS copy or global)
-    uint32_t nxt4 = kNoNext;
+    ChildTask tk{0, 0, 1, 0};
+    Node nd{0, 0, 0, 0};
     if (active) {
-        const Entry *prow = ent + nd.off;
-        if (nd.len >= 1 && nd.len <= (uint32_t)kParent) {
-            // four independent loads (indexes clamped into the row), then the LDS copy
-            const uint32_t last = nd.len - 1;
-            const Entry e0 = prow[0];
-            const Entry e1 = prow[last < 1 ? last : 1];
-            const Entry e2 = prow[last < 2 ? last : 2];
-            const Entry e3 = prow[last < 3 ? last : 3];
-            parent[0] = e0;
-            parent[1] = e1;
-            parent[2] = e2;
-            parent[3] = e3;
-            prow = parent;
-            // query codes after each entry's column (the query has readable slack at its end)
-            nxt4 = (uint32_t)a.query[e0.col + 1] | ((uint32_t)a.query[e1.col + 1] << 8) |
-                   ((uint32_t)a.query[e2.col + 1] << 16) | ((uint32_t)a.query[e3.col + 1] << 24);
-        }
-        if (a.sigma == 4) {
-            uint32_t o_lo[4] = {0, 0, 0, 0}, o_hi[4] = {0, 0, 0, 0};
-            occ4_dna(a, (int64_t)nd.lo - 1, o_lo);
-            occ4_dna(a, (int64_t)nd.hi, o_hi);
-            const int64_t b0 = nd.lo == 0 ? -1 : ((int64_t)nd.lo - 1) / kDnaBlockChars;
-            const int64_t b1 = (int64_t)nd.hi / kDnaBlockChars;
-            st[3] += (b0 >= 0 && b0 != b1) ? 2u : 1u;
-            staged = true;
-            uint32_t used = 0;
-#pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                const int64_t l = (int64_t)a.C[c] + o_lo[c];
-                const int64_t r = (int64_t)a.C[c] + o_hi[c] - 1;
-                ch_lo[c] = (uint32_t)l;
-                ch_hi[c] = (uint32_t)r;
-                if (!staged || l > r) continue;
-                RowSink s;
-                sink_init(s);
-                s.lo = (uint32_t)l;
-                s.hi = (uint32_t)r;
-                s.out = stage + used;
-                s.cap = (uint32_t)kStage - used;
-                s.hit_cap = 0;  // count hits now, write them after the allocation
-                const bool multi = l < r;
-                if (!multi) s.emit_hits = false;
-                child_row<true>(a, prow, nd.len, c, d1, false, 0, s, nullptr, nxt4);
-                if (s.n_entries > s.cap) {
-                    staged = false;
-                    continue;
-                }
-                st[0] += s.st_diag;
-                st[1] += s.st_gap2;
-                st[2] += s.st_gap3;
-                ch_n[c] = s.n_entries;
-                used += s.n_entries;
-                n.hits += s.n_hits;
-                if (s.n_entries == 0) continue;
-                if (multi) {
-                    if (s.n_entries > kLaneRow)
-                        n.wide++;
-                    else
-                        n.nodes++;
-                    n.entries += s.n_entries;
-                } else {
-                    n.chains++;
-                    n.centries += s.n_entries;
-                }
-            }
-        }
-        if (!staged) {  // the stage overflowed, or a protein alphabet: two passes
-            n = LevelCounts{0, 0, 0, 0, 0, 0};
-            st[0] = st[1] = st[2] = 0;
-            uint32_t dummy[5] = {0, 0, 0, 0, 0};
-            expand_node<false>(a, nd, prow, d1, n, o, caps, a.sigma == 4 ? dummy : st);
-            use_prow = prow;
-        }
+        tk = tasks[t];
+        nd = nodes[tk.node];
     }
-    // allocate this wave's output with one atomic per buffer (per-wave counts fit 32 bits)
+    const Entry *prow = ent + nd.off;
+    const bool multi = tk.lo < tk.hi;
+    bool staged = true;
+    uint32_t n_ent = 0, n_hits = 0, st_d = 0, st_2 = 0, st_3 = 0;
+    if (active) {
+        RowSink s;
+        sink_init(s);
+        s.lo = tk.lo;
+        s.hi = tk.hi;
+        s.out = stage;
+        s.cap = (uint32_t)kStage;
+        s.hit_cap = 0;  // count hits now, write them after the allocation
+        if (!multi) s.emit_hits = false;
+        child_row<true>(a, prow, nd.len, (int)tk.c, d1, false, 0, s);
+        n_ent = s.n_entries;
+        n_hits = s.n_hits;
+        st_d = s.st_diag;
+        st_2 = s.st_gap2;
+        st_3 = s.st_gap3;
+        staged = s.n_entries <= s.cap;
+    }
+    const bool has = active && n_ent > 0;
+    const uint32_t c_node = has && multi && n_ent <= (uint32_t)kLaneRow ? 1u : 0u;
+    const uint32_t c_wide = has && multi && n_ent > (uint32_t)kLaneRow ? 1u : 0u;
+    const uint32_t c_ent = has && multi ? n_ent : 0u;
+    const uint32_t c_ch = has && !multi ? 1u : 0u;
+    const uint32_t c_ce = has && !multi ? n_ent : 0u;
     uint32_t u_nodes, u_wide, u_ent, u_ch, u_ce, u_hits;
-    const unsigned long long p_nodes = wave_excl_scan_u32(n.nodes, &u_nodes);
-    const unsigned long long p_wide = wave_excl_scan_u32(n.wide, &u_wide);
-    const unsigned long long p_ent = wave_excl_scan_u32(n.entries, &u_ent);
-    const unsigned long long p_ch = wave_excl_scan_u32(n.chains, &u_ch);
-    const unsigned long long p_ce = wave_excl_scan_u32(n.centries, &u_ce);
-    const unsigned long long p_hits = wave_excl_scan_u32(n.hits, &u_hits);
-    const unsigned long long t_nodes = u_nodes, t_wide = u_wide, t_ent = u_ent, t_ch = u_ch, t_ce = u_ce,
-                             t_hits = u_hits;
+    const unsigned long long p_nodes = wave_excl_scan_u32(c_node, &u_nodes);
+    const unsigned long long p_wide = wave_excl_scan_u32(c_wide, &u_wide);
+    const unsigned long long p_ent = wave_excl_scan_u32(c_ent, &u_ent);
+    const unsigned long long p_ch = wave_excl_scan_u32(c_ch, &u_ch);
+    const unsigned long long p_ce = wave_excl_scan_u32(c_ce, &u_ce);
+    const unsigned long long p_hits = wave_excl_scan_u32(n_hits, &u_hits);
     const int lane = threadIdx.x & 63;
     unsigned long long b_nodes = 0, b_wide = 0, b_ent = 0, b_ch = 0, b_ce = 0, b_hits = 0;
     if (lane == 0) {
-        if (t_nodes) b_nodes = atomicAdd(&cnt->nodes, t_nodes);
-        if (t_wide) b_wide = atomicAdd(&cnt->lwnodes, t_wide);
-        if (t_ent) b_ent = atomicAdd(&cnt->entries, t_ent);
-        if (t_ch) b_ch = atomicAdd(&cnt->cnodes, t_ch);
-        if (t_ce) b_ce = atomicAdd(&cnt->centries, t_ce);
-        if (t_hits) b_hits = atomicAdd(&cnt->hits, t_hits);
+        if (u_nodes) b_nodes = atomicAdd(&cnt->nodes, (unsigned long long)u_nodes);
+        if (u_wide) b_wide = atomicAdd(&cnt->lwnodes, (unsigned long long)u_wide);
+        if (u_ent) b_ent = atomicAdd(&cnt->entries, (unsigned long long)u_ent);
+        if (u_ch) b_ch = atomicAdd(&cnt->cnodes, (unsigned long long)u_ch);
+        if (u_ce) b_ce = atomicAdd(&cnt->centries, (unsigned long long)u_ce);
+        if (u_hits) b_hits = atomicAdd(&cnt->hits, (unsigned long long)u_hits);
         unsigned long long of = 0;
-        if (b_nodes + t_nodes > caps.nodes) of |= kOvNodes;
-        if (b_wide + t_wide > caps.lwnodes) of |= kOvLevelWide;
-        if (b_ent + t_ent > caps.entries) of |= kOvEntries;
-        if (b_ch + t_ch > caps.cnodes) of |= kOvChainNodes;
-        if (b_ce + t_ce > caps.centries) of |= kOvChainEntries;
-        if (b_hits + t_hits > caps.hits) of |= kOvHits;
+        if (b_nodes + u_nodes > caps.nodes) of |= kOvNodes;
+        if (b_wide + u_wide > caps.lwnodes) of |= kOvLevelWide;
+        if (b_ent + u_ent > caps.entries) of |= kOvEntries;
+        if (b_ch + u_ch > caps.cnodes) of |= kOvChainNodes;
+        if (b_ce + u_ce > caps.centries) of |= kOvChainEntries;
+        if (b_hits + u_hits > caps.hits) of |= kOvHits;
         if (of) atomicOr(&cnt->overflow, of);
     }
     b_nodes = bcast0_u64(b_nodes);
@@ -254,82 +189,59 @@ __global__ void __launch_bounds__(kLevelBlock) k_expand_level(SearchArgs a, cons
     b_ch = bcast0_u64(b_ch);
     b_ce = bcast0_u64(b_ce);
     b_hits = bcast0_u64(b_hits);
-    const bool fits = b_nodes + t_nodes <= caps.nodes && b_wide + t_wide <= caps.lwnodes &&
-                      b_ent + t_ent <= caps.entries && b_ch + t_ch <= caps.cnodes && b_ce + t_ce <= caps.centries;
-    if (active && fits) {
-        LevelOut w = o;
-        w.node_base = b_nodes + p_nodes;
-        w.wide_base = b_wide + p_wide;
-        w.ent_base = b_ent + p_ent;
-        w.chain_base = b_ch + p_ch;
-        w.cent_base = b_ce + p_ce;
-        w.hit_base = b_hits + p_hits;
+    const bool fits = b_nodes + u_nodes <= caps.nodes && b_wide + u_wide <= caps.lwnodes &&
+                      b_ent + u_ent <= caps.entries && b_ch + u_ch <= caps.cnodes && b_ce + u_ce <= caps.centries;
+    if (has && fits) {
+        Entry *dst = multi ? o.oent + b_ent + p_ent : o.cent + b_ce + p_ce;
+        const uint32_t off = (uint32_t)(multi ? b_ent + p_ent : b_ce + p_ce);
+        if (multi) {
+            if (c_wide)
+                o.owide[b_wide + p_wide] = Node{tk.lo, tk.hi, off, n_ent};
+            else
+                o.onodes[b_nodes + p_nodes] = Node{tk.lo, tk.hi, off, n_ent};
+        } else {
+            o.chains[b_ch + p_ch] = Node{tk.lo, (uint32_t)d1, off, n_ent};
+        }
+        unsigned long long hslot = b_hits + p_hits;
         if (staged) {
-            uint32_t used = 0, k_nodes = 0, k_wide = 0, k_ent = 0, k_ch = 0, k_ce = 0;
-            unsigned long long hslot = w.hit_base;
-#pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                const uint32_t len = ch_n[c];
-                if (len == 0) continue;
-                const Entry *src = stage + used;
-                used += len;
-                const bool multi = ch_lo[c] < ch_hi[c];
-                Node cn;
-                Entry *dst;
-                if (multi) {
-                    cn.lo = ch_lo[c];
-                    cn.hi = ch_hi[c];
-                    cn.off = (uint32_t)(w.ent_base + k_ent);
-                    dst = o.oent + w.ent_base + k_ent;
-                    k_ent += len;
-                    if (len > kLaneRow)
-                        o.owide[w.wide_base + k_wide++] = Node{cn.lo, cn.hi, cn.off, len};
-                    else
-                        o.onodes[w.node_base + k_nodes++] = Node{cn.lo, cn.hi, cn.off, len};
-                } else {
-                    cn.lo = ch_lo[c];
-                    cn.hi = (uint32_t)d1;
-                    cn.off = (uint32_t)(w.cent_base + k_ce);
-                    dst = o.cent + w.cent_base + k_ce;
-                    k_ce += len;
-                    o.chains[w.chain_base + k_ch++] = Node{cn.lo, cn.hi, cn.off, len};
-                }
-                for (uint32_t k = 0; k < len; ++k) {
-                    const Entry e = src[k];
-                    dst[k] = e;
-                    if (multi && e.M >= a.H) {  // hits at every occurrence (chains emit their own)
-                        for (uint32_t h = ch_lo[c]; h <= ch_hi[c]; ++h, ++hslot) {
-                            if (hslot < caps.hits) {
-                                o.hkeys[hslot] = ((uint64_t)e.col << 32) | a.sa[h];
-                                o.hscores[hslot] = (uint32_t)e.M;
-                            }
+            for (uint32_t k = 0; k < n_ent; ++k) {
+                const Entry e = stage[k];
+                dst[k] = e;
+                if (multi && e.M >= a.H) {  // hits at every occurrence (chains emit their own)
+                    for (uint32_t h = tk.lo; h <= tk.hi; ++h, ++hslot) {
+                        if (hslot < caps.hits) {
+                            o.hkeys[hslot] = ((uint64_t)e.col << 32) | a.sa[h];
+                            o.hscores[hslot] = (uint32_t)e.M;
                         }
                     }
                 }
             }
-        } else {
-            LevelCounts n2;
-            expand_node<true>(a, nd, use_prow, d1, n2, w, caps, st);
+        } else {  // second pass straight to the allocated place
+            RowSink s;
+            sink_init(s);
+            s.lo = tk.lo;
+            s.hi = tk.hi;
+            s.out = dst;
+            s.cap = n_ent;
+            s.hkeys = o.hkeys;
+            s.hscores = o.hscores;
+            s.hit_base = hslot;
+            s.hit_cap = caps.hits;
+            if (!multi) s.emit_hits = false;
+            child_row<true>(a, prow, nd.len, (int)tk.c, d1, false, 0, s);
         }
     }
-    const unsigned long long s_nodes = wave_sum_u32(active ? 1u : 0u);
-    const unsigned long long s_ent = wave_sum_u32(n.entries + n.centries);
-    const unsigned long long s_diag = wave_sum_u32(st[0]);
-    const unsigned long long s_g2 = wave_sum_u32(st[1]);
-    const unsigned long long s_g3 = wave_sum_u32(st[2]);
-    const unsigned long long s_occ = wave_sum_u32(st[3]);
-    const unsigned long long s_in =
-        wave_sum_u32(active ? (uint32_t)(sizeof(Node) + nd.len * sizeof(Entry)) : 0u);
+    const uint32_t s_ent = wave_sum_u32(n_ent), s_d = wave_sum_u32(st_d), s_2 = wave_sum_u32(st_2),
+                   s_3 = wave_sum_u32(st_3);
     if (lane == 0) {
-        if (s_nodes) atomicAdd(&cnt->st_nodes, s_nodes);
-        if (s_ent) atomicAdd(&cnt->st_entries, s_ent);
-        if (s_diag) atomicAdd(&cnt->st_diag, s_diag);
-        if (s_g2) atomicAdd(&cnt->st_gap2, s_g2);
-        if (s_g3) atomicAdd(&cnt->st_gap3, s_g3);
-        if (s_occ) atomicAdd(&cnt->st_occ_reads, s_occ);
-        atomicAdd(&cnt->st_frontier_bytes, s_in + (t_nodes + t_wide + t_ch) * sizeof(Node) +
-                                               (t_ent + t_ce) * sizeof(Entry) + t_hits * 12ull);
-        if (t_hits) atomicAdd(&cnt->st_emitted, t_hits);
+        if (s_ent) atomicAdd(&cnt->st_entries, (unsigned long long)s_ent);
+        if (s_d) atomicAdd(&cnt->st_diag, (unsigned long long)s_d);
+        if (s_2) atomicAdd(&cnt->st_gap2, (unsigned long long)s_2);
+        if (s_3) atomicAdd(&cnt->st_gap3, (unsigned long long)s_3);
+        const unsigned long long tb = (unsigned long long)(u_nodes + u_wide + u_ch) * sizeof(Node) +
+                                      (unsigned long long)(u_ent + u_ce) * sizeof(Entry) + u_hits * 12ull;
+        if (tb) atomicAdd(&cnt->st_frontier_bytes, tb);
+        if (u_hits) atomicAdd(&cnt->st_emitted, (unsigned long long)u_hits);
     }
 }
 

@@ -239,22 +239,12 @@ __device__ inline void emit_entry(const SearchArgs &a, RowSink &s, uint32_t col,
 // (diagonal); G_b (a query character against a gap) runs left to right along
 // the row, also through columns with no candidate.  check_dom applies the
 // ungapped domination test for the occurrence starting at text position x.
-//
-// nxt4 (match/mismatch scoring, rows of at most four entries) holds in byte k
-// the query code after parent entry k's column, loaded by the caller together
-// with the row, so that the diagonal scores need no dependent profile loads.
-constexpr uint32_t kNoNext = 0xFFFFFFFFu;
-
 template <bool WRITE>
 __device__ void child_row(const SearchArgs &a, const Entry *prow, uint32_t plen, int c, int32_t d1, bool check_dom,
-                          int64_t x, RowSink &s, const int8_t *sub = nullptr, uint32_t nxt4 = kNoNext) {
+                          int64_t x, RowSink &s, const int8_t *sub = nullptr) {
     const int8_t *pc = a.prof + (size_t)c * a.m;
-    const bool fast = nxt4 != kNoNext && !a.matrix_mode && plen <= 4;
-    // score of the diagonal step into the column after parent entry k
-    auto diag_after = [&](uint32_t k, uint32_t col) -> int32_t {
-        if (fast) return ((nxt4 >> (8 * k)) & 0xFFu) == (uint32_t)c ? a.s_match : a.s_mismatch;
-        return pc[col + 1];
-    };
+    // score of the diagonal step into the column after col
+    auto diag_after = [&](uint32_t col) -> int32_t { return pc[col + 1]; };
     const int32_t open = a.sg + a.ss;  // first gap character
     const int32_t ext = a.ss;
     const int32_t rowgain = a.smax * (a.lmax - d1);
@@ -344,7 +334,7 @@ __device__ void child_row(const SearchArgs &a, const Entry *prow, uint32_t plen,
         if (k > 0) {
             const Entry p = prow[k - 1];
             if (p.col + 1 == j && p.M > 0 && !seg_first(a, j)) {
-                D = p.M + diag_after(k - 1, p.col);
+                D = p.M + diag_after(p.col);
                 yD = p.yM;
             }
         }
@@ -362,7 +352,7 @@ __device__ void child_row(const SearchArgs &a, const Entry *prow, uint32_t plen,
         column(j, D, yD, Gav, yGav);
         // diagonal into column j+1 when no parent entry sits there
         if (e.M > 0 && j + 1 < seg_end_of(a, j) && !(k + 1 < plen && prow[k + 1].col == j + 1)) {
-            column(j + 1, e.M + diag_after(k, j), e.yM, kNeg, 0);
+            column(j + 1, e.M + diag_after(j), e.yM, kNeg, 0);
         }
     }
     spread_to((int64_t)a.m - 1);

@@ -428,6 +428,9 @@ struct alae_workspace {
     uint64_t left_cap = 0;
     hipStream_t s2 = nullptr;  // the concurrent wave-walker pass
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    // child tasks of a level (node phase -> child phase)
+    ChildTask *tasks = nullptr;
+    uint64_t task_cap = 0;
     // batch segments
     uint32_t *qord = nullptr;
     uint64_t qord_cap = 0;
@@ -503,6 +506,7 @@ static void ws_release(alae_workspace *ws) {
     if (ws->s2) hipStreamDestroy(ws->s2);
     if (ws->ev_fork) hipEventDestroy(ws->ev_fork);
     if (ws->ev_join) hipEventDestroy(ws->ev_join);
+    hipFree(ws->tasks);
     hipFree(ws->qord);
     hipFree(ws->segbeg);
     hipFree(ws->d_off);
@@ -930,6 +934,7 @@ static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64
         caps.wentries = ws->went_cap;
         caps.wrow = wrow;
         caps.srow = srow;
+        caps.tasks = ws->task_cap;
         caps.onodes = ws->onode_cap;
         caps.oentries = ws->oent_cap;
     };
@@ -1000,6 +1005,10 @@ static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64
             z.nodes = z.entries = z.lwnodes = z.cnodes = z.centries = 0;
             z.overflow = 0;
             z.stage_need = 0;
+            z.tasks = 0;
+            if ((st = grow(ws->tasks, ws->task_cap, (uint64_t)sigma * std::max<uint64_t>(nn, 1), false, 0, s)) !=
+                ALAE_OK)
+                return st;
             HIP_TRY(hipMemcpyAsync(ws->d_cnt, &z, sizeof(Counters), hipMemcpyHostToDevice, s));
             set_caps(nxt);
             LevelOut o;
@@ -1012,9 +1021,14 @@ static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64
             o.hscores = ws->hscores;
             o.node_base = o.wide_base = o.ent_base = o.chain_base = o.cent_base = o.hit_base = 0;
             HIP_TRY(hipEventRecord(ws->evk0, s));
-            if (nn > 0)
-                k_expand_level<<<(uint32_t)((nn + kLevelBlock - 1) / kLevelBlock), kLevelBlock, 0, s>>>(
-                    a, ws->nodes[cur], (uint32_t)nn, ws->ents[cur], d1, o, caps, ws->d_cnt);
+            if (nn > 0) {
+                // node phase (child tasks), then one child row per lane
+                k_level_tasks<<<(uint32_t)((nn + 255) / 256), 256, 0, s>>>(a, ws->nodes[cur], (uint32_t)nn,
+                                                                          ws->tasks, caps, ws->d_cnt);
+                const uint64_t maxtasks = (uint64_t)sigma * nn;
+                k_expand_children<<<(uint32_t)((maxtasks + kLevelBlock - 1) / kLevelBlock), kLevelBlock, 0, s>>>(
+                    a, ws->nodes[cur], ws->ents[cur], ws->tasks, d1, o, caps, ws->d_cnt);
+            }
             HIP_TRY(hipEventRecord(ws->evkm, s));
             if (nlw > 0) {
                 const uint32_t blocks =
