@@ -21,7 +21,8 @@ namespace alae {
 
 constexpr int kNarrowRow = 24;
 constexpr int kNgrSlots = 4;
-constexpr int kWideCap = 1024;  // row entries a wave keeps in LDS
+constexpr int kWideCap = 1024;  // row entries a wave walker keeps in LDS
+constexpr int kWideWaves = 4;   // waves of a wave-walker block (one chain per block)
 
 // Eight bytes arr[p .. p+7] as one little-endian word (arr carries kSlack
 // readable bytes around its data).
@@ -761,10 +762,12 @@ __device__ void replay_materialize(Row &cur, uint32_t len, uint32_t K, const uin
 // (len, e_end, depth describe it) and the caller spills it.
 // With reuse on, the row may be held as its first copy (rp.K > 0); on a false
 // return the caller writes out the copies (replay_entry) when it spills.
-template <class Row>
+// W > 1: the block's W waves update each row together (xg: their LDS
+// exchange slots); everything else here is computed alike by every wave.
+template <int W = 1, class Row>
 __device__ bool walk_wide(const SearchArgs &a, Row &cur, Row &nxt, uint32_t &len, uint32_t &e_end, int32_t &depth,
                           uint32_t cap, uint64_t *hkeys, uint32_t *hscores, Caps caps, Counters *cnt, HitRes &hr,
-                          WideStats &w, Replay &rp, uint32_t *deltas) {
+                          WideStats &w, Replay &rp, uint32_t *deltas, RowXchg *xg = nullptr) {
     const int lane = threadIdx.x & 63;
     uint32_t txt = 0;
     int tpos = 64;
@@ -811,7 +814,7 @@ __device__ bool walk_wide(const SearchArgs &a, Row &cur, Row &nxt, uint32_t &len
         o.e_child = e_end + 1;
         o.rK = rp.K;
         o.rdelta = deltas;
-        wide_child_row(a, cur, len, nxt, c, d1, o, hr);
+        wide_child_row<W>(a, cur, len, nxt, c, d1, o, hr, xg);
         __syncthreads();
         w.steps++;
         w.bytes += (unsigned long long)(len + o.len) * 12ull;
@@ -832,23 +835,27 @@ __device__ bool walk_wide(const SearchArgs &a, Row &cur, Row &nxt, uint32_t &len
     }
 }
 
-// w.diag, w.gap2 and w.gap3 are per-lane partial counts; the rest is wave-uniform.
-__device__ inline void wide_stats_flush(Counters *cnt, const WideStats &w) {
+// w.diag, w.gap2 and w.gap3 are per-lane partial counts and w.hits is per
+// wave; the rest is the same in every wave that walked the rows together, so
+// only one of them (uniform = true) adds it.
+__device__ inline void wide_stats_flush(Counters *cnt, const WideStats &w, bool uniform = true) {
     const unsigned long long d = wave_sum_u64(w.diag), g2 = wave_sum_u64(w.gap2), g3 = wave_sum_u64(w.gap3);
     if ((threadIdx.x & 63) != 0) return;
-    atomicAdd(&cnt->st_wide_steps, w.steps);
-    atomicAdd(&cnt->st_entries, w.entries);
     atomicAdd(&cnt->st_diag, d);
     atomicAdd(&cnt->st_gap2, g2);
     atomicAdd(&cnt->st_gap3, g3);
     atomicAdd(&cnt->st_emitted, w.hits);
+    if (!uniform) return;
+    atomicAdd(&cnt->st_wide_steps, w.steps);
+    atomicAdd(&cnt->st_entries, w.entries);
     atomicAdd(&cnt->st_chain_bytes, w.bytes);
     if (w.reused) atomicAdd(&cnt->st_reused, w.reused);
     if (w.replay) atomicAdd(&cnt->st_replay, w.replay);
 }
 
-// Rows in LDS (one wave per block).  A row that outgrows kWideCap entries is
-// spilled to the global spill queue and continued by k_chain_wide_global.
+// Rows in LDS; the kWideWaves waves of a block walk one chain together.  A
+// row that outgrows kWideCap entries is spilled to the global spill queue and
+// continued by k_chain_wide_global.
 // A wave-walker pass that runs while the lane walker still pushes items.
 struct LiveQueue {
     const uint32_t *ready;  // per slot: 0 pending, 1 written, 2 never written (nullptr: static pass)
@@ -863,30 +870,31 @@ struct LiveQueue {
 // from first.  With a live queue, items are claimed in queue order as they
 // are published (order applies to the static part only), and the pass ends
 // when the lane walker has finished and every published item is taken; a
-// wave that sees no progress for `patience` gives its claimed item to the
+// block that sees no progress for `patience` gives its claimed item to the
 // next pass and stops, so the pass always ends.
-__global__ void __launch_bounds__(64) k_chain_wide_lds(SearchArgs a, const Node *witems, uint32_t first,
-                                                       uint32_t nw, const Entry *went, Node *onodes, Entry *oents,
-                                                       uint64_t *hkeys, uint32_t *hscores, Caps caps,
-                                                       Counters *cnt, const uint32_t *order, float *trace_work,
-                                                       LiveQueue live) {
+__global__ void __launch_bounds__(64 * kWideWaves) k_chain_wide_lds(SearchArgs a, const Node *witems, uint32_t first,
+                                                                    uint32_t nw, const Entry *went, Node *onodes,
+                                                                    Entry *oents, uint64_t *hkeys, uint32_t *hscores,
+                                                                    Caps caps, Counters *cnt, const uint32_t *order,
+                                                                    float *trace_work, LiveQueue live) {
     __shared__ uint32_t s_col[2][kWideCap];
     __shared__ int32_t s_M[2][kWideCap];
     __shared__ int32_t s_Ga[2][kWideCap];
     __shared__ uint32_t s_delta[64];
-    const int lane = threadIdx.x & 63;
+    __shared__ RowXchg s_xg;
+    __shared__ unsigned long long s_bc[2];  // thread 0 -> block: claimed slot and state, spill slot and offset
+    const uint32_t tid = threadIdx.x;
+    const bool lead = tid == 0;
+    const bool wave0 = tid < 64;
     HitRes hr = {0, 0, 0};
     WideStats w = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-    if (live.ready && lane == 0) atomicMin(&cnt->t_live0, (unsigned long long)__builtin_amdgcn_s_memrealtime());
+    if (live.ready && lead) atomicMin(&cnt->t_live0, (unsigned long long)__builtin_amdgcn_s_memrealtime());
     for (;;) {
-        unsigned long long it = 0;
-        if (lane == 0) it = atomicAdd(&cnt->wide_head, 1ull);
-        it = __shfl(it, 0, 64);
-        uint32_t item;
-        if (live.ready) {
-            // wait until slot `it` is published, the lane walker is done, or patience runs out
-            int state = 0;  // 1 take, 2 skip, 3 end, 4 give up
-            if (lane == 0) {
+        if (lead) {
+            const unsigned long long it = atomicAdd(&cnt->wide_head, 1ull);
+            int state = 1;  // 1 take, 2 skip, 3 end, 4 give up
+            if (live.ready) {
+                // wait until slot `it` is published, the lane walker is done, or patience runs out
                 unsigned long long seen = ~0ull;
                 uint64_t since = __builtin_amdgcn_s_memrealtime();
                 for (uint32_t poll = 0;; ++poll) {
@@ -936,14 +944,24 @@ __global__ void __launch_bounds__(64) k_chain_wide_lds(SearchArgs a, const Node 
                     const unsigned long long k = atomicAdd(&cnt->missed, 1ull);
                     live.missed[k] = (uint32_t)it;
                 }
+                if (state == 1) __threadfence();
+            } else if (it >= nw) {
+                state = 3;
             }
-            state = __shfl(state, 0, 64);
-            if (state == 2) continue;
-            if (state == 3 || state == 4) break;
+            s_bc[0] = it;
+            s_bc[1] = (unsigned long long)state;
+        }
+        __syncthreads();
+        const unsigned long long it = s_bc[0];
+        const int state = (int)s_bc[1];
+        __syncthreads();  // s_bc is written again below
+        if (state == 2) continue;
+        if (state == 3 || state == 4) break;
+        uint32_t item;
+        if (live.ready) {
             __threadfence();
             item = (it < live.nstatic && order) ? order[it] : (uint32_t)it;
         } else {
-            if (it >= nw) break;
             const uint32_t rel = (uint32_t)it - first;
             item = first + (order ? order[rel] : rel);
         }
@@ -958,10 +976,10 @@ __global__ void __launch_bounds__(64) k_chain_wide_lds(SearchArgs a, const Node 
         Replay rp;
         rp.K = 0;
         if (len <= (uint32_t)kWideCap) {
-            for (uint32_t k = lane; k < len; k += 64) cur.store(k, went[nd.off + k]);
+            for (uint32_t k = tid; k < len; k += blockDim.x) cur.store(k, went[nd.off + k]);
             __syncthreads();
-            done = walk_wide(a, cur, nxt, len, e_end, depth, (uint32_t)kWideCap, hkeys, hscores, caps, cnt, hr, w,
-                             rp, s_delta);
+            done = walk_wide<kWideWaves>(a, cur, nxt, len, e_end, depth, (uint32_t)kWideCap, hkeys, hscores, caps,
+                                         cnt, hr, w, rp, s_delta, &s_xg);
         } else {
             done = false;
         }
@@ -970,20 +988,21 @@ __global__ void __launch_bounds__(64) k_chain_wide_lds(SearchArgs a, const Node 
             // with its copies written out
             const uint32_t part = len;
             len *= rp.K + 1;
-            unsigned long long slot = 0, off = 0;
-            if (lane == 0) {
-                slot = atomicAdd(&cnt->onodes, 1ull);
-                off = atomicAdd(&cnt->oentries, (unsigned long long)len);
+            if (lead) {
+                const unsigned long long slot = atomicAdd(&cnt->onodes, 1ull);
+                const unsigned long long off = atomicAdd(&cnt->oentries, (unsigned long long)len);
                 if (slot >= caps.onodes) atomicOr(&cnt->overflow, kOvSpillNodes);
                 if (off + len > caps.oentries) atomicOr(&cnt->overflow, kOvSpillEntries);
+                s_bc[0] = slot;
+                s_bc[1] = off;
             }
-            slot = __shfl(slot, 0, 64);
-            off = __shfl(off, 0, 64);
+            __syncthreads();
+            const unsigned long long slot = s_bc[0], off = s_bc[1];
             if (slot < caps.onodes && off + len <= caps.oentries) {
                 const bool from_lds = nd.len <= (uint32_t)kWideCap;
-                for (uint32_t k = lane; k < len; k += 64)
+                for (uint32_t k = tid; k < len; k += blockDim.x)
                     oents[off + k] = from_lds ? replay_entry(cur, part, s_delta, k) : went[nd.off + k];
-                if (lane == 0) {
+                if (lead) {
                     Node sn;
                     sn.lo = kUniqueBit | e_end;
                     sn.hi = (uint32_t)depth;
@@ -993,12 +1012,12 @@ __global__ void __launch_bounds__(64) k_chain_wide_lds(SearchArgs a, const Node 
                 }
             }
         }
-        if (trace_work && lane == 0) trace_work[item - first] = (float)(w.entries + w.steps - work0);
+        if (trace_work && lead) trace_work[item - first] = (float)(w.entries + w.steps - work0);
         __syncthreads();
     }
     hit_release(hr, hkeys, hscores, caps.hits, cnt);
-    wide_stats_flush(cnt, w);
-    if (live.ready && lane == 0) atomicMax(&cnt->t_live1, (unsigned long long)__builtin_amdgcn_s_memrealtime());
+    wide_stats_flush(cnt, w, wave0);
+    if (live.ready && lead) atomicMax(&cnt->t_live1, (unsigned long long)__builtin_amdgcn_s_memrealtime());
 }
 
 // Features of chain items (the layout documented with alae_mlp).

@@ -1,8 +1,9 @@
 // Sparse DP row update of a trie node (Section 2.2 recurrences with the
 // filters of Section 3), in two forms:
 //   child_row       -- one lane computes a whole child row sequentially;
-//   wide_child_row  -- one wave computes a child row 64 parent entries at a
-//                      time, with G_b as a wave-level prefix-max scan.
+//   wide_child_row  -- one wave (or the W waves of a block) computes a child
+//                      row 64 (64*W) parent entries at a time, with G_b as a
+//                      wave-level prefix-max scan carried across waves.
 // Both produce the same entries (column, M, G_a, start tags) for the same
 // parent row.
 #pragma once
@@ -570,16 +571,34 @@ struct WideOut {
     // replayed forks: every hit is also emitted at col + rdelta[r], r = 1..rK
     uint32_t rK;
     const uint32_t *rdelta;
-    // results (wave-uniform)
+    // results: len and overflow are uniform over the lanes that update the
+    // row, hits over a wave; diag, gap2 and gap3 are per lane
     uint32_t len;
     bool overflow;
     unsigned long long hits, diag, gap2, gap3;
 };
 
-template <class Row>
+// Exchange slots of a block whose W waves update one row together (LDS);
+// two sets, used by alternate rounds.
+constexpr int kMaxRowWaves = 8;
+struct RowXchg {
+    int64_t key[2][kMaxRowWaves];
+    uint32_t tag[2][kMaxRowWaves];
+    uint32_t cnt[2][kMaxRowWaves];
+};
+
+// W == 1: one wave walks the row 64 parent entries per round, carrying the
+// G_b prefix maximum and the output offset in registers.  W > 1: the block's
+// W waves take 64*W entries per round; the carries of the waves before each
+// one (prefix maximum, output count) pass through xg, with two barriers a
+// round.  Both give the same row.
+template <int W = 1, class Row>
 __device__ inline void wide_child_row(const SearchArgs &a, const Row cur, uint32_t len, const Row nxt, int c,
-                                      int32_t d1, WideOut &o, HitRes &hr) {
+                                      int32_t d1, WideOut &o, HitRes &hr, RowXchg *xg = nullptr) {
+    static_assert(W >= 1 && W <= kMaxRowWaves, "waves per row");
     const int lane = threadIdx.x & 63;
+    const int wave = W > 1 ? (int)(threadIdx.x >> 6) : 0;
+    int par = 0;
     const int8_t *pc = a.prof + (size_t)c * a.m;
     const int32_t open = a.sg + a.ss;
     const int32_t ext = a.ss;
@@ -594,7 +613,8 @@ __device__ inline void wide_child_row(const SearchArgs &a, const Row cur, uint32
     uint32_t out = 0;
     bool overflow = false;
     unsigned long long hits = 0, diag = 0, gap2 = 0, gap3 = 0;
-    for (uint32_t base = 0; base < len; base += 64) {
+    for (uint32_t rbase = 0; rbase < len; rbase += 64u * W) {
+        const uint32_t base = rbase + 64u * (uint32_t)wave;
         const uint32_t k = base + lane;
         const bool valid = k < len;
         Entry e;
@@ -611,9 +631,20 @@ __device__ inline void wide_child_row(const SearchArgs &a, const Row cur, uint32
         int32_t pM = lane_up1(e.M);
         uint32_t pyM = lane_up1(e.yM);
         if (lane == 0) {
-            pcol = c_pcol;
-            pM = c_pM;
-            pyM = c_pyM;
+            if (W == 1) {
+                pcol = c_pcol;
+                pM = c_pM;
+                pyM = c_pyM;
+            } else if (valid && k > 0) {  // the entry before this wave's first
+                const Entry pe = cur.load(k - 1);
+                pcol = pe.col;
+                pM = pe.M;
+                pyM = pe.yM;
+            } else {
+                pcol = kNone;
+                pM = kNeg;
+                pyM = 0;
+            }
         }
         uint32_t ncol = lane_down1(e.col);
         if (lane == 63) ncol = (k + 1 < len) ? cur.load(k + 1).col : kNone;
@@ -660,9 +691,35 @@ __device__ inline void wide_child_row(const SearchArgs &a, const Row cur, uint32
         int64_t exk, allk;
         uint32_t ext_tag, allt;
         wave_excl_max(lk, lt, exk, ext_tag, allk, allt);
-        if (c_key >= exk) {  // earlier rounds come first
-            exk = c_key;
-            ext_tag = c_tag;
+        // carry-in: earlier rounds, then the waves before this one (earlier wins ties)
+        int64_t cin = c_key;
+        uint32_t cint = c_tag;
+        if (W > 1) {
+            if (lane == 0) {
+                xg->key[par][wave] = allk;
+                xg->tag[par][wave] = allt;
+            }
+            __syncthreads();
+            int64_t bk = c_key;
+            uint32_t bt = c_tag;
+#pragma unroll
+            for (int w2 = 0; w2 < W; ++w2) {
+                if (w2 == wave) {
+                    cin = bk;
+                    cint = bt;
+                }
+                const int64_t kk = xg->key[par][w2];
+                if (kk > bk) {
+                    bk = kk;
+                    bt = xg->tag[par][w2];
+                }
+            }
+            allk = bk;  // the whole round, for the next one
+            allt = bt;
+        }
+        if (cin >= exk) {  // earlier rounds come first
+            exk = cin;
+            ext_tag = cint;
         }
         // G_b and M at A
         int32_t GbA = kNeg;
@@ -720,8 +777,22 @@ __device__ inline void wide_child_row(const SearchArgs &a, const Row cur, uint32
         const uint32_t cnt_lane = nA + nB + nspread;
         uint32_t tot;
         const uint32_t pre = wave_excl_scan_u32(cnt_lane, &tot);
+        uint32_t woff = 0;  // entries of the waves before this one
+        if (W > 1) {
+            if (lane == 0) xg->cnt[par][wave] = tot;
+            __syncthreads();
+            uint32_t all = 0;
+#pragma unroll
+            for (int w2 = 0; w2 < W; ++w2) {
+                const uint32_t v = xg->cnt[par][w2];
+                woff += w2 < wave ? v : 0u;
+                all += v;
+            }
+            tot = all;
+            par ^= 1;
+        }
         if (out + tot <= o.cap) {
-            uint32_t p = out + pre;
+            uint32_t p = out + woff + pre;
             if (nA) {
                 Entry w;
                 w.col = e.col;
@@ -806,10 +877,12 @@ __device__ inline void wide_child_row(const SearchArgs &a, const Row cur, uint32
         gap2 += c2;
         gap3 += c3;
         // carries for the next round
-        const int lastlane = (int)((len - base - 1) < 63u ? (len - base - 1) : 63u);
-        c_pcol = (uint32_t)__builtin_amdgcn_readlane((int)e.col, lastlane);
-        c_pM = __builtin_amdgcn_readlane(e.M, lastlane);
-        c_pyM = (uint32_t)__builtin_amdgcn_readlane((int)e.yM, lastlane);
+        if (W == 1) {
+            const int lastlane = (int)((len - base - 1) < 63u ? (len - base - 1) : 63u);
+            c_pcol = (uint32_t)__builtin_amdgcn_readlane((int)e.col, lastlane);
+            c_pM = __builtin_amdgcn_readlane(e.M, lastlane);
+            c_pyM = (uint32_t)__builtin_amdgcn_readlane((int)e.yM, lastlane);
+        }
         if (allk > c_key) {
             c_key = allk;
             c_tag = allt;

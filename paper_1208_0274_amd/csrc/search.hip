@@ -1159,7 +1159,7 @@ static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64
         HIP_TRY(hipEventElapsedTime(&ms, ws->evk0, ws->evk1));
         order_ms = ms;
     }
-    const uint32_t live_blocks = (uint32_t)cus * 2u;
+    const uint32_t live_blocks = (uint32_t)cus * 2u;  // kWideWaves waves each
     if (ng > 0 || nw1 > 0) {
         const Counters before = *ws->h_cnt;
         for (;;) {
@@ -1205,7 +1205,7 @@ static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64
                                                         ws->hkeys, ws->hscores, caps, ws->d_cnt, gq.order, gq.twork,
                                                         tracing ? ws->wsrc : nullptr, ws->ready);
             HIP_TRY(hipGetLastError());
-            k_chain_wide_lds<<<live_blocks, 64, 0, ws->s2>>>(a, ws->wnodes, 0, 0xFFFFFFFFu, ws->wents, ws->onodes,
+            k_chain_wide_lds<<<live_blocks, 64 * kWideWaves, 0, ws->s2>>>(a, ws->wnodes, 0, 0xFFFFFFFFu, ws->wents, ws->onodes,
                                                              ws->oents, ws->hkeys, ws->hscores, caps, ws->d_cnt,
                                                              wq.order, tracing ? ws->qb[1].twork : nullptr, lq);
             HIP_TRY(hipGetLastError());
@@ -1248,7 +1248,7 @@ static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64
             HIP_TRY(hipMemcpyAsync(ws->left, lst.data(), nleft * sizeof(uint32_t), hipMemcpyHostToDevice, s));
             HIP_TRY(hipStreamSynchronize(s));
             const Counters before = *ws->h_cnt;
-            const uint32_t blocks = (uint32_t)std::min<uint64_t>(nleft, (uint64_t)cus * 24u);
+            const uint32_t blocks = (uint32_t)std::min<uint64_t>(nleft, (uint64_t)cus * (24u / kWideWaves));
             LiveQueue none;
             memset(&none, 0, sizeof(none));
             for (;;) {
@@ -1258,7 +1258,7 @@ static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64
                 HIP_TRY(hipMemcpyAsync(ws->d_cnt, &z, sizeof(Counters), hipMemcpyHostToDevice, s));
                 set_caps(cur);
                 HIP_TRY(hipEventRecord(ws->evk0, s));
-                k_chain_wide_lds<<<blocks, 64, 0, s>>>(a, ws->wnodes, 0, (uint32_t)nleft, ws->wents, ws->onodes,
+                k_chain_wide_lds<<<blocks, 64 * kWideWaves, 0, s>>>(a, ws->wnodes, 0, (uint32_t)nleft, ws->wents, ws->onodes,
                                                        ws->oents, ws->hkeys, ws->hscores, caps, ws->d_cnt, ws->left,
                                                        tracing ? ws->qb[1].twork : nullptr, none);
                 if ((st = timed(wide_ms)) != ALAE_OK) return st;
