@@ -36,9 +36,9 @@ struct LevelOut {
 // wave then allocates its outputs with one atomic per buffer and each lane
 // copies its stage out.  A longer child row is counted first and computed
 // again straight into its allocated place.
-constexpr int kStage = 8;
+constexpr int kStage = 4;
 constexpr int kStageWords = kStage * 5 + 1;  // one pad word: lanes start in different banks
-constexpr int kLevelBlock = 128;
+constexpr int kLevelBlock = 256;
 
 // ---------------------------------------------------------------------------
 // Two phases per level: the node phase turns every node (one lane each) into
@@ -54,8 +54,11 @@ struct ChildTask {
 };
 static_assert(sizeof(ChildTask) == 16, "child task is 16 bytes");
 
-__global__ void __launch_bounds__(256) k_level_tasks(SearchArgs a, const Node *nodes, uint32_t nn, ChildTask *tasks,
-                                                     Caps caps, Counters *cnt) {
+constexpr int kTaskBlock = 1024;
+
+__global__ void __launch_bounds__(kTaskBlock) k_level_tasks(SearchArgs a, const Node *nodes, uint32_t nn,
+                                                            ChildTask *tasks, Caps caps, Counters *cnt) {
+    __shared__ BlockReserveLds<4, kTaskBlock / 64> s_res;
     const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
     const bool active = t < nn;
     uint32_t mask = 0, nocc = 0, nin = 0;
@@ -84,13 +87,13 @@ __global__ void __launch_bounds__(256) k_level_tasks(SearchArgs a, const Node *n
     const uint32_t ntask = (uint32_t)__popc(mask);
     uint32_t tot;
     const uint32_t pre = wave_excl_scan_u32(ntask, &tot);
-    unsigned long long base = 0;
-    const int lane = threadIdx.x & 63;
-    if (lane == 0 && tot) {
-        base = atomicAdd(&cnt->tasks, (unsigned long long)tot);
-        if (base + tot > caps.tasks) atomicOr(&cnt->overflow, kOvTasks);
-    }
-    base = bcast0_u64(base) + pre;
+    unsigned long long *const ctr[4] = {&cnt->tasks, &cnt->st_occ_reads, &cnt->st_nodes, &cnt->st_frontier_bytes};
+    const unsigned long long wtot[4] = {tot, wave_sum_u32(nocc), wave_sum_u32(active ? 1u : 0u), wave_sum_u32(nin)};
+    const unsigned long long cap[4] = {caps.tasks, ~0ull, ~0ull, ~0ull};
+    const uint32_t ovb[4] = {kOvTasks, 0, 0, 0};
+    unsigned long long bases[4];
+    block_reserve<4, kTaskBlock / 64>(s_res, ctr, wtot, cap, ovb, &cnt->overflow, bases);
+    unsigned long long base = bases[0] + pre;
     if (a.sigma == 4) {
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
@@ -107,12 +110,6 @@ __global__ void __launch_bounds__(256) k_level_tasks(SearchArgs a, const Node *n
             ++base;
         }
     }
-    const uint32_t s_occ = wave_sum_u32(nocc), s_nodes = wave_sum_u32(active ? 1u : 0u), s_in = wave_sum_u32(nin);
-    if (lane == 0) {
-        if (s_occ) atomicAdd(&cnt->st_occ_reads, (unsigned long long)s_occ);
-        if (s_nodes) atomicAdd(&cnt->st_nodes, (unsigned long long)s_nodes);
-        if (s_in) atomicAdd(&cnt->st_frontier_bytes, (unsigned long long)s_in);
-    }
 }
 
 // One child row per lane, staged in LDS.
@@ -120,6 +117,7 @@ __global__ void __launch_bounds__(kLevelBlock) k_expand_children(SearchArgs a, c
                                                                  const ChildTask *tasks, int32_t d1, LevelOut o,
                                                                  Caps caps, Counters *cnt) {
     __shared__ uint32_t s_stage[kLevelBlock * kStageWords];
+    __shared__ BlockReserveLds<12, kLevelBlock / 64> s_res;
     const uint64_t ntasks = cnt->tasks;  // written by the node phase before this launch
     const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
     if ((uint64_t)blockIdx.x * blockDim.x >= ntasks) return;  // whole block past the end
@@ -165,30 +163,22 @@ __global__ void __launch_bounds__(kLevelBlock) k_expand_children(SearchArgs a, c
     const unsigned long long p_ch = wave_excl_scan_u32(c_ch, &u_ch);
     const unsigned long long p_ce = wave_excl_scan_u32(c_ce, &u_ce);
     const unsigned long long p_hits = wave_excl_scan_u32(n_hits, &u_hits);
-    const int lane = threadIdx.x & 63;
-    unsigned long long b_nodes = 0, b_wide = 0, b_ent = 0, b_ch = 0, b_ce = 0, b_hits = 0;
-    if (lane == 0) {
-        if (u_nodes) b_nodes = atomicAdd(&cnt->nodes, (unsigned long long)u_nodes);
-        if (u_wide) b_wide = atomicAdd(&cnt->lwnodes, (unsigned long long)u_wide);
-        if (u_ent) b_ent = atomicAdd(&cnt->entries, (unsigned long long)u_ent);
-        if (u_ch) b_ch = atomicAdd(&cnt->cnodes, (unsigned long long)u_ch);
-        if (u_ce) b_ce = atomicAdd(&cnt->centries, (unsigned long long)u_ce);
-        if (u_hits) b_hits = atomicAdd(&cnt->hits, (unsigned long long)u_hits);
-        unsigned long long of = 0;
-        if (b_nodes + u_nodes > caps.nodes) of |= kOvNodes;
-        if (b_wide + u_wide > caps.lwnodes) of |= kOvLevelWide;
-        if (b_ent + u_ent > caps.entries) of |= kOvEntries;
-        if (b_ch + u_ch > caps.cnodes) of |= kOvChainNodes;
-        if (b_ce + u_ce > caps.centries) of |= kOvChainEntries;
-        if (b_hits + u_hits > caps.hits) of |= kOvHits;
-        if (of) atomicOr(&cnt->overflow, of);
-    }
-    b_nodes = bcast0_u64(b_nodes);
-    b_wide = bcast0_u64(b_wide);
-    b_ent = bcast0_u64(b_ent);
-    b_ch = bcast0_u64(b_ch);
-    b_ce = bcast0_u64(b_ce);
-    b_hits = bcast0_u64(b_hits);
+    // allocations (6) and statistics (6), one atomic per counter and block
+    unsigned long long *const ctr[12] = {&cnt->nodes,    &cnt->lwnodes,  &cnt->entries,     &cnt->cnodes,
+                                         &cnt->centries, &cnt->hits,     &cnt->st_entries,  &cnt->st_diag,
+                                         &cnt->st_gap2,  &cnt->st_gap3,  &cnt->st_emitted,  &cnt->st_frontier_bytes};
+    const unsigned long long fb = (unsigned long long)(u_nodes + u_wide + u_ch) * sizeof(Node) +
+                                  (unsigned long long)(u_ent + u_ce) * sizeof(Entry) + u_hits * 12ull;
+    const unsigned long long wtot[12] = {u_nodes, u_wide, u_ent, u_ch, u_ce, u_hits, wave_sum_u32(n_ent),
+                                         wave_sum_u32(st_d), wave_sum_u32(st_2), wave_sum_u32(st_3), u_hits, fb};
+    const unsigned long long cap[12] = {caps.nodes, caps.lwnodes, caps.entries, caps.cnodes, caps.centries,
+                                        caps.hits,  ~0ull,        ~0ull,        ~0ull,       ~0ull,
+                                        ~0ull,      ~0ull};
+    const uint32_t ovb[12] = {kOvNodes, kOvLevelWide, kOvEntries, kOvChainNodes, kOvChainEntries, kOvHits,
+                              0,        0,            0,          0,             0,               0};
+    unsigned long long b[12];
+    block_reserve<12, kLevelBlock / 64>(s_res, ctr, wtot, cap, ovb, &cnt->overflow, b);
+    const unsigned long long b_nodes = b[0], b_wide = b[1], b_ent = b[2], b_ch = b[3], b_ce = b[4], b_hits = b[5];
     const bool fits = b_nodes + u_nodes <= caps.nodes && b_wide + u_wide <= caps.lwnodes &&
                       b_ent + u_ent <= caps.entries && b_ch + u_ch <= caps.cnodes && b_ce + u_ce <= caps.centries;
     if (has && fits) {
@@ -230,18 +220,6 @@ __global__ void __launch_bounds__(kLevelBlock) k_expand_children(SearchArgs a, c
             if (!multi) s.emit_hits = false;
             child_row<true>(a, prow, nd.len, (int)tk.c, d1, false, 0, s);
         }
-    }
-    const uint32_t s_ent = wave_sum_u32(n_ent), s_d = wave_sum_u32(st_d), s_2 = wave_sum_u32(st_2),
-                   s_3 = wave_sum_u32(st_3);
-    if (lane == 0) {
-        if (s_ent) atomicAdd(&cnt->st_entries, (unsigned long long)s_ent);
-        if (s_d) atomicAdd(&cnt->st_diag, (unsigned long long)s_d);
-        if (s_2) atomicAdd(&cnt->st_gap2, (unsigned long long)s_2);
-        if (s_3) atomicAdd(&cnt->st_gap3, (unsigned long long)s_3);
-        const unsigned long long tb = (unsigned long long)(u_nodes + u_wide + u_ch) * sizeof(Node) +
-                                      (unsigned long long)(u_ent + u_ce) * sizeof(Entry) + u_hits * 12ull;
-        if (tb) atomicAdd(&cnt->st_frontier_bytes, tb);
-        if (u_hits) atomicAdd(&cnt->st_emitted, (unsigned long long)u_hits);
     }
 }
 

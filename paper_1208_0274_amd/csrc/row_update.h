@@ -426,6 +426,60 @@ __device__ inline unsigned long long wave_sum_u64(unsigned long long v) {
     return v;
 }
 
+// ---------------------------------------------------------------------------
+// Block-wide reservation.  Every wave passes its totals for NC global
+// counters (the same value in all of its lanes); thread 0 adds the block's
+// totals with one atomic per counter, and each wave gets back its first slot
+// per counter.  Atomics on one address are served one at a time by the
+// memory system, so allocating per block instead of per wave divides that
+// serial work by the block's wave count.  A counter whose block range passes
+// its capacity raises its overflow bit.  Every thread of the block calls it.
+// ---------------------------------------------------------------------------
+template <int NC, int NW>
+struct BlockReserveLds {
+    unsigned long long tot[NW][NC];
+    unsigned long long base[NC];
+};
+
+template <int NC, int NW>
+__device__ inline void block_reserve(BlockReserveLds<NC, NW> &sh, unsigned long long *const (&ctr)[NC],
+                                     const unsigned long long (&tot)[NC], const unsigned long long (&cap)[NC],
+                                     const uint32_t (&ovbit)[NC], unsigned long long *overflow,
+                                     unsigned long long (&base)[NC]) {
+    const int lane = threadIdx.x & 63;
+    const int wave = (int)(threadIdx.x >> 6);
+    if (lane == 0) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) sh.tot[wave][c] = tot[c];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long of = 0;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            unsigned long long all = 0;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) all += sh.tot[w][c];
+            unsigned long long b = 0;
+            if (all) {
+                b = atomicAdd(ctr[c], all);
+                if (b + all > cap[c]) of |= ovbit[c];
+            }
+            sh.base[c] = b;
+        }
+        if (of) atomicOr(overflow, of);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        unsigned long long b = sh.base[c];
+#pragma unroll
+        for (int w = 0; w < NW; ++w) b += w < wave ? sh.tot[w][c] : 0ull;
+        base[c] = b;
+    }
+    __syncthreads();  // sh is free for the next call
+}
+
 // Exclusive max-scan of (key, tag) over the lanes of a wave; ties keep the
 // lower lane.  ex: max over lanes below (kNegKey if none); all: over all lanes.
 // The key moves as two 32-bit halves; kNegKey is the identity.

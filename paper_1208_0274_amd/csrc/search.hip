@@ -1023,7 +1023,7 @@ static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64
             HIP_TRY(hipEventRecord(ws->evk0, s));
             if (nn > 0) {
                 // node phase (child tasks), then one child row per lane
-                k_level_tasks<<<(uint32_t)((nn + 255) / 256), 256, 0, s>>>(a, ws->nodes[cur], (uint32_t)nn,
+                k_level_tasks<<<(uint32_t)((nn + kTaskBlock - 1) / kTaskBlock), kTaskBlock, 0, s>>>(a, ws->nodes[cur], (uint32_t)nn,
                                                                           ws->tasks, caps, ws->d_cnt);
                 const uint64_t maxtasks = (uint64_t)sigma * nn;
                 k_expand_children<<<(uint32_t)((maxtasks + kLevelBlock - 1) / kLevelBlock), kLevelBlock, 0, s>>>(
