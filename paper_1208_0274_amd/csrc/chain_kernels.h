@@ -209,12 +209,17 @@ __device__ inline bool wave_queue_alloc(Counters *cnt, unsigned long long *nodes
 
 // ---------------------------------------------------------------------------
 // k_chain_start: one lane per chain created by a level.  Queue records and
-// hit slots are reserved once per wave where every lane takes part; the
+// hit slots are reserved once per block where every lane takes part; the
 // no-gap walk reserves its hit slots per lane in small chunks.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_chain_start(SearchArgs a, SubTable subt, const Node *items, uint32_t nitems,
-                                                     const Entry *ient, ChainQueues q, Caps caps, Counters *cnt) {
+constexpr int kStartBlock = 256;
+
+__global__ void __launch_bounds__(kStartBlock) k_chain_start(SearchArgs a, SubTable subt, const Node *items,
+                                                             uint32_t nitems, const Entry *ient, ChainQueues q,
+                                                             Caps caps, Counters *cnt) {
     __shared__ int8_t sub[20 * 20];
+    __shared__ BlockReserveLds<5, kStartBlock / 64> s_res5;
+    __shared__ BlockReserveLds<11, kStartBlock / 64> s_res11;
     for (int i = threadIdx.x; i < a.sigma * a.sigma; i += blockDim.x) sub[i] = subt.s[i];
     __syncthreads();
     const int lane = threadIdx.x & 63;
@@ -271,16 +276,22 @@ __global__ void __launch_bounds__(256) k_chain_start(SearchArgs a, SubTable subt
         return len <= 32u ? ((killGa >> k) & 1u) != 0
                           : (a.use_domination && e.Ga > 0 && dominated(a, sub, x, e.yGa));
     };
-    // phase 2: one reservation per wave for the first row's hits and the queue records
+    // phase 2: one reservation per block for the first row's hits and the queue records
     {
-        uint32_t ht;
-        const uint32_t hp = wave_excl_scan_u32(nh, &ht);
-        unsigned long long hb = 0;
-        if (lane == 0 && ht) {
-            hb = atomicAdd(&cnt->hits, (unsigned long long)ht);
-            if (hb + ht > caps.hits) atomicOr(&cnt->overflow, kOvHits);
-        }
-        hb = __shfl(hb, 0, 64) + hp;
+        const bool pw = path == kWide, pg = path == kGeneral;
+        uint32_t t_h, t_wn, t_we, t_gn, t_ge;
+        const uint32_t p_h = wave_excl_scan_u32(nh, &t_h);
+        const uint32_t p_wn = wave_excl_scan_u32(pw ? 1u : 0u, &t_wn);
+        const uint32_t p_we = wave_excl_scan_u32(pw ? len : 0u, &t_we);
+        const uint32_t p_gn = wave_excl_scan_u32(pg ? 1u : 0u, &t_gn);
+        const uint32_t p_ge = wave_excl_scan_u32(pg ? live : 0u, &t_ge);
+        unsigned long long *const ctr[5] = {&cnt->hits, &cnt->wnodes, &cnt->wentries, &cnt->gnodes, &cnt->gentries};
+        const unsigned long long wtot[5] = {t_h, t_wn, t_we, t_gn, t_ge};
+        const unsigned long long cap[5] = {caps.hits, caps.wnodes, caps.wentries, caps.gnodes, caps.gentries};
+        const uint32_t ovb[5] = {kOvHits, kOvWideNodes, kOvWideEntries, kOvGeneralNodes, kOvGeneralEntries};
+        unsigned long long b[5];
+        block_reserve<5, kStartBlock / 64>(s_res5, ctr, wtot, cap, ovb, &cnt->overflow, b);
+        unsigned long long hb = b[0] + p_h;
         if (nh) {
             for (uint32_t k = 0; k < len; ++k) {
                 const Entry e = row[k];
@@ -293,12 +304,8 @@ __global__ void __launch_bounds__(256) k_chain_start(SearchArgs a, SubTable subt
             }
             n_hits += nh;
         }
-    }
-    {
-        unsigned long long slot, off;
-        const bool ok = wave_queue_alloc(cnt, &cnt->wnodes, &cnt->wentries, caps.wnodes, caps.wentries, kOvWideNodes,
-                                         kOvWideEntries, path == kWide ? 1u : 0u, path == kWide ? len : 0u, slot, off);
-        if (path == kWide && ok) {
+        if (pw && b[1] + t_wn <= caps.wnodes && b[2] + t_we <= caps.wentries) {
+            const unsigned long long slot = b[1] + p_wn, off = b[2] + p_we;
             Entry *dst = q.wents + off;
             for (uint32_t k = 0; k < len; ++k) {
                 Entry e = row[k];
@@ -315,13 +322,8 @@ __global__ void __launch_bounds__(256) k_chain_start(SearchArgs a, SubTable subt
             q.wnodes[slot] = nd;
             ++n_wide;
         }
-    }
-    {
-        unsigned long long slot, off;
-        const bool ok = wave_queue_alloc(cnt, &cnt->gnodes, &cnt->gentries, caps.gnodes, caps.gentries,
-                                         kOvGeneralNodes, kOvGeneralEntries, path == kGeneral ? 1u : 0u,
-                                         path == kGeneral ? live : 0u, slot, off);
-        if (path == kGeneral && ok) {
+        if (pg && b[3] + t_gn <= caps.gnodes && b[4] + t_ge <= caps.gentries) {
+            const unsigned long long slot = b[3] + p_gn, off = b[4] + p_ge;
             Entry *dst = q.gents + off;
             uint32_t w = 0;
             for (uint32_t k = 0; k < len; ++k) {
@@ -423,13 +425,29 @@ __global__ void __launch_bounds__(256) k_chain_start(SearchArgs a, SubTable subt
         }
         lane_hit_release(lh, q.hkeys, q.hscores, caps);
     }
-    // phase 4: hand-offs to the general walker, one reservation per wave
+    // phase 4: hand-offs to the general walker and the statistics, one reservation per block
     {
         const uint32_t cntlive = handoff ? (uint32_t)__popc(alive) : 0u;
-        unsigned long long slot, off;
-        const bool ok = wave_queue_alloc(cnt, &cnt->gnodes, &cnt->gentries, caps.gnodes, caps.gentries,
-                                         kOvGeneralNodes, kOvGeneralEntries, handoff ? 1u : 0u, cntlive, slot, off);
-        if (handoff && ok) {
+        uint32_t t_n, t_e;
+        const uint32_t p_n = wave_excl_scan_u32(handoff ? 1u : 0u, &t_n);
+        const uint32_t p_e = wave_excl_scan_u32(cntlive, &t_e);
+        const unsigned long long w_dom = wave_sum_u64(n_dom), w_steps = wave_sum_u64(n_steps),
+                                 w_ent = wave_sum_u64(n_entries), w_hits = wave_sum_u64(n_hits),
+                                 w_wide = wave_sum_u64(n_wide), w_pad = wave_sum_u64(lh.pad),
+                                 w_items = wave_sum_u64(t < nitems ? 1ull : 0ull);
+        unsigned long long *const ctr[11] = {&cnt->gnodes,       &cnt->gentries,   &cnt->st_dominated,
+                                             &cnt->st_ngr_steps, &cnt->st_entries, &cnt->st_diag,
+                                             &cnt->st_emitted,   &cnt->st_promoted, &cnt->hit_padding,
+                                             &cnt->st_sa_reads,  &cnt->st_text_reads};
+        const unsigned long long wtot[11] = {t_n,    t_e,    w_dom, w_steps, w_ent, w_ent,
+                                             w_hits, w_wide, w_pad, w_items, w_items + w_steps / 8};
+        const unsigned long long cap[11] = {caps.gnodes, caps.gentries, ~0ull, ~0ull, ~0ull, ~0ull,
+                                            ~0ull,       ~0ull,         ~0ull, ~0ull, ~0ull};
+        const uint32_t ovb[11] = {kOvGeneralNodes, kOvGeneralEntries, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+        unsigned long long b[11];
+        block_reserve<11, kStartBlock / 64>(s_res11, ctr, wtot, cap, ovb, &cnt->overflow, b);
+        if (handoff && b[0] + t_n <= caps.gnodes && b[1] + t_e <= caps.gentries) {
+            const unsigned long long slot = b[0] + p_n, off = b[1] + p_e;
             Entry *dst = q.gents + off;
             uint32_t w = 0;
 #pragma unroll
@@ -450,23 +468,6 @@ __global__ void __launch_bounds__(256) k_chain_start(SearchArgs a, SubTable subt
             nd.off = (uint32_t)off;
             nd.len = cntlive;
             q.gnodes[slot] = nd;
-        }
-    }
-    const unsigned long long w_dom = wave_sum_u64(n_dom), w_steps = wave_sum_u64(n_steps),
-                             w_ent = wave_sum_u64(n_entries), w_hits = wave_sum_u64(n_hits),
-                             w_wide = wave_sum_u64(n_wide), w_pad = wave_sum_u64(lh.pad),
-                             w_items = wave_sum_u64(t < nitems ? 1ull : 0ull);
-    if (lane == 0) {
-        if (w_dom) atomicAdd(&cnt->st_dominated, w_dom);
-        if (w_steps) atomicAdd(&cnt->st_ngr_steps, w_steps);
-        if (w_ent) atomicAdd(&cnt->st_entries, w_ent);
-        if (w_ent) atomicAdd(&cnt->st_diag, w_ent);
-        if (w_hits) atomicAdd(&cnt->st_emitted, w_hits);
-        if (w_wide) atomicAdd(&cnt->st_promoted, w_wide);
-        if (w_pad) atomicAdd(&cnt->hit_padding, w_pad);
-        if (w_items) {
-            atomicAdd(&cnt->st_sa_reads, w_items);
-            atomicAdd(&cnt->st_text_reads, w_items + w_steps / 8);
         }
     }
 }

@@ -1062,7 +1062,7 @@ static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64
                 set_caps(nxt);
                 ChainQueues q{ws->gnodes, ws->gents, ws->wnodes, ws->wents, ws->hkeys, ws->hscores};
                 HIP_TRY(hipEventRecord(ws->evk0, s));
-                k_chain_start<<<(uint32_t)((nc + tb - 1) / tb), tb, 0, s>>>(a, sub, ws->cnodes, (uint32_t)nc,
+                k_chain_start<<<(uint32_t)((nc + kStartBlock - 1) / kStartBlock), kStartBlock, 0, s>>>(a, sub, ws->cnodes, (uint32_t)nc,
                                                                            ws->cents, q, caps, ws->d_cnt);
                 if ((st = timed(start_ms)) != ALAE_OK) return st;
                 const Counters &c = *ws->h_cnt;
