@@ -23,7 +23,6 @@ constexpr int kNarrowRow = 24;
 constexpr int kNgrSlots = 4;
 constexpr int kWideCap = 1024;  // row entries a wave walker keeps in LDS
 constexpr int kWideWaves = 4;   // waves of a wave-walker block (one chain per block)
-constexpr uint32_t kLdsQueryCols = 1u << 17;  // DNA queries up to this long are kept in LDS (2 bits a column)
 
 // Eight bytes arr[p .. p+7] as one little-endian word (arr carries kSlack
 // readable bytes around its data).
@@ -769,8 +768,7 @@ __device__ void replay_materialize(Row &cur, uint32_t len, uint32_t K, const uin
 template <int W = 1, class Row>
 __device__ bool walk_wide(const SearchArgs &a, Row &cur, Row &nxt, uint32_t &len, uint32_t &e_end, int32_t &depth,
                           uint32_t cap, uint64_t *hkeys, uint32_t *hscores, Caps caps, Counters *cnt, HitRes &hr,
-                          WideStats &w, Replay &rp, uint32_t *deltas, RowXchg *xg = nullptr,
-                          const uint32_t *qcodes = nullptr) {
+                          WideStats &w, Replay &rp, uint32_t *deltas, RowXchg *xg = nullptr) {
     const int lane = threadIdx.x & 63;
     uint32_t txt = 0;
     int tpos = 64;
@@ -817,7 +815,6 @@ __device__ bool walk_wide(const SearchArgs &a, Row &cur, Row &nxt, uint32_t &len
         o.e_child = e_end + 1;
         o.rK = rp.K;
         o.rdelta = deltas;
-        o.qcodes = qcodes;
         wide_child_row<W>(a, cur, len, nxt, c, d1, o, hr, xg);
         __syncthreads();
         w.steps++;
@@ -887,25 +884,9 @@ __global__ void __launch_bounds__(64 * kWideWaves) k_chain_wide_lds(SearchArgs a
     __shared__ uint32_t s_delta[64];
     __shared__ RowXchg s_xg;
     __shared__ unsigned long long s_bc[2];  // thread 0 -> block: claimed slot and state, spill slot and offset
-    __shared__ uint32_t s_q[kLdsQueryCols / 16];
     const uint32_t tid = threadIdx.x;
     const bool lead = tid == 0;
     const bool wave0 = tid < 64;
-    // match/mismatch DNA scoring: the query's codes in LDS instead of profile loads
-    const bool qlds = a.sigma == 4 && !a.matrix_mode && a.m <= kLdsQueryCols;
-    if (qlds) {
-        const uint32_t nq = (a.m + 15u) / 16u;
-        for (uint32_t wi = tid; wi < nq; wi += blockDim.x) {
-            uint32_t v = 0;
-#pragma unroll
-            for (uint32_t j = 0; j < 16; ++j) {
-                const uint32_t col = wi * 16u + j;
-                v |= (col < a.m ? (uint32_t)(a.query[col] & 3u) : 0u) << (2u * j);
-            }
-            s_q[wi] = v;
-        }
-    }
-    __syncthreads();
     HitRes hr = {0, 0, 0};
     WideStats w = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     if (live.ready && lead) atomicMin(&cnt->t_live0, (unsigned long long)__builtin_amdgcn_s_memrealtime());
@@ -999,7 +980,7 @@ __global__ void __launch_bounds__(64 * kWideWaves) k_chain_wide_lds(SearchArgs a
             for (uint32_t k = tid; k < len; k += blockDim.x) cur.store(k, went[nd.off + k]);
             __syncthreads();
             done = walk_wide<kWideWaves>(a, cur, nxt, len, e_end, depth, (uint32_t)kWideCap, hkeys, hscores, caps,
-                                         cnt, hr, w, rp, s_delta, &s_xg, qlds ? s_q : nullptr);
+                                         cnt, hr, w, rp, s_delta, &s_xg);
         } else {
             done = false;
         }

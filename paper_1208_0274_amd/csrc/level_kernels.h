@@ -286,7 +286,6 @@ __global__ void __launch_bounds__(64) k_expand_level_wide(SearchArgs a, const No
             w.emit_hits = false;
             w.rK = 0;
             w.rdelta = nullptr;
-            w.qcodes = nullptr;
             wide_child_row(a, AosRow{const_cast<Entry *>(ent) + nd.off}, nd.len, AosRow{buf}, c, d1, w, hr);
             __syncthreads();
             if (w.overflow) {

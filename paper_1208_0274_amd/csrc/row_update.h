@@ -625,9 +625,6 @@ struct WideOut {
     // replayed forks: every hit is also emitted at col + rdelta[r], r = 1..rK
     uint32_t rK;
     const uint32_t *rdelta;
-    // the query as 2-bit codes, 16 columns a word (LDS; match/mismatch DNA
-    // scoring only), or nullptr: substitution scores come from the profile
-    const uint32_t *qcodes;
     // results: len and overflow are uniform over the lanes that update the
     // row, hits over a wave; diag, gap2 and gap3 are per lane
     uint32_t len;
@@ -657,12 +654,6 @@ __device__ inline void wide_child_row(const SearchArgs &a, const Row cur, uint32
     const int wave = W > 1 ? (int)(threadIdx.x >> 6) : 0;
     int par = 0;
     const int8_t *pc = a.prof + (size_t)c * a.m;
-    const uint32_t *qc = o.qcodes;
-    // substitution score of text character c against query column col
-    auto subst = [&](uint32_t col) -> int32_t {
-        if (qc) return ((qc[col >> 4] >> ((col & 15u) * 2u)) & 3u) == (uint32_t)c ? a.s_match : a.s_mismatch;
-        return pc[col];
-    };
     const int32_t open = a.sg + a.ss;
     const int32_t ext = a.ss;
     const int64_t absss = -(int64_t)a.ss;
@@ -716,7 +707,7 @@ __device__ inline void wide_child_row(const SearchArgs &a, const Row cur, uint32
         int32_t D = kNeg;
         uint32_t yD = 0;
         if (valid && pcol != kNone && pcol + 1 == e.col && pM > 0 && !seg_first(a, e.col)) {
-            D = pM + subst(e.col);
+            D = pM + pc[e.col];
             yD = pyM;
         }
         int32_t GaA = kNeg;
@@ -741,7 +732,7 @@ __device__ inline void wide_child_row(const SearchArgs &a, const Row cur, uint32
         const uint32_t send = valid ? seg_end_of(a, e.col) : 0u;  // end of this entry's query
         const int64_t skey = valid ? seg_key(a, e.col) : 0;
         const bool hasB = valid && e.M > 0 && e.col + 1 < send && ncol != e.col + 1;
-        const int32_t M0B = hasB ? e.M + subst(e.col + 1) : kNeg;
+        const int32_t M0B = hasB ? e.M + pc[e.col + 1] : kNeg;
         const uint32_t yM0B = e.yM;
         const int64_t kA = (valid && M0A > 0) ? (int64_t)M0A + absss * (int64_t)e.col + skey : kNegKey;
         const int64_t kB = (hasB && M0B > 0) ? (int64_t)M0B + absss * (int64_t)(e.col + 1) + skey : kNegKey;
