@@ -1334,17 +1334,29 @@ static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64
         const int qb = std::max(1, bit_length(m - 1));
         int bits = qb + tb;
         if ((m - 1) == (1ull << qb) - 1 && (idx->n - 1) == (1ull << tb) - 1) ++bits;  // keep the padding key on top
-        HIP_TRY(repack_hit_keys(ws->hkeys, emitted, tb, bits, s));
-        bool in_alt = false;
-        HIP_TRY(radix_sort_pairs(ws->hkeys, ws->hscores, ws->hkeys_alt, ws->hscores_alt, emitted, bits, ws->scratch,
-                                 &in_alt, s));
-        const uint64_t *k = in_alt ? ws->hkeys_alt : ws->hkeys;
-        const uint32_t *v = in_alt ? ws->hscores_alt : ws->hscores;
+        // scores fit below the key when smax * m does: one 64-bit record a hit
+        const int sb = bit_length((uint64_t)std::max(1, a.smax) * m);
+        const bool packed = bits + sb <= 64;
         if ((st = grow(ws->flags, ws->flags_cap, emitted + 1, false, 0, s)) != ALAE_OK) return st;
         if ((st = grow(ws->pos, ws->pos_cap, emitted + 1, false, 0, s)) != ALAE_OK) return st;
         if ((st = grow_pair(ws->res_keys, ws->res_scores, ws->res_cap, emitted, 0, s)) != ALAE_OK) return st;
         const uint64_t valid = emitted - padding;
-        HIP_TRY(max_merge_sorted(k, v, valid, ws->res_keys, ws->res_scores, ws->flags, ws->pos, ws->scratch, s, tb));
+        bool in_alt = false;
+        if (packed) {
+            HIP_TRY(pack_hit_records(ws->hkeys, ws->hscores, emitted, tb, sb, bits, s));
+            HIP_TRY(radix_sort_keys(ws->hkeys, ws->hkeys_alt, emitted, sb, bits, ws->scratch, &in_alt, s));
+            const uint64_t *k = in_alt ? ws->hkeys_alt : ws->hkeys;
+            HIP_TRY(max_merge_packed(k, valid, sb, tb, ws->res_keys, ws->res_scores, ws->flags, ws->pos, ws->scratch,
+                                     s));
+        } else {
+            HIP_TRY(repack_hit_keys(ws->hkeys, emitted, tb, bits, s));
+            HIP_TRY(radix_sort_pairs(ws->hkeys, ws->hscores, ws->hkeys_alt, ws->hscores_alt, emitted, bits,
+                                     ws->scratch, &in_alt, s));
+            const uint64_t *k = in_alt ? ws->hkeys_alt : ws->hkeys;
+            const uint32_t *v = in_alt ? ws->hscores_alt : ws->hscores;
+            HIP_TRY(max_merge_sorted(k, v, valid, ws->res_keys, ws->res_scores, ws->flags, ws->pos, ws->scratch, s,
+                                     tb));
+        }
         uint32_t cnt32 = 0;
         HIP_TRY(hipEventRecord(ws->evk1, s));
         HIP_TRY(hipMemcpyAsync(&cnt32, ws->pos + valid, sizeof(uint32_t), hipMemcpyDeviceToHost, s));

@@ -84,22 +84,44 @@ constexpr int kBins = 1 << kDigit;
 constexpr int kSortItems = 64;
 constexpr int kSortTile = kThreads * kSortItems;
 
+// Lanes of a wave holding the same digit: the peers mask (ballot per digit
+// bit) and this lane's rank among them.
+__device__ inline uint64_t digit_peers(uint32_t d, bool valid) {
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < kDigit; ++b) {
+        const bool bit = (d >> b) & 1u;
+        const uint64_t bal = __ballot(bit);
+        peers &= bit ? bal : ~bal;
+    }
+    return peers;
+}
+
+// Per-block digit counts; one LDS atomic per distinct digit of a wave's keys
+// (hit keys come in runs that share digits).
 __global__ void __launch_bounds__(kThreads) radix_hist(const uint64_t *keys, uint64_t n, int shift, uint32_t *hist,
                                                        uint32_t nblocks) {
     __shared__ uint32_t cnt[kBins];
     for (int b = threadIdx.x; b < kBins; b += kThreads) cnt[b] = 0;
     __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     const uint64_t base = (uint64_t)blockIdx.x * kSortTile;
     for (int r = 0; r < kSortItems; ++r) {
         const uint64_t i = base + (uint64_t)r * kThreads + threadIdx.x;
-        if (i < n) atomicAdd(&cnt[(keys[i] >> shift) & (kBins - 1)], 1u);
+        const bool valid = i < n;
+        const uint32_t d = valid ? (uint32_t)(keys[i] >> shift) & (kBins - 1) : 0u;
+        const uint64_t peers = digit_peers(d, valid);
+        if (valid && (peers & below) == 0) atomicAdd(&cnt[d], (uint32_t)__popcll(peers));
     }
     __syncthreads();
     for (int b = threadIdx.x; b < kBins; b += kThreads) hist[(uint64_t)b * nblocks + blockIdx.x] = cnt[b];
 }
 
 // Stable scatter: elements of a tile are ranked in index order (round, wave,
-// lane); offs holds the exclusive scan of the digit-major histogram.
+// lane); offs holds the exclusive scan of the digit-major histogram.  VALS:
+// 32-bit values move with the keys.
+template <bool VALS>
 __global__ void __launch_bounds__(kThreads) radix_scatter(const uint64_t *kin, const uint32_t *vin, uint64_t *kout,
                                                           uint32_t *vout, uint64_t n, int shift,
                                                           const uint32_t *offs, uint32_t nblocks) {
@@ -120,15 +142,9 @@ __global__ void __launch_bounds__(kThreads) radix_scatter(const uint64_t *kin, c
         const uint64_t i = base + (uint64_t)r * kThreads + tid;
         const bool valid = i < n;
         const uint64_t k = valid ? kin[i] : 0ull;
-        const uint32_t v = valid ? vin[i] : 0u;
+        const uint32_t v = (VALS && valid) ? vin[i] : 0u;
         const uint32_t d = (uint32_t)(k >> shift) & (kBins - 1);
-        uint64_t peers = __ballot(valid);
-#pragma unroll
-        for (int b = 0; b < kDigit; ++b) {
-            const bool bit = (d >> b) & 1u;
-            const uint64_t bal = __ballot(bit);
-            peers &= bit ? bal : ~bal;
-        }
+        const uint64_t peers = digit_peers(d, valid);
         const uint32_t rank = (uint32_t)__popcll(peers & below);
         const uint32_t same = (uint32_t)__popcll(peers);
         const bool leader = valid && rank == 0;
@@ -138,7 +154,7 @@ __global__ void __launch_bounds__(kThreads) radix_scatter(const uint64_t *kin, c
             uint32_t pos = run[d] + rank;
             for (int w = 0; w < wave; ++w) pos += wcnt[w][d];
             kout[pos] = k;
-            vout[pos] = v;
+            if (VALS) vout[pos] = v;
         }
         __syncthreads();
         if (leader) {
@@ -168,6 +184,37 @@ __global__ void merge_write(const uint64_t *keys, const uint32_t *scores, uint64
     // packed keys (high part << low_bits | low part) go back to (high << 32) | low
     const uint64_t out = low_bits ? ((key >> low_bits) << 32) | (key & ((1ull << low_bits) - 1)) : key;
     out_keys[pos[i]] = out;
+    out_scores[pos[i]] = (uint32_t)best;
+}
+
+// Hit records as one word: ((query end << low_bits | text end) << sb) | score,
+// the padding key going to `pad` (above every real record).
+__global__ void pack_records(uint64_t *keys, const uint32_t *scores, uint64_t n, int low_bits, int sb,
+                             uint64_t pad) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint64_t k = keys[i];
+    keys[i] = k == ~0ull ? pad : ((((k >> 32) << low_bits) | (k & 0xFFFFFFFFull)) << sb) | (uint64_t)scores[i];
+}
+
+__global__ void merge_flags_packed(const uint64_t *recs, uint64_t n, int sb, uint32_t *flags) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) flags[i] = (i == 0 || (recs[i] >> sb) != (recs[i - 1] >> sb)) ? 1u : 0u;
+    if (i == n) flags[i] = 0u;
+}
+
+__global__ void merge_write_packed(const uint64_t *recs, uint64_t n, int sb, int low_bits, const uint32_t *flags,
+                                   const uint32_t *pos, uint64_t *out_keys, uint32_t *out_scores) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n || !flags[i]) return;
+    const uint64_t smask = (1ull << sb) - 1;
+    const uint64_t key = recs[i] >> sb;
+    uint64_t best = recs[i] & smask;
+    for (uint64_t j = i + 1; j < n && (recs[j] >> sb) == key; ++j) {
+        const uint64_t s = recs[j] & smask;
+        best = s > best ? s : best;
+    }
+    out_keys[pos[i]] = ((key >> low_bits) << 32) | (key & ((1ull << low_bits) - 1));
     out_scores[pos[i]] = (uint32_t)best;
 }
 
@@ -226,7 +273,7 @@ hipError_t radix_sort_pairs(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, 
         if (e != hipSuccess) return e;
         e = scan_exclusive_u32(hist, hist, (uint64_t)kBins * blocks, tmp, s);
         if (e != hipSuccess) return e;
-        radix_scatter<<<blocks, kThreads, 0, s>>>(kin, vin, kout, vout, n, shift, hist, blocks);
+        radix_scatter<true><<<blocks, kThreads, 0, s>>>(kin, vin, kout, vout, n, shift, hist, blocks);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
         std::swap(kin, kout);
@@ -235,6 +282,54 @@ hipError_t radix_sort_pairs(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, 
     }
     *result_in_alt = alt;
     return hipSuccess;
+}
+
+hipError_t radix_sort_keys(uint64_t *keys, uint64_t *keys_alt, uint64_t n, int lo_bit, int bits, uint32_t *scratch,
+                           bool *result_in_alt, hipStream_t s) {
+    *result_in_alt = false;
+    if (n <= 1 || bits <= 0) return hipSuccess;
+    const uint32_t blocks = (uint32_t)ceil_div(n, kSortTile);
+    uint32_t *hist = scratch;
+    uint32_t *tmp = scratch + (uint64_t)kBins * blocks;
+    uint64_t *kin = keys, *kout = keys_alt;
+    bool alt = false;
+    for (int shift = lo_bit; shift < lo_bit + bits; shift += kDigit) {
+        radix_hist<<<blocks, kThreads, 0, s>>>(kin, n, shift, hist, blocks);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        e = scan_exclusive_u32(hist, hist, (uint64_t)kBins * blocks, tmp, s);
+        if (e != hipSuccess) return e;
+        radix_scatter<false><<<blocks, kThreads, 0, s>>>(kin, nullptr, kout, nullptr, n, shift, hist, blocks);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        std::swap(kin, kout);
+        alt = !alt;
+    }
+    *result_in_alt = alt;
+    return hipSuccess;
+}
+
+hipError_t pack_hit_records(uint64_t *keys, const uint32_t *scores, uint64_t n, int low_bits, int sb,
+                            int total_bits, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    const int all = total_bits + sb;
+    const uint64_t pad = all >= 64 ? ~0ull : ((1ull << all) - 1);
+    pack_records<<<(uint32_t)ceil_div(n, 256), 256, 0, s>>>(keys, scores, n, low_bits, sb, pad);
+    return hipGetLastError();
+}
+
+hipError_t max_merge_packed(const uint64_t *recs, uint64_t n, int sb, int low_bits, uint64_t *out_keys,
+                            uint32_t *out_scores, uint32_t *flags, uint32_t *pos, uint32_t *tmp, hipStream_t s) {
+    const uint32_t threads = 256;
+    merge_flags_packed<<<(uint32_t)ceil_div(n + 1, threads), threads, 0, s>>>(recs, n, sb, flags);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = scan_exclusive_u32(flags, pos, n + 1, tmp, s);
+    if (e != hipSuccess) return e;
+    if (n == 0) return hipSuccess;
+    merge_write_packed<<<(uint32_t)ceil_div(n, threads), threads, 0, s>>>(recs, n, sb, low_bits, flags, pos,
+                                                                          out_keys, out_scores);
+    return hipGetLastError();
 }
 
 hipError_t repack_hit_keys(uint64_t *keys, uint64_t n, int low_bits, int total_bits, hipStream_t s) {
