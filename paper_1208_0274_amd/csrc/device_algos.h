@@ -44,8 +44,11 @@ hipError_t pack_hit_records(uint64_t *keys, const uint32_t *scores, uint64_t n, 
 hipError_t max_merge_sorted(const uint64_t *keys, const uint32_t *scores, uint64_t n, uint64_t *out_keys,
                             uint32_t *out_scores, uint32_t *flags, uint32_t *pos, uint32_t *tmp,
                             hipStream_t s, int low_bits = 0);
-// The same for records packed by pack_hit_records.
+// The same for records packed by pack_hit_records: tiles holds
+// merge_tile_count(n) + 1 words and receives the distinct count at index
+// merge_tile_count(n); tmp scan_scratch_words(merge_tile_count(n) + 1).
 hipError_t max_merge_packed(const uint64_t *recs, uint64_t n, int sb, int low_bits, uint64_t *out_keys,
-                            uint32_t *out_scores, uint32_t *flags, uint32_t *pos, uint32_t *tmp, hipStream_t s);
+                            uint32_t *out_scores, uint32_t *tiles, uint32_t *tmp, hipStream_t s);
+uint64_t merge_tile_count(uint64_t n);
 
 }  // namespace alae

@@ -1342,12 +1342,13 @@ static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64
         if ((st = grow_pair(ws->res_keys, ws->res_scores, ws->res_cap, emitted, 0, s)) != ALAE_OK) return st;
         const uint64_t valid = emitted - padding;
         bool in_alt = false;
+        const uint32_t *count_at = ws->pos + valid;  // where the merge leaves the distinct count
         if (packed) {
             HIP_TRY(pack_hit_records(ws->hkeys, ws->hscores, emitted, tb, sb, bits, s));
             HIP_TRY(radix_sort_keys(ws->hkeys, ws->hkeys_alt, emitted, sb, bits, ws->scratch, &in_alt, s));
             const uint64_t *k = in_alt ? ws->hkeys_alt : ws->hkeys;
-            HIP_TRY(max_merge_packed(k, valid, sb, tb, ws->res_keys, ws->res_scores, ws->flags, ws->pos, ws->scratch,
-                                     s));
+            HIP_TRY(max_merge_packed(k, valid, sb, tb, ws->res_keys, ws->res_scores, ws->pos, ws->scratch, s));
+            count_at = ws->pos + merge_tile_count(valid);
         } else {
             HIP_TRY(repack_hit_keys(ws->hkeys, emitted, tb, bits, s));
             HIP_TRY(radix_sort_pairs(ws->hkeys, ws->hscores, ws->hkeys_alt, ws->hscores_alt, emitted, bits,
@@ -1359,7 +1360,7 @@ static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64
         }
         uint32_t cnt32 = 0;
         HIP_TRY(hipEventRecord(ws->evk1, s));
-        HIP_TRY(hipMemcpyAsync(&cnt32, ws->pos + valid, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(&cnt32, count_at, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
         HIP_TRY(hipEventElapsedTime(&merge_ms, ws->evk0, ws->evk1));
         unique = cnt32;

@@ -107,12 +107,22 @@ __global__ void __launch_bounds__(kThreads) radix_hist(const uint64_t *keys, uin
     const int lane = threadIdx.x & 63;
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     const uint64_t base = (uint64_t)blockIdx.x * kSortTile;
-    for (int r = 0; r < kSortItems; ++r) {
-        const uint64_t i = base + (uint64_t)r * kThreads + threadIdx.x;
-        const bool valid = i < n;
-        const uint32_t d = valid ? (uint32_t)(keys[i] >> shift) & (kBins - 1) : 0u;
-        const uint64_t peers = digit_peers(d, valid);
-        if (valid && (peers & below) == 0) atomicAdd(&cnt[d], (uint32_t)__popcll(peers));
+    constexpr int kBatch = 16;  // loads issued together
+    for (int r0 = 0; r0 < kSortItems; r0 += kBatch) {
+        uint64_t kk[kBatch];
+#pragma unroll
+        for (int j = 0; j < kBatch; ++j) {
+            const uint64_t i = base + (uint64_t)(r0 + j) * kThreads + threadIdx.x;
+            kk[j] = i < n ? keys[i] : 0ull;
+        }
+#pragma unroll
+        for (int j = 0; j < kBatch; ++j) {
+            const uint64_t i = base + (uint64_t)(r0 + j) * kThreads + threadIdx.x;
+            const bool valid = i < n;
+            const uint32_t d = (uint32_t)(kk[j] >> shift) & (kBins - 1);
+            const uint64_t peers = digit_peers(d, valid);
+            if (valid && (peers & below) == 0) atomicAdd(&cnt[d], (uint32_t)__popcll(peers));
+        }
     }
     __syncthreads();
     for (int b = threadIdx.x; b < kBins; b += kThreads) hist[(uint64_t)b * nblocks + blockIdx.x] = cnt[b];
@@ -138,11 +148,18 @@ __global__ void __launch_bounds__(kThreads) radix_scatter(const uint64_t *kin, c
     __syncthreads();
     const uint64_t base = (uint64_t)blockIdx.x * kSortTile;
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    uint64_t k_next = base + tid < n ? kin[base + tid] : 0ull;  // the next round's element, loaded early
+    uint32_t v_next = (VALS && base + tid < n) ? vin[base + tid] : 0u;
     for (int r = 0; r < kSortItems; ++r) {
         const uint64_t i = base + (uint64_t)r * kThreads + tid;
         const bool valid = i < n;
-        const uint64_t k = valid ? kin[i] : 0ull;
-        const uint32_t v = (VALS && valid) ? vin[i] : 0u;
+        const uint64_t k = k_next;
+        const uint32_t v = v_next;
+        if (r + 1 < kSortItems) {
+            const uint64_t i2 = i + kThreads;
+            k_next = i2 < n ? kin[i2] : 0ull;
+            if (VALS) v_next = i2 < n ? vin[i2] : 0u;
+        }
         const uint32_t d = (uint32_t)(k >> shift) & (kBins - 1);
         const uint64_t peers = digit_peers(d, valid);
         const uint32_t rank = (uint32_t)__popcll(peers & below);
@@ -197,25 +214,59 @@ __global__ void pack_records(uint64_t *keys, const uint32_t *scores, uint64_t n,
     keys[i] = k == ~0ull ? pad : ((((k >> 32) << low_bits) | (k & 0xFFFFFFFFull)) << sb) | (uint64_t)scores[i];
 }
 
-__global__ void merge_flags_packed(const uint64_t *recs, uint64_t n, int sb, uint32_t *flags) {
-    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) flags[i] = (i == 0 || (recs[i] >> sb) != (recs[i - 1] >> sb)) ? 1u : 0u;
-    if (i == n) flags[i] = 0u;
+// Max-merge of packed records in two passes over tiles of kTile records
+// (kItems consecutive records a thread): count the records that start a new
+// key per tile, then (after a scan of the tile counts) write one record per
+// key at its place.  A group's largest score is found by reading on from its
+// first record.
+__device__ inline uint32_t group_starts(const uint64_t *recs, uint64_t n, int sb, uint64_t first, bool (&st)[kItems]) {
+    uint64_t prev = (first == 0 || first > n) ? ~0ull : recs[first - 1] >> sb;
+    uint32_t c = 0;
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+        const uint64_t i = first + k;
+        const uint64_t key = i < n ? recs[i] >> sb : 0ull;
+        st[k] = i < n && (i == 0 || key != prev);
+        c += st[k] ? 1u : 0u;
+        prev = key;
+    }
+    return c;
 }
 
-__global__ void merge_write_packed(const uint64_t *recs, uint64_t n, int sb, int low_bits, const uint32_t *flags,
-                                   const uint32_t *pos, uint64_t *out_keys, uint32_t *out_scores) {
-    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n || !flags[i]) return;
+__global__ void __launch_bounds__(kThreads) merge_count(const uint64_t *recs, uint64_t n, int sb,
+                                                        uint32_t *tile_counts) {
+    const uint64_t first = (uint64_t)blockIdx.x * kTile + (uint64_t)threadIdx.x * kItems;
+    bool st[kItems];
+    const uint32_t c = group_starts(recs, n, sb, first, st);
+    uint32_t total;
+    block_exclusive_scan(c, &total);
+    if (threadIdx.x == 0) tile_counts[blockIdx.x] = total;
+    if (blockIdx.x == 0 && threadIdx.x == 0) tile_counts[gridDim.x] = 0u;  // the scan leaves the total there
+}
+
+__global__ void __launch_bounds__(kThreads) merge_emit(const uint64_t *recs, uint64_t n, int sb, int low_bits,
+                                                       const uint32_t *tile_prefix, uint64_t *out_keys,
+                                                       uint32_t *out_scores) {
+    const uint64_t first = (uint64_t)blockIdx.x * kTile + (uint64_t)threadIdx.x * kItems;
+    bool st[kItems];
+    const uint32_t c = group_starts(recs, n, sb, first, st);
+    uint32_t total;
+    uint64_t pos = (uint64_t)tile_prefix[blockIdx.x] + block_exclusive_scan(c, &total);
     const uint64_t smask = (1ull << sb) - 1;
-    const uint64_t key = recs[i] >> sb;
-    uint64_t best = recs[i] & smask;
-    for (uint64_t j = i + 1; j < n && (recs[j] >> sb) == key; ++j) {
-        const uint64_t s = recs[j] & smask;
-        best = s > best ? s : best;
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+        if (!st[k]) continue;
+        const uint64_t i = first + k;
+        const uint64_t key = recs[i] >> sb;
+        uint64_t best = recs[i] & smask;
+        for (uint64_t j = i + 1; j < n && (recs[j] >> sb) == key; ++j) {
+            const uint64_t s = recs[j] & smask;
+            best = s > best ? s : best;
+        }
+        out_keys[pos] = ((key >> low_bits) << 32) | (key & ((1ull << low_bits) - 1));
+        out_scores[pos] = (uint32_t)best;
+        ++pos;
     }
-    out_keys[pos[i]] = ((key >> low_bits) << 32) | (key & ((1ull << low_bits) - 1));
-    out_scores[pos[i]] = (uint32_t)best;
 }
 
 __global__ void repack_keys(uint64_t *keys, uint64_t n, int low_bits, uint64_t pad) {
@@ -226,6 +277,8 @@ __global__ void repack_keys(uint64_t *keys, uint64_t n, int low_bits, uint64_t p
 }
 
 uint64_t ceil_div(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
+
+const uint32_t kZero = 0;
 
 }  // namespace
 
@@ -319,18 +372,19 @@ hipError_t pack_hit_records(uint64_t *keys, const uint32_t *scores, uint64_t n, 
 }
 
 hipError_t max_merge_packed(const uint64_t *recs, uint64_t n, int sb, int low_bits, uint64_t *out_keys,
-                            uint32_t *out_scores, uint32_t *flags, uint32_t *pos, uint32_t *tmp, hipStream_t s) {
-    const uint32_t threads = 256;
-    merge_flags_packed<<<(uint32_t)ceil_div(n + 1, threads), threads, 0, s>>>(recs, n, sb, flags);
+                            uint32_t *out_scores, uint32_t *tiles, uint32_t *tmp, hipStream_t s) {
+    const uint64_t nt = ceil_div(n, kTile);
+    if (n == 0) return hipMemcpyAsync(tiles, &kZero, sizeof(uint32_t), hipMemcpyHostToDevice, s);
+    merge_count<<<(uint32_t)nt, kThreads, 0, s>>>(recs, n, sb, tiles);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    e = scan_exclusive_u32(flags, pos, n + 1, tmp, s);
+    e = scan_exclusive_u32(tiles, tiles, nt + 1, tmp, s);  // tiles[nt]: the distinct count
     if (e != hipSuccess) return e;
-    if (n == 0) return hipSuccess;
-    merge_write_packed<<<(uint32_t)ceil_div(n, threads), threads, 0, s>>>(recs, n, sb, low_bits, flags, pos,
-                                                                          out_keys, out_scores);
+    merge_emit<<<(uint32_t)nt, kThreads, 0, s>>>(recs, n, sb, low_bits, tiles, out_keys, out_scores);
     return hipGetLastError();
 }
+
+uint64_t merge_tile_count(uint64_t n) { return ceil_div(n, kTile); }
 
 hipError_t repack_hit_keys(uint64_t *keys, uint64_t n, int low_bits, int total_bits, hipStream_t s) {
     if (n == 0) return hipSuccess;
