@@ -765,7 +765,7 @@ __device__ void replay_materialize(Row &cur, uint32_t len, uint32_t K, const uin
 // return the caller writes out the copies (replay_entry) when it spills.
 // W > 1: the block's W waves update each row together (xg: their LDS
 // exchange slots); everything else here is computed alike by every wave.
-template <int W = 1, class Row>
+template <int W = 1, bool FAST = false, class Row>
 __device__ bool walk_wide(const SearchArgs &a, Row &cur, Row &nxt, uint32_t &len, uint32_t &e_end, int32_t &depth,
                           uint32_t cap, uint64_t *hkeys, uint32_t *hscores, Caps caps, Counters *cnt, HitRes &hr,
                           WideStats &w, Replay &rp, uint32_t *deltas, RowXchg *xg = nullptr) {
@@ -815,7 +815,7 @@ __device__ bool walk_wide(const SearchArgs &a, Row &cur, Row &nxt, uint32_t &len
         o.e_child = e_end + 1;
         o.rK = rp.K;
         o.rdelta = deltas;
-        wide_child_row<W>(a, cur, len, nxt, c, d1, o, hr, xg);
+        wide_child_row<W, FAST>(a, cur, len, nxt, c, d1, o, hr, xg);
         __syncthreads();
         w.steps++;
         w.bytes += (unsigned long long)(len + o.len) * 12ull;
@@ -873,6 +873,8 @@ struct LiveQueue {
 // when the lane walker has finished and every published item is taken; a
 // block that sees no progress for `patience` gives its claimed item to the
 // next pass and stops, so the pass always ends.
+// FAST: see wide_child_row (single query, 31-bit prefix-max keys).
+template <bool FAST>
 __global__ void __launch_bounds__(64 * kWideWaves) k_chain_wide_lds(SearchArgs a, const Node *witems, uint32_t first,
                                                                     uint32_t nw, const Entry *went, Node *onodes,
                                                                     Entry *oents, uint64_t *hkeys, uint32_t *hscores,
@@ -979,7 +981,7 @@ __global__ void __launch_bounds__(64 * kWideWaves) k_chain_wide_lds(SearchArgs a
         if (len <= (uint32_t)kWideCap) {
             for (uint32_t k = tid; k < len; k += blockDim.x) cur.store(k, went[nd.off + k]);
             __syncthreads();
-            done = walk_wide<kWideWaves>(a, cur, nxt, len, e_end, depth, (uint32_t)kWideCap, hkeys, hscores, caps,
+            done = walk_wide<kWideWaves, FAST>(a, cur, nxt, len, e_end, depth, (uint32_t)kWideCap, hkeys, hscores, caps,
                                          cnt, hr, w, rp, s_delta, &s_xg);
         } else {
             done = false;

@@ -480,6 +480,22 @@ __device__ inline void block_reserve(BlockReserveLds<NC, NW> &sh, unsigned long 
     __syncthreads();  // sh is free for the next call
 }
 
+// Exclusive max-scan of a 32-bit key over the lanes of a wave (no tags):
+// ex = max over lanes below (kNegKey32 if none), all = over all lanes.
+constexpr int32_t kNegKey32 = INT32_MIN / 4;
+__device__ inline void wave_excl_max_i32(int32_t key, int32_t &ex, int32_t &all) {
+    const uint32_t id = (uint32_t)kNegKey32;
+    int32_t k = (int32_t)dpp<kDppWaveShr1>(id, (uint32_t)key);
+    k = imax(k, (int32_t)dpp<kDppRowShr + 1, 0xF>(id, (uint32_t)k));
+    k = imax(k, (int32_t)dpp<kDppRowShr + 2, 0xF>(id, (uint32_t)k));
+    k = imax(k, (int32_t)dpp<kDppRowShr + 4, 0xF>(id, (uint32_t)k));
+    k = imax(k, (int32_t)dpp<kDppRowShr + 8, 0xF>(id, (uint32_t)k));
+    k = imax(k, (int32_t)dpp<kDppRowBcast15, 0xA>(id, (uint32_t)k));
+    k = imax(k, (int32_t)dpp<kDppRowBcast31, 0xC>(id, (uint32_t)k));
+    ex = k;
+    all = __builtin_amdgcn_readlane(imax(k, key), 63);
+}
+
 // Exclusive max-scan of (key, tag) over the lanes of a wave; ties keep the
 // lower lane.  ex: max over lanes below (kNegKey if none); all: over all lanes.
 // The key moves as two 32-bit halves; kNegKey is the identity.
@@ -542,12 +558,14 @@ __device__ inline void wave_excl_max(int64_t key, uint32_t tag, int64_t &ex_key,
 // Row storage seen by the wave-parallel update: entries with start tags in
 // global memory, or column/M/G_a arrays (no tags) in LDS.
 struct AosRow {
+    static constexpr bool kTags = true;
     Entry *p;
     __device__ Entry load(uint32_t k) const { return p[k]; }
     __device__ void store(uint32_t k, const Entry &e) const { p[k] = e; }
 };
 
 struct SoaRow {
+    static constexpr bool kTags = false;
     uint32_t *col;
     int32_t *M;
     int32_t *Ga;
@@ -646,10 +664,13 @@ struct RowXchg {
 // W waves take 64*W entries per round; the carries of the waves before each
 // one (prefix maximum, output count) pass through xg, with two barriers a
 // round.  Both give the same row.
-template <int W = 1, class Row>
+// FAST: a single query whose prefix-max keys fit 31 bits ((s_max + |s_s|) m <
+// 2^30) and rows without start tags; the scan then moves one 32-bit key.
+template <int W = 1, bool FAST = false, class Row>
 __device__ inline void wide_child_row(const SearchArgs &a, const Row cur, uint32_t len, const Row nxt, int c,
                                       int32_t d1, WideOut &o, HitRes &hr, RowXchg *xg = nullptr) {
     static_assert(W >= 1 && W <= kMaxRowWaves, "waves per row");
+    static_assert(!FAST || !Row::kTags, "the 32-bit scan carries no start tags");
     const int lane = threadIdx.x & 63;
     const int wave = W > 1 ? (int)(threadIdx.x >> 6) : 0;
     int par = 0;
@@ -706,7 +727,7 @@ __device__ inline void wide_child_row(const SearchArgs &a, const Row cur, uint32
         // column A = e.col: diagonal from the previous entry and G_a
         int32_t D = kNeg;
         uint32_t yD = 0;
-        if (valid && pcol != kNone && pcol + 1 == e.col && pM > 0 && !seg_first(a, e.col)) {
+        if (valid && pcol != kNone && pcol + 1 == e.col && pM > 0 && (FAST || !seg_first(a, e.col))) {
             D = pM + pc[e.col];
             yD = pyM;
         }
@@ -729,8 +750,8 @@ __device__ inline void wide_child_row(const SearchArgs &a, const Row cur, uint32
             yM0A = yGaA;
         }
         // column B = e.col + 1: diagonal only, unless the next entry owns it
-        const uint32_t send = valid ? seg_end_of(a, e.col) : 0u;  // end of this entry's query
-        const int64_t skey = valid ? seg_key(a, e.col) : 0;
+        const uint32_t send = FAST ? a.m : (valid ? seg_end_of(a, e.col) : 0u);  // end of this entry's query
+        const int64_t skey = FAST ? 0 : (valid ? seg_key(a, e.col) : 0);
         const bool hasB = valid && e.M > 0 && e.col + 1 < send && ncol != e.col + 1;
         const int32_t M0B = hasB ? e.M + pc[e.col + 1] : kNeg;
         const uint32_t yM0B = e.yM;
@@ -744,7 +765,15 @@ __device__ inline void wide_child_row(const SearchArgs &a, const Row cur, uint32
         }
         int64_t exk, allk;
         uint32_t ext_tag, allt;
-        wave_excl_max(lk, lt, exk, ext_tag, allk, allt);
+        if constexpr (FAST) {
+            int32_t ex32, all32;
+            wave_excl_max_i32(lk > 0 ? (int32_t)lk : kNegKey32, ex32, all32);
+            exk = ex32 > 0 ? (int64_t)ex32 : kNegKey;
+            allk = all32 > 0 ? (int64_t)all32 : kNegKey;
+            ext_tag = allt = 0;
+        } else {
+            wave_excl_max(lk, lt, exk, ext_tag, allk, allt);
+        }
         // carry-in: earlier rounds, then the waves before this one (earlier wins ties)
         int64_t cin = c_key;
         uint32_t cint = c_tag;

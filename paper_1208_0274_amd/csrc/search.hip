@@ -1160,6 +1160,8 @@ static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64
         order_ms = ms;
     }
     const uint32_t live_blocks = (uint32_t)cus * 2u;  // kWideWaves waves each
+    // one query whose prefix-max keys fit 31 bits: the wave walkers' 32-bit scan
+    const bool wide_fast = !multi && (int64_t)(std::max(1, a.smax) - a.ss) * (int64_t)m < (1ll << 30);
     if (ng > 0 || nw1 > 0) {
         const Counters before = *ws->h_cnt;
         for (;;) {
@@ -1205,9 +1207,14 @@ static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64
                                                         ws->hkeys, ws->hscores, caps, ws->d_cnt, gq.order, gq.twork,
                                                         tracing ? ws->wsrc : nullptr, ws->ready);
             HIP_TRY(hipGetLastError());
-            k_chain_wide_lds<<<live_blocks, 64 * kWideWaves, 0, ws->s2>>>(a, ws->wnodes, 0, 0xFFFFFFFFu, ws->wents, ws->onodes,
-                                                             ws->oents, ws->hkeys, ws->hscores, caps, ws->d_cnt,
-                                                             wq.order, tracing ? ws->qb[1].twork : nullptr, lq);
+            if (wide_fast)
+                k_chain_wide_lds<true><<<live_blocks, 64 * kWideWaves, 0, ws->s2>>>(
+                    a, ws->wnodes, 0, 0xFFFFFFFFu, ws->wents, ws->onodes, ws->oents, ws->hkeys, ws->hscores, caps,
+                    ws->d_cnt, wq.order, tracing ? ws->qb[1].twork : nullptr, lq);
+            else
+                k_chain_wide_lds<false><<<live_blocks, 64 * kWideWaves, 0, ws->s2>>>(
+                    a, ws->wnodes, 0, 0xFFFFFFFFu, ws->wents, ws->onodes, ws->oents, ws->hkeys, ws->hscores, caps,
+                    ws->d_cnt, wq.order, tracing ? ws->qb[1].twork : nullptr, lq);
             HIP_TRY(hipGetLastError());
             HIP_TRY(hipEventRecord(ws->ev_join, ws->s2));
             HIP_TRY(hipStreamWaitEvent(s, ws->ev_join, 0));
@@ -1258,9 +1265,14 @@ static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64
                 HIP_TRY(hipMemcpyAsync(ws->d_cnt, &z, sizeof(Counters), hipMemcpyHostToDevice, s));
                 set_caps(cur);
                 HIP_TRY(hipEventRecord(ws->evk0, s));
-                k_chain_wide_lds<<<blocks, 64 * kWideWaves, 0, s>>>(a, ws->wnodes, 0, (uint32_t)nleft, ws->wents, ws->onodes,
-                                                       ws->oents, ws->hkeys, ws->hscores, caps, ws->d_cnt, ws->left,
-                                                       tracing ? ws->qb[1].twork : nullptr, none);
+                if (wide_fast)
+                    k_chain_wide_lds<true><<<blocks, 64 * kWideWaves, 0, s>>>(
+                        a, ws->wnodes, 0, (uint32_t)nleft, ws->wents, ws->onodes, ws->oents, ws->hkeys, ws->hscores,
+                        caps, ws->d_cnt, ws->left, tracing ? ws->qb[1].twork : nullptr, none);
+                else
+                    k_chain_wide_lds<false><<<blocks, 64 * kWideWaves, 0, s>>>(
+                        a, ws->wnodes, 0, (uint32_t)nleft, ws->wents, ws->onodes, ws->oents, ws->hkeys, ws->hscores,
+                        caps, ws->d_cnt, ws->left, tracing ? ws->qb[1].twork : nullptr, none);
                 if ((st = timed(wide_ms)) != ALAE_OK) return st;
                 const Counters &c = *ws->h_cnt;
                 if (!c.overflow) break;
