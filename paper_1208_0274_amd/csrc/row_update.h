@@ -8,6 +8,8 @@
 // parent row.
 #pragma once
 
+#include <type_traits>
+
 #include "device_common.h"
 
 namespace alae {
@@ -677,13 +679,16 @@ __device__ inline void wide_child_row(const SearchArgs &a, const Row cur, uint32
     const int8_t *pc = a.prof + (size_t)c * a.m;
     const int32_t open = a.sg + a.ss;
     const int32_t ext = a.ss;
-    const int64_t absss = -(int64_t)a.ss;
+    // prefix-max keys: 32-bit for FAST, else 64-bit with the query segment offset
+    using Key = std::conditional_t<FAST, int32_t, int64_t>;
+    constexpr Key kNoKey = FAST ? (Key)kNegKey32 : (Key)kNegKey;
+    const Key absss = -(Key)a.ss;
     const int32_t rowgain = a.smax * (a.lmax - d1);
     constexpr uint32_t kNone = 0xFFFFFFFFu;
     // carries between rounds (wave-uniform)
     uint32_t c_pcol = kNone, c_pyM = 0;
     int32_t c_pM = kNeg;
-    int64_t c_key = kNegKey;
+    Key c_key = kNoKey;
     uint32_t c_tag = 0;
     uint32_t out = 0;
     bool overflow = false;
@@ -704,7 +709,7 @@ __device__ inline void wide_child_row(const SearchArgs &a, const Row cur, uint32
         }
         uint32_t pcol = lane_up1(e.col);
         int32_t pM = lane_up1(e.M);
-        uint32_t pyM = lane_up1(e.yM);
+        uint32_t pyM = Row::kTags ? lane_up1(e.yM) : 0u;
         if (lane == 0) {
             if (W == 1) {
                 pcol = c_pcol;
@@ -751,31 +756,28 @@ __device__ inline void wide_child_row(const SearchArgs &a, const Row cur, uint32
         }
         // column B = e.col + 1: diagonal only, unless the next entry owns it
         const uint32_t send = FAST ? a.m : (valid ? seg_end_of(a, e.col) : 0u);  // end of this entry's query
-        const int64_t skey = FAST ? 0 : (valid ? seg_key(a, e.col) : 0);
+        const Key skey = FAST ? 0 : (valid ? (Key)seg_key(a, e.col) : 0);
         const bool hasB = valid && e.M > 0 && e.col + 1 < send && ncol != e.col + 1;
         const int32_t M0B = hasB ? e.M + pc[e.col + 1] : kNeg;
         const uint32_t yM0B = e.yM;
-        const int64_t kA = (valid && M0A > 0) ? (int64_t)M0A + absss * (int64_t)e.col + skey : kNegKey;
-        const int64_t kB = (hasB && M0B > 0) ? (int64_t)M0B + absss * (int64_t)(e.col + 1) + skey : kNegKey;
-        int64_t lk = kA;
+        const Key kA = (valid && M0A > 0) ? (Key)M0A + absss * (Key)e.col + skey : kNoKey;
+        const Key kB = (hasB && M0B > 0) ? (Key)M0B + absss * (Key)(e.col + 1) + skey : kNoKey;
+        Key lk = kA;
         uint32_t lt = yM0A;
         if (kB > lk) {
             lk = kB;
             lt = yM0B;
         }
-        int64_t exk, allk;
+        Key exk, allk;
         uint32_t ext_tag, allt;
         if constexpr (FAST) {
-            int32_t ex32, all32;
-            wave_excl_max_i32(lk > 0 ? (int32_t)lk : kNegKey32, ex32, all32);
-            exk = ex32 > 0 ? (int64_t)ex32 : kNegKey;
-            allk = all32 > 0 ? (int64_t)all32 : kNegKey;
+            wave_excl_max_i32(lk, exk, allk);
             ext_tag = allt = 0;
         } else {
             wave_excl_max(lk, lt, exk, ext_tag, allk, allt);
         }
         // carry-in: earlier rounds, then the waves before this one (earlier wins ties)
-        int64_t cin = c_key;
+        Key cin = c_key;
         uint32_t cint = c_tag;
         if (W > 1) {
             if (lane == 0) {
@@ -783,7 +785,7 @@ __device__ inline void wide_child_row(const SearchArgs &a, const Row cur, uint32
                 xg->tag[par][wave] = allt;
             }
             __syncthreads();
-            int64_t bk = c_key;
+            Key bk = c_key;
             uint32_t bt = c_tag;
 #pragma unroll
             for (int w2 = 0; w2 < W; ++w2) {
@@ -791,7 +793,7 @@ __device__ inline void wide_child_row(const SearchArgs &a, const Row cur, uint32
                     cin = bk;
                     cint = bt;
                 }
-                const int64_t kk = xg->key[par][w2];
+                const Key kk = (Key)xg->key[par][w2];
                 if (kk > bk) {
                     bk = kk;
                     bt = xg->tag[par][w2];
@@ -806,8 +808,8 @@ __device__ inline void wide_child_row(const SearchArgs &a, const Row cur, uint32
         }
         // G_b and M at A
         int32_t GbA = kNeg;
-        if (valid && exk > kNegKey) {
-            const int64_t v = exk + a.sg - absss * (int64_t)e.col - skey;
+        if (valid && exk > kNoKey) {
+            const Key v = exk + a.sg - absss * (Key)e.col - skey;
             GbA = v > 0 ? (int32_t)v : kNeg;
         }
         int32_t MA = M0A;
@@ -819,15 +821,15 @@ __device__ inline void wide_child_row(const SearchArgs &a, const Row cur, uint32
         const bool keepMA = valid && keep_state(a, MA, e.col, rowgain);
         const bool keepGaA = valid && keep_state(a, GaA, e.col, rowgain);
         // G_b and M at B
-        int64_t kAB = exk;
+        Key kAB = exk;
         uint32_t tAB = ext_tag;
         if (kA > kAB) {
             kAB = kA;
             tAB = yM0A;
         }
         int32_t GbB = kNeg;
-        if (hasB && kAB > kNegKey) {
-            const int64_t v = kAB + a.sg - absss * (int64_t)(e.col + 1) - skey;
+        if (hasB && kAB > kNoKey) {
+            const Key v = kAB + a.sg - absss * (Key)(e.col + 1) - skey;
             GbB = v > 0 ? (int32_t)v : kNeg;
         }
         int32_t MB = M0B;
@@ -838,7 +840,7 @@ __device__ inline void wide_child_row(const SearchArgs &a, const Row cur, uint32
         }
         const bool keepMB = hasB && keep_state(a, MB, e.col + 1, rowgain);
         // G_b-only columns after this lane's last candidate, up to the next candidate
-        int64_t kinc = kAB;
+        Key kinc = kAB;
         uint32_t tinc = tAB;
         if (kB > kinc) {
             kinc = kB;
@@ -847,9 +849,9 @@ __device__ inline void wide_child_row(const SearchArgs &a, const Row cur, uint32
         const uint32_t lc = hasB ? e.col + 1 : e.col;
         const uint32_t stop = (ncol == kNone || ncol > send) ? send : ncol;
         uint32_t nspread = 0, nspread_hits = 0;
-        if (valid && kinc > kNegKey) {
+        if (valid && kinc > kNoKey) {
             for (uint32_t col = lc + 1; col < stop; ++col) {
-                const int64_t v = kinc + a.sg - absss * (int64_t)col - skey;
+                const Key v = kinc + a.sg - absss * (Key)col - skey;
                 if (v <= 0 || !keep_state(a, (int32_t)v, col, rowgain)) break;
                 ++nspread;
                 nspread_hits += (v >= a.H);
@@ -898,7 +900,7 @@ __device__ inline void wide_child_row(const SearchArgs &a, const Row cur, uint32
                 const uint32_t col = lc + 1 + s;
                 Entry w;
                 w.col = col;
-                w.M = (int32_t)(kinc + a.sg - absss * (int64_t)col - skey);
+                w.M = (int32_t)(kinc + a.sg - absss * (Key)col - skey);
                 w.Ga = kNeg;
                 w.yM = tinc;
                 w.yGa = 0;
@@ -931,7 +933,7 @@ __device__ inline void wide_child_row(const SearchArgs &a, const Row cur, uint32
             if (nB && MB >= a.H) put(e.col + 1, MB);
             for (uint32_t s = 0; s < nspread; ++s) {
                 const uint32_t col = lc + 1 + s;
-                const int32_t v = (int32_t)(kinc + a.sg - absss * (int64_t)col - skey);
+                const int32_t v = (int32_t)(kinc + a.sg - absss * (Key)col - skey);
                 if (v < a.H) break;
                 put(col, v);
             }

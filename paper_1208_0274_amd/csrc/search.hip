@@ -1159,7 +1159,7 @@ static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64
         HIP_TRY(hipEventElapsedTime(&ms, ws->evk0, ws->evk1));
         order_ms = ms;
     }
-    const uint32_t live_blocks = (uint32_t)cus * 2u;  // kWideWaves waves each
+    const uint32_t live_blocks = (uint32_t)cus * 3u;  // kWideWaves waves each
     // one query whose prefix-max keys fit 31 bits: the wave walkers' 32-bit scan
     const bool wide_fast = !multi && (int64_t)(std::max(1, a.smax) - a.ss) * (int64_t)m < (1ll << 30);
     if (ng > 0 || nw1 > 0) {
