@@ -82,14 +82,18 @@ def cpu_baseline(w, budget_s: float):
                       f"host has {cores} cores"}
 
 
+LEVEL_KERNEL = "k_level_tasks+k_expand_children"  # the trie-expansion step of one level (node phase, child phase)
+
+
 def measured_traffic():
-    """HBM bytes per launch of k_expand_level from the committed rocprofv3
-    counter summary (FETCH_SIZE and WRITE_SIZE scaled by a device-copy
-    calibration), or None when the kernel sources changed since it was taken."""
+    """HBM bytes per level of the trie-expansion kernels from the committed
+    rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE scaled by a
+    device-copy calibration), or None when the kernel sources changed since it
+    was taken."""
     import hashlib
     import re
 
-    path = os.path.join(ROOT, "profiles", "k_expand_level_traffic.md")
+    path = os.path.join(ROOT, "profiles", "trie_expansion_traffic.md")
     if not os.path.exists(path):
         return None
     text = open(path).read()
@@ -281,7 +285,7 @@ def main():
     ms = float(np.mean(times) * 1e3)
     st = stats[-1]
     entries_per_s = float(np.mean([s.entries / t for s, t in zip(stats, times)]))
-    level_ms = float(np.mean([s.level_lane_ms for s in stats]))  # k_expand_level alone
+    level_ms = float(np.mean([s.level_lane_ms for s in stats]))  # the two trie-expansion kernels of every level
     launches = max(1, st.level_lane_launches)
     alg_bytes = st.level_alg_bytes()
     achieved = alg_bytes / (level_ms * 1e-3) / 1e9 if level_ms > 0 else 0.0
@@ -310,7 +314,7 @@ def main():
                        "chain_wave_leftover": float(np.mean([s.wide_ms for s in stats])),
                        "sort_merge": float(np.mean([s.merge_ms for s in stats]))},
         "search_stats": {k: (float(v) if isinstance(v, float) else int(v)) for k, v in st.as_dict().items()},
-        "roofline": {"kernel": "k_expand_level", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+        "roofline": {"kernel": LEVEL_KERNEL, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "traffic_GBps": (traffic / (level_ms / launches * 1e-3) / 1e9) if traffic else None,
                      "alg_bytes_per_launch": alg_bytes / launches, "avg_launch_ms": level_ms / launches,

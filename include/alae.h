@@ -123,8 +123,9 @@ typedef struct {
     uint64_t partitioned;    /* lane-queue chains the work predictor sent to the first wave pass */
     uint64_t leftover;       /* wave-queue chains walked after the concurrent pass            */
     double order_ms;         /* device time of features, predictions and the partition        */
-    double level_lane_ms;    /* device time of the one-lane-per-node level kernel alone       */
-    uint64_t level_lane_launches; /* its launches                                          */
+    double level_lane_ms;    /* device time of the two trie-expansion kernels of the levels   */
+                             /* (node phase, then one lane per child row), wide rows apart   */
+    uint64_t level_lane_launches; /* levels that ran them                                  */
 } alae_stats;
 
 /*

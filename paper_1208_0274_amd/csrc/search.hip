@@ -1039,7 +1039,7 @@ static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64
             }
             if ((st = timed(expand_ms)) != ALAE_OK) return st;
             ++level_launches;
-            if (nn > 0) {  // the lane kernel alone (the roofline's kernel)
+            if (nn > 0) {  // the node and child phases alone (the trie-expansion kernels)
                 float lms = 0.f;
                 HIP_TRY(hipEventElapsedTime(&lms, ws->evk0, ws->evkm));
                 lane_ms += lms;
