@@ -12,7 +12,7 @@
 // Children with several occurrences form the next level; a child with one
 // occurrence becomes a chain item (BWT row + depth + row) for the chain
 // kernels.  Hits of multi-occurrence children are emitted here for every
-// occurrence (Algorithm 1, lines 6-10).
+// occurrence (Algorithm 1).
 #pragma once
 
 #include "row_update.h"

@@ -13,9 +13,9 @@
 //      score filter (Theorem 2 (ii)) and the length filter (Theorem 1); when a
 //      node becomes unique its states are checked for domination
 //      (Section 3.2); entries with M >= H are emitted for every occurrence
-//      (Algorithm 1, lines 6-10);
+//      (Algorithm 1);
 //   4. the emitted records are sorted by (query end, text end) and merged,
-//      keeping the largest score per pair (Algorithm 1, line 8-9).
+//      keeping the largest score per pair (Algorithm 1).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
