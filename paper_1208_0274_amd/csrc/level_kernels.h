@@ -3,8 +3,10 @@
 // FM-index of the reversed text, and its sparse row is computed from X's row
 // (Section 2.2 with the filters of Section 3).
 //
-//   k_expand_level       one lane per node whose row has at most kLaneRow
-//                        entries (almost all nodes);
+//   k_level_tasks        one lane per node whose row has at most kLaneRow
+//                        entries (almost all nodes): its non-empty children
+//                        as tasks;
+//   k_expand_children    one lane per task: the child's row;
 //   k_expand_level_wide  one wave per node with a longer row (stretches the
 //                        text repeats, e.g. overlapping copies of a query
 //                        segment).
@@ -48,9 +50,9 @@ constexpr int kLevelBlock = 256;
 // for 64 nodes.
 // ---------------------------------------------------------------------------
 struct ChildTask {
-    uint32_t node;  // index in the level's node list
-    uint32_t c;     // character appended
-    uint32_t lo, hi;
+    uint32_t lo, hi;  // the child's BWT range
+    uint32_t off;     // the parent's row (entries off .. off + len - 1 of the level)
+    uint32_t len_c;   // parent row length | appended character << 24
 };
 static_assert(sizeof(ChildTask) == 16, "child task is 16 bytes");
 
@@ -98,7 +100,8 @@ __global__ void __launch_bounds__(kTaskBlock) k_level_tasks(SearchArgs a, const 
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
             if (!(mask & (1u << c))) continue;
-            if (base < caps.tasks) tasks[base] = ChildTask{t, (uint32_t)c, a.C[c] + o_lo[c], a.C[c] + o_hi[c] - 1};
+            if (base < caps.tasks)
+                tasks[base] = ChildTask{a.C[c] + o_lo[c], a.C[c] + o_hi[c] - 1, nd.off, nd.len | ((uint32_t)c << 24)};
             ++base;
         }
     } else {
@@ -106,14 +109,14 @@ __global__ void __launch_bounds__(kTaskBlock) k_level_tasks(SearchArgs a, const 
             const int c = __ffs(mm) - 1;
             const uint32_t lo = a.C[c] + occ1_gen(a, c, (int64_t)nd.lo - 1);
             const uint32_t hi = a.C[c] + occ1_gen(a, c, (int64_t)nd.hi) - 1;
-            if (base < caps.tasks) tasks[base] = ChildTask{t, (uint32_t)c, lo, hi};
+            if (base < caps.tasks) tasks[base] = ChildTask{lo, hi, nd.off, nd.len | ((uint32_t)c << 24)};
             ++base;
         }
     }
 }
 
 // One child row per lane, staged in LDS.
-__global__ void __launch_bounds__(kLevelBlock) k_expand_children(SearchArgs a, const Node *nodes, const Entry *ent,
+__global__ void __launch_bounds__(kLevelBlock) k_expand_children(SearchArgs a, const Entry *ent,
                                                                  const ChildTask *tasks, int32_t d1, LevelOut o,
                                                                  Caps caps, Counters *cnt) {
     __shared__ uint32_t s_stage[kLevelBlock * kStageWords];
@@ -123,13 +126,11 @@ __global__ void __launch_bounds__(kLevelBlock) k_expand_children(SearchArgs a, c
     if ((uint64_t)blockIdx.x * blockDim.x >= ntasks) return;  // whole block past the end
     const bool active = t < ntasks && t < caps.tasks;
     Entry *stage = reinterpret_cast<Entry *>(s_stage + threadIdx.x * kStageWords);
-    ChildTask tk{0, 0, 1, 0};
-    Node nd{0, 0, 0, 0};
-    if (active) {
-        tk = tasks[t];
-        nd = nodes[tk.node];
-    }
-    const Entry *prow = ent + nd.off;
+    ChildTask tk{1, 0, 0, 0};
+    if (active) tk = tasks[t];
+    const Entry *prow = ent + tk.off;
+    const uint32_t plen = tk.len_c & 0xFFFFFFu;
+    const int tc = (int)(tk.len_c >> 24);
     const bool multi = tk.lo < tk.hi;
     bool staged = true;
     uint32_t n_ent = 0, n_hits = 0, st_d = 0, st_2 = 0, st_3 = 0;
@@ -142,7 +143,7 @@ __global__ void __launch_bounds__(kLevelBlock) k_expand_children(SearchArgs a, c
         s.cap = (uint32_t)kStage;
         s.hit_cap = 0;  // count hits now, write them after the allocation
         if (!multi) s.emit_hits = false;
-        child_row<true>(a, prow, nd.len, (int)tk.c, d1, false, 0, s);
+        child_row<true>(a, prow, plen, tc, d1, false, 0, s);
         n_ent = s.n_entries;
         n_hits = s.n_hits;
         st_d = s.st_diag;
@@ -218,7 +219,7 @@ __global__ void __launch_bounds__(kLevelBlock) k_expand_children(SearchArgs a, c
             s.hit_base = hslot;
             s.hit_cap = caps.hits;
             if (!multi) s.emit_hits = false;
-            child_row<true>(a, prow, nd.len, (int)tk.c, d1, false, 0, s);
+            child_row<true>(a, prow, plen, tc, d1, false, 0, s);
         }
     }
 }

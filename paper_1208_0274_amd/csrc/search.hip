@@ -1027,7 +1027,7 @@ static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64
                                                                           ws->tasks, caps, ws->d_cnt);
                 const uint64_t maxtasks = (uint64_t)sigma * nn;
                 k_expand_children<<<(uint32_t)((maxtasks + kLevelBlock - 1) / kLevelBlock), kLevelBlock, 0, s>>>(
-                    a, ws->nodes[cur], ws->ents[cur], ws->tasks, d1, o, caps, ws->d_cnt);
+                    a, ws->ents[cur], ws->tasks, d1, o, caps, ws->d_cnt);
             }
             HIP_TRY(hipEventRecord(ws->evkm, s));
             if (nlw > 0) {
