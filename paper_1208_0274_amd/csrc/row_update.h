@@ -154,6 +154,17 @@ __device__ inline bool keep_state(const SearchArgs &a, int32_t v, uint32_t col, 
     return v + g >= a.H;
 }
 
+// keep_state for a single query (SINGLE): no segment lookups.
+template <bool SINGLE>
+__device__ inline bool keep_state_q(const SearchArgs &a, int32_t v, uint32_t col, int32_t rowgain) {
+    if (!SINGLE) return keep_state(a, v, col, rowgain);
+    if (v <= 0) return false;
+    if (!a.use_score_filter) return true;
+    int32_t g = a.u_closed ? a.smax * (int32_t)(a.m - 1 - col) : a.U[col];
+    if (rowgain < g) g = rowgain;
+    return v + g >= a.H;
+}
+
 // ---------------------------------------------------------------------------
 // Sequential (one lane) row update
 // ---------------------------------------------------------------------------
@@ -818,8 +829,8 @@ __device__ inline void wide_child_row(const SearchArgs &a, const Row cur, uint32
             MA = GbA;
             yMA = ext_tag;
         }
-        const bool keepMA = valid && keep_state(a, MA, e.col, rowgain);
-        const bool keepGaA = valid && keep_state(a, GaA, e.col, rowgain);
+        const bool keepMA = valid && keep_state_q<FAST>(a, MA, e.col, rowgain);
+        const bool keepGaA = valid && keep_state_q<FAST>(a, GaA, e.col, rowgain);
         // G_b and M at B
         Key kAB = exk;
         uint32_t tAB = ext_tag;
@@ -838,7 +849,7 @@ __device__ inline void wide_child_row(const SearchArgs &a, const Row cur, uint32
             MB = GbB;
             yMB = tAB;
         }
-        const bool keepMB = hasB && keep_state(a, MB, e.col + 1, rowgain);
+        const bool keepMB = hasB && keep_state_q<FAST>(a, MB, e.col + 1, rowgain);
         // G_b-only columns after this lane's last candidate, up to the next candidate
         Key kinc = kAB;
         uint32_t tinc = tAB;
@@ -852,7 +863,7 @@ __device__ inline void wide_child_row(const SearchArgs &a, const Row cur, uint32
         if (valid && kinc > kNoKey) {
             for (uint32_t col = lc + 1; col < stop; ++col) {
                 const Key v = kinc + a.sg - absss * (Key)col - skey;
-                if (v <= 0 || !keep_state(a, (int32_t)v, col, rowgain)) break;
+                if (v <= 0 || !keep_state_q<FAST>(a, (int32_t)v, col, rowgain)) break;
                 ++nspread;
                 nspread_hits += (v >= a.H);
             }
