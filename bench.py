@@ -321,6 +321,17 @@ def main():
                      "launches_per_step": int(st.level_lane_launches)},
     }
     if not args.no_extras:
+        log("autotuner: launch shapes")
+        shapes, rep = ws.autotune(dq, H, sc, reps=2)
+        tuned = []
+        for _ in range(args.steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ws.search_device(dq, H, sc, **shapes)
+            torch.cuda.synchronize()
+            tuned.append(time.perf_counter() - t0)
+        out["autotune"] = {"shapes": shapes, "default_device_ms": rep["default_ms"], "best_device_ms": rep["best_ms"],
+                           "trials": len(rep["trials"]), "tuned_step_ms": float(np.mean(tuned) * 1e3)}
         log("learned scheduling: trace, train, timed searches")
         out["learned_scheduling"] = learned_scheduling(alae, ws, dq, H, sc, args.steps, ms)
         log("serving: Poisson arrivals")

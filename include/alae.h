@@ -174,6 +174,10 @@ typedef struct {
     alae_trace *trace;         /* record (features, work) of every chain item when not NULL */
     float partition_threshold; /* with order_model: predicted log2(1 + work) from which a lane-queue
                                   chain is walked by the wave walker from its start (<= 0: never) */
+    /* launch shapes (alae_autotune picks them; none changes the hit set) */
+    int32_t level_stage;        /* LDS stage entries per lane of the child phase: 2, 4 or 8 (0 = 4) */
+    int32_t wide_blocks_per_cu; /* wave-walker blocks per compute unit, 1..8 (0 = 3)             */
+    int32_t lane_waves_per_cu;  /* lane-walker waves per compute unit, 1..16 (0 = 8)             */
 } alae_search_opts;
 
 /* Index options; pass NULL for the defaults. */
@@ -281,6 +285,30 @@ void alae_workspace_free(alae_workspace *ws);
 alae_status alae_search_device(alae_workspace *ws, const uint8_t *d_query_codes, size_t m,
                                const alae_scoring *scoring, int32_t H, const alae_search_opts *opts,
                                void *stream, size_t *hit_count);
+/*
+ * Launch-shape autotuner.  Times searches of one device-resident query (as in
+ * alae_search_device) with the launch shapes of alae_search_opts changed one
+ * at a time (coordinate descent: wave-walker blocks per CU in {2,3,4,6},
+ * lane-walker waves per CU in {4,8,12}, child-phase LDS stage in {2,4,8}; a
+ * change is kept when it is at least 1% faster), each timing the mean device
+ * time of `reps` searches after one warm-up search.  opts is in/out: its other
+ * fields are used as given (trace is ignored) and the chosen shapes are
+ * written back.  Every trial must return the same hit count, otherwise
+ * ALAE_E_INTERNAL.  The workspace result afterwards is that of the last trial.
+ */
+typedef struct {
+    int32_t level_stage, wide_blocks_per_cu, lane_waves_per_cu;
+    double ms;  /* mean device time of a search with these shapes */
+} alae_tune_trial;
+typedef struct {
+    double default_ms;         /* with the shapes passed in (0 = defaults)  */
+    double best_ms;            /* with the chosen shapes                     */
+    int32_t trials;            /* entries of trial[] filled                  */
+    alae_tune_trial trial[16];
+} alae_tune_report;
+alae_status alae_autotune(alae_workspace *ws, const uint8_t *d_query_codes, size_t m, const alae_scoring *scoring,
+                          int32_t H, alae_search_opts *opts, int32_t reps, void *stream, alae_tune_report *report);
+
 /*
  * Device-resident batch: d_query_codes holds the k queries end to end
  * (lens[i] > 0 codes each, host array lens).  The workspace result is then

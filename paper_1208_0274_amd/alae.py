@@ -97,7 +97,19 @@ class SearchOpts(ctypes.Structure):
                 ("use_reuse", ctypes.c_int32), ("order_queues", ctypes.c_int32),
                 ("entry_capacity", ctypes.c_uint64), ("hit_capacity", ctypes.c_uint64),
                 ("stats", ctypes.POINTER(Stats)), ("order_model", ctypes.c_void_p),
-                ("trace", ctypes.POINTER(TraceStruct)), ("partition_threshold", ctypes.c_float)]
+                ("trace", ctypes.POINTER(TraceStruct)), ("partition_threshold", ctypes.c_float),
+                ("level_stage", ctypes.c_int32), ("wide_blocks_per_cu", ctypes.c_int32),
+                ("lane_waves_per_cu", ctypes.c_int32)]
+
+
+class TuneTrial(ctypes.Structure):
+    _fields_ = [("level_stage", ctypes.c_int32), ("wide_blocks_per_cu", ctypes.c_int32),
+                ("lane_waves_per_cu", ctypes.c_int32), ("ms", ctypes.c_double)]
+
+
+class TuneReport(ctypes.Structure):
+    _fields_ = [("default_ms", ctypes.c_double), ("best_ms", ctypes.c_double), ("trials", ctypes.c_int32),
+                ("trial", TuneTrial * 16)]
 
 
 class IndexOpts(ctypes.Structure):
@@ -148,6 +160,8 @@ _sig("alae_search_device", _st, _vp, _vp, ctypes.c_size_t, ctypes.POINTER(Scorin
 _sig("alae_search_device_batch", _st, _vp, _vp, ctypes.POINTER(ctypes.c_size_t), ctypes.c_size_t,
      ctypes.POINTER(Scoring), ctypes.c_int32, ctypes.POINTER(SearchOpts), _vp, ctypes.POINTER(ctypes.c_size_t))
 _sig("alae_workspace_batch_offsets", _st, _vp, ctypes.POINTER(ctypes.c_size_t), ctypes.c_size_t)
+_sig("alae_autotune", _st, _vp, _vp, ctypes.c_size_t, ctypes.POINTER(Scoring), ctypes.c_int32,
+     ctypes.POINTER(SearchOpts), ctypes.c_int32, _vp, ctypes.POINTER(TuneReport))
 class ServerOpts(ctypes.Structure):
     _fields_ = [("memory_budget", ctypes.c_uint64), ("max_inflight", ctypes.c_int32), ("max_batch", ctypes.c_int32)]
 
@@ -205,8 +219,11 @@ def make_scoring(sa=1, sb=-3, sg=-5, ss=-2, matrix=None):
 
 def make_opts(stats: Stats | None = None, use_domination=True, use_score_filter=True, use_qprefix=True,
               entry_capacity=0, hit_capacity=0, score_bits=0, use_reuse=False, order_model=None, trace=None,
-              order_queues=0, partition_threshold=0.0):
+              order_queues=0, partition_threshold=0.0, level_stage=0, wide_blocks_per_cu=0, lane_waves_per_cu=0):
     o = SearchOpts()
+    o.level_stage = int(level_stage)
+    o.wide_blocks_per_cu = int(wide_blocks_per_cu)
+    o.lane_waves_per_cu = int(lane_waves_per_cu)
     o.partition_threshold = float(partition_threshold)
     o.order_queues = int(order_queues)
     o.use_reuse = 1 if use_reuse else 0
@@ -375,6 +392,21 @@ class Workspace:
         _check(_lib.alae_search_device(self._h, _vp(d_query.data_ptr()), int(d_query.numel()), ctypes.byref(sc),
                                        int(H), ctypes.byref(opts), sptr, ctypes.byref(cnt)), "alae_search_device")
         return int(cnt.value)
+
+    def autotune(self, d_query, H: int, scoring: Scoring | None = None, reps: int = 2, stream=None, **opt):
+        """Pick the launch shapes for this query (alae_autotune).  Returns (shapes, report): shapes is a
+        dict of the three chosen options, to pass to search_device; report has the timings."""
+        sc = scoring if scoring is not None else make_scoring()
+        opts = make_opts(**opt)
+        rep = TuneReport()
+        sptr = _vp(stream.cuda_stream) if stream is not None else None
+        _check(_lib.alae_autotune(self._h, _vp(d_query.data_ptr()), int(d_query.numel()), ctypes.byref(sc), int(H),
+                                  ctypes.byref(opts), int(reps), sptr, ctypes.byref(rep)), "alae_autotune")
+        shapes = {"level_stage": opts.level_stage, "wide_blocks_per_cu": opts.wide_blocks_per_cu,
+                  "lane_waves_per_cu": opts.lane_waves_per_cu}
+        trials = [{"level_stage": r.level_stage, "wide_blocks_per_cu": r.wide_blocks_per_cu,
+                   "lane_waves_per_cu": r.lane_waves_per_cu, "ms": r.ms} for r in rep.trial[:rep.trials]]
+        return shapes, {"default_ms": rep.default_ms, "best_ms": rep.best_ms, "trials": trials}
 
     def search_device_batch(self, d_queries, lens, H: int, scoring: Scoring | None = None,
                             stats: Stats | None = None, stream=None, **opt) -> int:

@@ -34,12 +34,13 @@ struct LevelOut {
     unsigned long long node_base, wide_base, ent_base, chain_base, cent_base, hit_base;
 };
 
-// Child rows are computed into a per-lane LDS stage of kStage entries; the
+// Child rows are computed into a per-lane LDS stage of STAGE entries; the
 // wave then allocates its outputs with one atomic per buffer and each lane
 // copies its stage out.  A longer child row is counted first and computed
 // again straight into its allocated place.
-constexpr int kStage = 4;
-constexpr int kStageWords = kStage * 5 + 1;  // one pad word: lanes start in different banks
+constexpr int kStageDefault = 4;  // the search picks 2, 4 or 8 (alae_search_opts.level_stage)
+// words of one lane's stage; one pad word so that lanes start in different banks
+constexpr int stage_words(int stage) { return stage * 5 + 1; }
 constexpr int kLevelBlock = 256;
 
 // ---------------------------------------------------------------------------
@@ -115,17 +116,18 @@ __global__ void __launch_bounds__(kTaskBlock) k_level_tasks(SearchArgs a, const 
     }
 }
 
-// One child row per lane, staged in LDS.
+// One child row per lane, staged in LDS (STAGE entries a lane).
+template <int STAGE>
 __global__ void __launch_bounds__(kLevelBlock) k_expand_children(SearchArgs a, const Entry *ent,
                                                                  const ChildTask *tasks, int32_t d1, LevelOut o,
                                                                  Caps caps, Counters *cnt) {
-    __shared__ uint32_t s_stage[kLevelBlock * kStageWords];
+    __shared__ uint32_t s_stage[kLevelBlock * stage_words(STAGE)];
     __shared__ BlockReserveLds<12, kLevelBlock / 64> s_res;
     const uint64_t ntasks = cnt->tasks;  // written by the node phase before this launch
     const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
     if ((uint64_t)blockIdx.x * blockDim.x >= ntasks) return;  // whole block past the end
     const bool active = t < ntasks && t < caps.tasks;
-    Entry *stage = reinterpret_cast<Entry *>(s_stage + threadIdx.x * kStageWords);
+    Entry *stage = reinterpret_cast<Entry *>(s_stage + threadIdx.x * stage_words(STAGE));
     ChildTask tk{1, 0, 0, 0};
     if (active) tk = tasks[t];
     const Entry *prow = ent + tk.off;
@@ -140,7 +142,7 @@ __global__ void __launch_bounds__(kLevelBlock) k_expand_children(SearchArgs a, c
         s.lo = tk.lo;
         s.hi = tk.hi;
         s.out = stage;
-        s.cap = (uint32_t)kStage;
+        s.cap = (uint32_t)STAGE;
         s.hit_cap = 0;  // count hits now, write them after the allocation
         if (!multi) s.emit_hits = false;
         child_row<true>(a, prow, plen, tc, d1, false, 0, s);

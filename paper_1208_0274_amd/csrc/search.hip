@@ -894,7 +894,11 @@ static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64
     int32_t depth = seed_depth;
     int cus = 256;
     hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ws->device);
-    const uint32_t max_waves = (uint32_t)cus * 8u;
+    // launch shapes (alae_search_opts; validated by the entry points)
+    const int level_stage = (opts && opts->level_stage) ? opts->level_stage : kStageDefault;
+    const uint32_t wide_bpc = (opts && opts->wide_blocks_per_cu) ? (uint32_t)opts->wide_blocks_per_cu : 3u;
+    const uint32_t lane_wpc = (opts && opts->lane_waves_per_cu) ? (uint32_t)opts->lane_waves_per_cu : 8u;
+    const uint32_t max_waves = (uint32_t)cus * lane_wpc;
     const uint64_t wrow = m + 2;  // a row never holds more than m entries
     // staging rows of the level-wide kernel start short and grow to the longest child row met
     uint64_t srow = std::min<uint64_t>(wrow, 4096);
@@ -1026,8 +1030,16 @@ static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64
                 k_level_tasks<<<(uint32_t)((nn + kTaskBlock - 1) / kTaskBlock), kTaskBlock, 0, s>>>(a, ws->nodes[cur], (uint32_t)nn,
                                                                           ws->tasks, caps, ws->d_cnt);
                 const uint64_t maxtasks = (uint64_t)sigma * nn;
-                k_expand_children<<<(uint32_t)((maxtasks + kLevelBlock - 1) / kLevelBlock), kLevelBlock, 0, s>>>(
-                    a, ws->ents[cur], ws->tasks, d1, o, caps, ws->d_cnt);
+                const uint32_t cblocks = (uint32_t)((maxtasks + kLevelBlock - 1) / kLevelBlock);
+                if (level_stage == 2)
+                    k_expand_children<2><<<cblocks, kLevelBlock, 0, s>>>(a, ws->ents[cur], ws->tasks, d1, o, caps,
+                                                                         ws->d_cnt);
+                else if (level_stage == 8)
+                    k_expand_children<8><<<cblocks, kLevelBlock, 0, s>>>(a, ws->ents[cur], ws->tasks, d1, o, caps,
+                                                                         ws->d_cnt);
+                else
+                    k_expand_children<4><<<cblocks, kLevelBlock, 0, s>>>(a, ws->ents[cur], ws->tasks, d1, o, caps,
+                                                                         ws->d_cnt);
             }
             HIP_TRY(hipEventRecord(ws->evkm, s));
             if (nlw > 0) {
@@ -1159,7 +1171,7 @@ static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64
         HIP_TRY(hipEventElapsedTime(&ms, ws->evk0, ws->evk1));
         order_ms = ms;
     }
-    const uint32_t live_blocks = (uint32_t)cus * 3u;  // kWideWaves waves each
+    const uint32_t live_blocks = (uint32_t)cus * wide_bpc;  // kWideWaves waves each
     // one query whose prefix-max keys fit 31 bits: the wave walkers' 32-bit scan
     const bool wide_fast = !multi && (int64_t)(std::max(1, a.smax) - a.ss) * (int64_t)m < (1ll << 30);
     if (ng > 0 || nw1 > 0) {
@@ -1435,6 +1447,16 @@ static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64
 
 }  // namespace alae
 
+// Launch-shape options: 0 (default) or a supported value.
+static bool launch_shapes_ok(const alae_search_opts *o, const char *where) {
+    if (!o) return true;
+    const bool ok = (o->level_stage == 0 || o->level_stage == 2 || o->level_stage == 4 || o->level_stage == 8) &&
+                    o->wide_blocks_per_cu >= 0 && o->wide_blocks_per_cu <= 8 && o->lane_waves_per_cu >= 0 &&
+                    o->lane_waves_per_cu <= 16;
+    if (!ok) set_error("%s: level_stage must be 0, 2, 4 or 8, wide_blocks_per_cu 0..8, lane_waves_per_cu 0..16", where);
+    return ok;
+}
+
 extern "C" {
 
 alae_status alae_workspace_create(const alae_index *index, alae_workspace **out) {
@@ -1479,6 +1501,7 @@ alae_status alae_search_device(alae_workspace *ws, const uint8_t *d_query_codes,
         set_error("alae_search_device: null argument");
         return ALAE_E_ARG;
     }
+    if (!launch_shapes_ok(opts, "alae_search_device")) return ALAE_E_ARG;
     HIP_TRY(hipSetDevice(ws->device));
     hipStream_t s = (hipStream_t)stream;
     HIP_TRY(hipEventRecord(ws->ev0, s));
@@ -1496,9 +1519,87 @@ alae_status alae_search_device(alae_workspace *ws, const uint8_t *d_query_codes,
     return ALAE_OK;
 }
 
+alae_status alae_autotune(alae_workspace *ws, const uint8_t *d_query_codes, size_t m, const alae_scoring *scoring,
+                          int32_t H, alae_search_opts *opts, int32_t reps, void *stream, alae_tune_report *report) {
+    if (!ws || !d_query_codes || !opts || !report || reps < 1) {
+        set_error("alae_autotune: null argument or reps < 1");
+        return ALAE_E_ARG;
+    }
+    if (!launch_shapes_ok(opts, "alae_autotune")) return ALAE_E_ARG;
+    alae_search_opts o = *opts;
+    o.trace = nullptr;  // tracing would change what is timed
+    if (!o.level_stage) o.level_stage = kStageDefault;
+    if (!o.wide_blocks_per_cu) o.wide_blocks_per_cu = 3;
+    if (!o.lane_waves_per_cu) o.lane_waves_per_cu = 8;
+    memset(report, 0, sizeof(*report));
+    size_t want = 0;
+    bool have = false;
+    // mean device time of `reps` searches with the shapes of c; every search must give the same hit count
+    auto timed = [&](const alae_search_opts &c, double *ms) -> alae_status {
+        alae_stats st;
+        alae_search_opts r = c;
+        r.stats = &st;
+        double sum = 0.0;
+        for (int i = 0; i < reps; ++i) {
+            size_t cnt = 0;
+            memset(&st, 0, sizeof(st));
+            const alae_status e = alae_search_device(ws, d_query_codes, m, scoring, H, &r, stream, &cnt);
+            if (e != ALAE_OK) return e;
+            if (have && cnt != want) {
+                set_error("alae_autotune: hit count changed with the launch shapes (%zu, %zu)", cnt, want);
+                return ALAE_E_INTERNAL;
+            }
+            want = cnt;
+            have = true;
+            sum += st.device_ms;
+        }
+        *ms = sum / reps;
+        if (report->trials < (int32_t)(sizeof(report->trial) / sizeof(report->trial[0]))) {
+            alae_tune_trial &tr = report->trial[report->trials++];
+            tr.level_stage = c.level_stage;
+            tr.wide_blocks_per_cu = c.wide_blocks_per_cu;
+            tr.lane_waves_per_cu = c.lane_waves_per_cu;
+            tr.ms = *ms;
+        }
+        return ALAE_OK;
+    };
+    double warm = 0.0;
+    alae_status st = timed(o, &warm);  // warm-up: buffers grow to the query's needs
+    if (st != ALAE_OK) return st;
+    report->trials = 0;
+    double best_ms = 0.0;
+    if ((st = timed(o, &best_ms)) != ALAE_OK) return st;
+    report->default_ms = best_ms;
+    // coordinate descent over the three shapes; a change must win by 1%
+    const int32_t wide_c[] = {2, 3, 4, 6}, lane_c[] = {4, 8, 12}, stage_c[] = {2, 4, 8};
+    for (int pass = 0; pass < 3; ++pass) {
+        const int32_t *cand = pass == 0 ? wide_c : pass == 1 ? lane_c : stage_c;
+        const int nc = pass == 0 ? 4 : 3;
+        const int32_t start = pass == 0 ? o.wide_blocks_per_cu : pass == 1 ? o.lane_waves_per_cu : o.level_stage;
+        for (int i = 0; i < nc; ++i) {
+            if (cand[i] == start) continue;  // timed already
+            alae_search_opts c = o;
+            int32_t &field = pass == 0 ? c.wide_blocks_per_cu : pass == 1 ? c.lane_waves_per_cu : c.level_stage;
+            field = cand[i];
+            double ms = 0.0;
+            if ((st = timed(c, &ms)) != ALAE_OK) return st;
+            if (ms < 0.99 * best_ms) {
+                best_ms = ms;
+                o = c;
+            }
+        }
+    }
+    report->best_ms = best_ms;
+    opts->level_stage = o.level_stage;
+    opts->wide_blocks_per_cu = o.wide_blocks_per_cu;
+    opts->lane_waves_per_cu = o.lane_waves_per_cu;
+    return ALAE_OK;
+}
+
 alae_status alae_search_device_batch(alae_workspace *ws, const uint8_t *d_query_codes, const size_t *lens, size_t k,
                                      const alae_scoring *scoring, int32_t H, const alae_search_opts *opts,
                                      void *stream, size_t *hit_count) {
+    if (!launch_shapes_ok(opts, "alae_search_device_batch")) return ALAE_E_ARG;
     if (!ws || !d_query_codes || !lens || !hit_count || k == 0) {
         set_error("alae_search_device_batch: null argument or empty batch");
         return ALAE_E_ARG;
@@ -1653,6 +1754,7 @@ alae_status alae_search(const alae_index *index, const char *query, size_t m, co
         alae_status vs = check_scoring(scoring, index->sigma, H, sch);
         if (vs != ALAE_OK) return vs;
     }
+    if (!launch_shapes_ok(opts, "alae_search")) return ALAE_E_ARG;
     alae_workspace *ws = nullptr;
     alae_status st = alae_workspace_create(index, &ws);
     if (st != ALAE_OK) return st;

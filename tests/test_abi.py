@@ -58,3 +58,13 @@ def test_query_validation():
     with pytest.raises(alae.AlaeError) as ei:
         alae.search(idx, "ACGT", 3, alae.make_scoring(matrix=m))
     assert ei.value.status == 3
+
+
+@pytest.mark.parametrize("shape", [dict(level_stage=3), dict(level_stage=16), dict(wide_blocks_per_cu=9),
+                                   dict(lane_waves_per_cu=17), dict(wide_blocks_per_cu=-1)])
+def test_launch_shape_validation(shape):
+    """Unsupported launch shapes are rejected before any device work."""
+    idx = alae.Index.build("ACGTACGTTTGACA", "dna")
+    with pytest.raises(alae.AlaeError) as ei:
+        alae.search(idx, "ACGT", 3, **shape)
+    assert ei.value.status == 1
