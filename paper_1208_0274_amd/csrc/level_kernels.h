@@ -116,16 +116,12 @@ __global__ void __launch_bounds__(kTaskBlock) k_level_tasks(SearchArgs a, const 
     }
 }
 
-// One child row per lane, staged in LDS (STAGE entries a lane).
+// The tasks base .. base + kLevelBlock - 1 of one block (t = this lane's).
 template <int STAGE>
-__global__ void __launch_bounds__(kLevelBlock) k_expand_children(SearchArgs a, const Entry *ent,
-                                                                 const ChildTask *tasks, int32_t d1, LevelOut o,
-                                                                 Caps caps, Counters *cnt) {
-    __shared__ uint32_t s_stage[kLevelBlock * stage_words(STAGE)];
-    __shared__ BlockReserveLds<12, kLevelBlock / 64> s_res;
-    const uint64_t ntasks = cnt->tasks;  // written by the node phase before this launch
-    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-    if ((uint64_t)blockIdx.x * blockDim.x >= ntasks) return;  // whole block past the end
+__device__ inline void expand_child_tile(const SearchArgs &a, const Entry *ent, const ChildTask *tasks, int32_t d1,
+                                         const LevelOut &o, const Caps &caps, Counters *cnt, uint64_t t,
+                                         uint64_t ntasks, uint32_t *s_stage,
+                                         BlockReserveLds<12, kLevelBlock / 64> &s_res) {
     const bool active = t < ntasks && t < caps.tasks;
     Entry *stage = reinterpret_cast<Entry *>(s_stage + threadIdx.x * stage_words(STAGE));
     ChildTask tk{1, 0, 0, 0};
@@ -224,6 +220,21 @@ __global__ void __launch_bounds__(kLevelBlock) k_expand_children(SearchArgs a, c
             child_row<true>(a, prow, plen, tc, d1, false, 0, s);
         }
     }
+}
+
+// One child row per lane, staged in LDS (STAGE entries a lane).  The grid is
+// sized for the most tasks a level can have (the host does not wait for the
+// node phase's count); blocks past the tasks it made leave at once.
+template <int STAGE>
+__global__ void __launch_bounds__(kLevelBlock) k_expand_children(SearchArgs a, const Entry *ent,
+                                                                 const ChildTask *tasks, int32_t d1, LevelOut o,
+                                                                 Caps caps, Counters *cnt) {
+    __shared__ uint32_t s_stage[kLevelBlock * stage_words(STAGE)];
+    __shared__ BlockReserveLds<12, kLevelBlock / 64> s_res;
+    const uint64_t ntasks = cnt->tasks;  // written by the node phase before this launch
+    const uint64_t base = (uint64_t)blockIdx.x * kLevelBlock;
+    if (base >= ntasks) return;  // the whole block
+    expand_child_tile<STAGE>(a, ent, tasks, d1, o, caps, cnt, base + threadIdx.x, ntasks, s_stage, s_res);
 }
 
 // Hits of a staged row for every occurrence [lo, hi] (wave-parallel).

@@ -219,13 +219,30 @@ __global__ void pack_records(uint64_t *keys, const uint32_t *scores, uint64_t n,
 // key per tile, then (after a scan of the tile counts) write one record per
 // key at its place.  A group's largest score is found by reading on from its
 // first record.
-__device__ inline uint32_t group_starts(const uint64_t *recs, uint64_t n, int sb, uint64_t first, bool (&st)[kItems]) {
-    uint64_t prev = (first == 0 || first > n) ? ~0ull : recs[first - 1] >> sb;
+// The tile's records go through LDS: loaded with coalesced reads, then each
+// thread takes kItems consecutive ones.
+__device__ inline void load_tile(const uint64_t *recs, uint64_t n, uint64_t tile, uint64_t *s_rec) {
+    for (int k = threadIdx.x; k < kTile; k += kThreads) {
+        const uint64_t i = tile + k;
+        s_rec[k] = i < n ? recs[i] : 0ull;
+    }
+    __syncthreads();
+}
+
+__device__ inline uint32_t group_starts(const uint64_t *recs, const uint64_t *s_rec, uint64_t n, int sb,
+                                        uint64_t tile, bool (&st)[kItems]) {
+    const int k0 = threadIdx.x * kItems;
+    const uint64_t first = tile + k0;
+    uint64_t prev = ~0ull;
+    if (k0 > 0)
+        prev = s_rec[k0 - 1] >> sb;
+    else if (first > 0 && first <= n)
+        prev = recs[first - 1] >> sb;
     uint32_t c = 0;
 #pragma unroll
     for (int k = 0; k < kItems; ++k) {
         const uint64_t i = first + k;
-        const uint64_t key = i < n ? recs[i] >> sb : 0ull;
+        const uint64_t key = s_rec[k0 + k] >> sb;
         st[k] = i < n && (i == 0 || key != prev);
         c += st[k] ? 1u : 0u;
         prev = key;
@@ -235,37 +252,58 @@ __device__ inline uint32_t group_starts(const uint64_t *recs, uint64_t n, int sb
 
 __global__ void __launch_bounds__(kThreads) merge_count(const uint64_t *recs, uint64_t n, int sb,
                                                         uint32_t *tile_counts) {
-    const uint64_t first = (uint64_t)blockIdx.x * kTile + (uint64_t)threadIdx.x * kItems;
+    __shared__ uint64_t s_rec[kTile];
+    const uint64_t tile = (uint64_t)blockIdx.x * kTile;
+    load_tile(recs, n, tile, s_rec);
     bool st[kItems];
-    const uint32_t c = group_starts(recs, n, sb, first, st);
+    const uint32_t c = group_starts(recs, s_rec, n, sb, tile, st);
     uint32_t total;
     block_exclusive_scan(c, &total);
     if (threadIdx.x == 0) tile_counts[blockIdx.x] = total;
     if (blockIdx.x == 0 && threadIdx.x == 0) tile_counts[gridDim.x] = 0u;  // the scan leaves the total there
 }
 
+// One output record per key that starts in this tile, with the largest score
+// of its group (read on past the tile's end when the group continues);
+// written through LDS so that the tile's outputs leave as one coalesced run.
 __global__ void __launch_bounds__(kThreads) merge_emit(const uint64_t *recs, uint64_t n, int sb, int low_bits,
                                                        const uint32_t *tile_prefix, uint64_t *out_keys,
                                                        uint32_t *out_scores) {
-    const uint64_t first = (uint64_t)blockIdx.x * kTile + (uint64_t)threadIdx.x * kItems;
+    __shared__ uint64_t s_rec[kTile];
+    __shared__ uint64_t s_key[kTile];
+    __shared__ uint32_t s_score[kTile];
+    const uint64_t tile = (uint64_t)blockIdx.x * kTile;
+    load_tile(recs, n, tile, s_rec);
     bool st[kItems];
-    const uint32_t c = group_starts(recs, n, sb, first, st);
+    const uint32_t c = group_starts(recs, s_rec, n, sb, tile, st);
     uint32_t total;
-    uint64_t pos = (uint64_t)tile_prefix[blockIdx.x] + block_exclusive_scan(c, &total);
+    uint32_t pos = block_exclusive_scan(c, &total);
     const uint64_t smask = (1ull << sb) - 1;
+    const int k0 = threadIdx.x * kItems;
 #pragma unroll
     for (int k = 0; k < kItems; ++k) {
         if (!st[k]) continue;
-        const uint64_t i = first + k;
-        const uint64_t key = recs[i] >> sb;
-        uint64_t best = recs[i] & smask;
-        for (uint64_t j = i + 1; j < n && (recs[j] >> sb) == key; ++j) {
-            const uint64_t s = recs[j] & smask;
+        const uint64_t key = s_rec[k0 + k] >> sb;
+        uint64_t best = s_rec[k0 + k] & smask;
+        int j = k0 + k + 1;
+        for (; j < kTile && tile + j < n && (s_rec[j] >> sb) == key; ++j) {
+            const uint64_t s = s_rec[j] & smask;
             best = s > best ? s : best;
         }
-        out_keys[pos] = ((key >> low_bits) << 32) | (key & ((1ull << low_bits) - 1));
-        out_scores[pos] = (uint32_t)best;
+        if (j == kTile)  // the group may go on in the next tile
+            for (uint64_t g = tile + kTile; g < n && (recs[g] >> sb) == key; ++g) {
+                const uint64_t s = recs[g] & smask;
+                best = s > best ? s : best;
+            }
+        s_key[pos] = ((key >> low_bits) << 32) | (key & ((1ull << low_bits) - 1));
+        s_score[pos] = (uint32_t)best;
         ++pos;
+    }
+    __syncthreads();
+    const uint64_t out = tile_prefix[blockIdx.x];
+    for (uint32_t k = threadIdx.x; k < total; k += kThreads) {
+        out_keys[out + k] = s_key[k];
+        out_scores[out + k] = s_score[k];
     }
 }
 
