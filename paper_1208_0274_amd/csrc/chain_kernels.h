@@ -444,7 +444,7 @@ __global__ void __launch_bounds__(kStartBlock) k_chain_start(SearchArgs a, SubTa
                                             ~0ull,       ~0ull,         ~0ull, ~0ull, ~0ull};
         const uint32_t ovb[11] = {kOvGeneralNodes, kOvGeneralEntries, 0, 0, 0, 0, 0, 0, 0, 0, 0};
         unsigned long long b[11];
-        block_reserve<11, kStartBlock / 64>(s_res11, ctr, wtot, cap, ovb, &cnt->overflow, b);
+        block_reserve<11, kStartBlock / 64, 2>(s_res11, ctr, wtot, cap, ovb, &cnt->overflow, b);
         if (handoff && b[0] + t_n <= caps.gnodes && b[1] + t_e <= caps.gentries) {
             const unsigned long long slot = b[0] + p_n, off = b[1] + p_e;
             Entry *dst = q.gents + off;

@@ -95,7 +95,7 @@ __global__ void __launch_bounds__(kTaskBlock) k_level_tasks(SearchArgs a, const 
     const unsigned long long cap[4] = {caps.tasks, ~0ull, ~0ull, ~0ull};
     const uint32_t ovb[4] = {kOvTasks, 0, 0, 0};
     unsigned long long bases[4];
-    block_reserve<4, kTaskBlock / 64>(s_res, ctr, wtot, cap, ovb, &cnt->overflow, bases);
+    block_reserve<4, kTaskBlock / 64, 1>(s_res, ctr, wtot, cap, ovb, &cnt->overflow, bases);
     unsigned long long base = bases[0] + pre;
     if (a.sigma == 4) {
 #pragma unroll
@@ -176,7 +176,7 @@ __device__ inline void expand_child_tile(const SearchArgs &a, const Entry *ent, 
     const uint32_t ovb[12] = {kOvNodes, kOvLevelWide, kOvEntries, kOvChainNodes, kOvChainEntries, kOvHits,
                               0,        0,            0,          0,             0,               0};
     unsigned long long b[12];
-    block_reserve<12, kLevelBlock / 64>(s_res, ctr, wtot, cap, ovb, &cnt->overflow, b);
+    block_reserve<12, kLevelBlock / 64, 6>(s_res, ctr, wtot, cap, ovb, &cnt->overflow, b);
     const unsigned long long b_nodes = b[0], b_wide = b[1], b_ent = b[2], b_ch = b[3], b_ce = b[4], b_hits = b[5];
     const bool fits = b_nodes + u_nodes <= caps.nodes && b_wide + u_wide <= caps.lwnodes &&
                       b_ent + u_ent <= caps.entries && b_ch + u_ch <= caps.cnodes && b_ce + u_ce <= caps.centries;

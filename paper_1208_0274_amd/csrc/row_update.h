@@ -454,7 +454,9 @@ struct BlockReserveLds {
     unsigned long long base[NC];
 };
 
-template <int NC, int NW>
+// Counters from NRES on are statistics: added without waiting for the old
+// value (their base[] entries are 0).
+template <int NC, int NW, int NRES = NC>
 __device__ inline void block_reserve(BlockReserveLds<NC, NW> &sh, unsigned long long *const (&ctr)[NC],
                                      const unsigned long long (&tot)[NC], const unsigned long long (&cap)[NC],
                                      const uint32_t (&ovbit)[NC], unsigned long long *overflow,
@@ -474,9 +476,11 @@ __device__ inline void block_reserve(BlockReserveLds<NC, NW> &sh, unsigned long 
 #pragma unroll
             for (int w = 0; w < NW; ++w) all += sh.tot[w][c];
             unsigned long long b = 0;
-            if (all) {
+            if (all && c < NRES) {
                 b = atomicAdd(ctr[c], all);
                 if (b + all > cap[c]) of |= ovbit[c];
+            } else if (all) {
+                __hip_atomic_fetch_add(ctr[c], all, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
             sh.base[c] = b;
         }
