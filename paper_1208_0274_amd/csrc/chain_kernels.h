@@ -9,17 +9,19 @@
 //                    (Section 3.2), and walks it in registers while every
 //                    entry is in the no-gap region (M <= |sg+ss|, no G_a):
 //                    there the row update is the diagonal step of Eq. 3;
-//   k_chain_general  one lane per chain whose row has gap states (up to
-//                    kNarrowRow entries, kept in private memory);
-//   k_chain_wide_*   one wave per chain with a longer row (LDS, or global
-//                    memory for rows beyond kWideCap entries).
+//   k_chain_general  one lane per chain whose row has gap states (first row
+//                    up to kNarrowRow entries, later rows up to kPromoteRow,
+//                    kept in private memory);
+//   k_chain_wide_*   a block of waves (LDS rows) or one wave (global memory,
+//                    rows beyond kWideCap entries) per chain with a longer row.
 #pragma once
 
 #include "row_update.h"
 
 namespace alae {
 
-constexpr int kNarrowRow = 24;
+constexpr int kNarrowRow = 24;  // row capacity of the lane walker (a chain's first row may fill it)
+constexpr int kPromoteRow = 12; // a lane-walker row longer than this goes on to the wave walkers
 constexpr int kNgrSlots = 4;
 constexpr int kWideCap = 1024;  // row entries a wave walker keeps in LDS
 constexpr int kWideWaves = 4;   // waves of a wave-walker block (one chain per block)
@@ -473,7 +475,8 @@ __global__ void __launch_bounds__(kStartBlock) k_chain_start(SearchArgs a, SubTa
 
 // ---------------------------------------------------------------------------
 // k_chain_general: one lane per chain with gap states; idle lanes take the
-// next queue items.  A row wider than kNarrowRow goes to the wave walkers.
+// next queue items.  A row wider than kPromoteRow goes to the wave walkers:
+// the lane walks a row one entry at a time, a wave-walker block 256 at once.
 // ---------------------------------------------------------------------------
 // order (nullable) gives the sequence in which queue items are taken;
 // trace_work (nullable) receives each item's work (entries computed + rows).
@@ -543,7 +546,7 @@ __global__ void __launch_bounds__(256) k_chain_general(SearchArgs a, const Node 
                 child_row<true>(a, rows[cur], len, c, d1, false, 0, s);
                 ++n_steps;
                 my_work += (float)s.n_entries;
-                if (s.n_entries > (uint32_t)kNarrowRow) {
+                if (s.n_entries > (uint32_t)kPromoteRow) {
                     push_wide(a, rows[cur], len, e_end, depth, witems, went, caps, cnt, n_dom, my_item, wsrc, ready);
                     ++n_prom;
                     active = false;
