@@ -487,7 +487,13 @@ __global__ void __launch_bounds__(256) k_chain_general(SearchArgs a, const Node 
                                                        uint32_t *wsrc, uint32_t *ready) {
     const int lane = threadIdx.x & 63;
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    if (lane == 0) atomicMin(&cnt->t_gen0, (unsigned long long)__builtin_amdgcn_s_memrealtime());
+    if (lane == 0) {
+        atomicMin(&cnt->t_gen0, (unsigned long long)__builtin_amdgcn_s_memrealtime());
+        // counted before this wave's first claim: a wave walker that has seen every item
+        // claimed and as many finished waves as started ones knows that no push is left
+        __hip_atomic_fetch_add(&cnt->gen_started, 1ull, __ATOMIC_SEQ_CST, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __atomic_thread_fence(__ATOMIC_SEQ_CST);
     HitRes hr = {0, 0, 0};
     Entry rows[2][kNarrowRow];
     int cur = 0;
@@ -864,7 +870,7 @@ __device__ inline void wide_stats_flush(Counters *cnt, const WideStats &w, bool 
 struct LiveQueue {
     const uint32_t *ready;  // per slot: 0 pending, 1 written, 2 never written (nullptr: static pass)
     uint32_t nstatic;       // items 0 .. nstatic-1 were queued before the launch
-    uint32_t gen_waves;     // lane-walker waves whose end means no more items
+    uint64_t gen_items;     // lane-walker queue items (all claimed + every started wave done: no more pushes)
     uint32_t *missed;       // items claimed but given up (the next pass takes them)
     uint64_t patience;      // ticks of the 100 MHz clock to wait without any progress
 };
@@ -923,11 +929,28 @@ __global__ void __launch_bounds__(64 * kWideWaves) k_chain_wide_lds(SearchArgs a
                         __builtin_amdgcn_s_sleep(127);
                         continue;
                     }
+                    // producer finished: every item claimed and every started wave done, read in
+                    // this order (a claim precedes the read of the head, a claiming wave's start
+                    // precedes its claim, a wave's pushes precede its finish); polled with relaxed
+                    // loads (sequentially consistent ones would invalidate the CU's caches each
+                    // time) and confirmed with sequentially consistent ones
+                    auto finished = [&](int order) {
+                        const unsigned long long h = __hip_atomic_load(&cnt->general_head, order,
+                                                                       __HIP_MEMORY_SCOPE_AGENT);
+                        const unsigned long long s0 = __hip_atomic_load(&cnt->gen_started, order,
+                                                                        __HIP_MEMORY_SCOPE_AGENT);
+                        const unsigned long long d0 = __hip_atomic_load(&cnt->gen_done, order,
+                                                                        __HIP_MEMORY_SCOPE_AGENT);
+                        return h >= live.gen_items && d0 == s0;
+                    };
                     const unsigned long long done =
                         __hip_atomic_load(&cnt->gen_done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     const unsigned long long made =
                         __hip_atomic_load(&cnt->wnodes, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    if (done >= live.gen_waves) {
+                    // (a lane-walker wave finishes only once every item has been claimed, so
+                    // nothing needs checking before the first one has)
+                    if ((done > 0 || live.gen_items == 0) && finished(__ATOMIC_RELAXED) &&
+                        finished(__ATOMIC_SEQ_CST)) {
                         // every push has been published; a slot past the end stays empty
                         __atomic_thread_fence(__ATOMIC_ACQUIRE);
                         const uint32_t r2 =

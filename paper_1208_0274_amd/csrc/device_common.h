@@ -211,6 +211,7 @@ struct Counters {
     kCounter st_reused;       // entries replayed from an identical fork instead of computed
     kCounter st_replay;       // chains recognised as copies of one fork
     kCounter gen_done;        // lane-walker waves that have finished
+    kCounter gen_started;     // lane-walker waves that have begun (before their first claim)
     kCounter missed;          // wave-queue items a live consumer left for the next pass
     kCounter t_gen0, t_gen1;  // first start / last end of lane-walker waves (100 MHz clock)
     kCounter t_live0, t_live1;  // same for the live wave pass

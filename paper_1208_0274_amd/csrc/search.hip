@@ -1181,6 +1181,7 @@ static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64
             z.general_head = 0;
             z.wide_head = 0;
             z.gen_done = 0;
+            z.gen_started = 0;
             z.missed = 0;
             z.t_gen0 = z.t_live0 = z.t_push0 = ~0ull;
             z.t_gen1 = z.t_live1 = 0;
@@ -1207,7 +1208,7 @@ static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64
             LiveQueue lq;
             lq.ready = ws->ready;
             lq.nstatic = (uint32_t)nw1;
-            lq.gen_waves = ng > 0 ? gblocks * 4u : 0u;
+            lq.gen_items = ng;
             lq.missed = ws->missed;
             lq.patience = 20000000;  // 200 ms of the 100 MHz clock without any progress
             HIP_TRY(hipEventRecord(ws->evk0, s));
