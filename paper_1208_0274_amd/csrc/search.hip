@@ -1220,15 +1220,28 @@ static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64
                                                         ws->hkeys, ws->hscores, caps, ws->d_cnt, gq.order, gq.twork,
                                                         tracing ? ws->wsrc : nullptr, ws->ready);
             HIP_TRY(hipGetLastError());
-            if (wide_fast)
-                k_chain_wide_lds<true><<<live_blocks, 64 * kWideWaves, 0, ws->s2>>>(
-                    a, ws->wnodes, 0, 0xFFFFFFFFu, ws->wents, ws->onodes, ws->oents, ws->hkeys, ws->hscores, caps,
-                    ws->d_cnt, wq.order, tracing ? ws->qb[1].twork : nullptr, lq);
-            else
-                k_chain_wide_lds<false><<<live_blocks, 64 * kWideWaves, 0, ws->s2>>>(
-                    a, ws->wnodes, 0, 0xFFFFFFFFu, ws->wents, ws->onodes, ws->oents, ws->hkeys, ws->hscores, caps,
-                    ws->d_cnt, wq.order, tracing ? ws->qb[1].twork : nullptr, lq);
+            // At most two wave-walker blocks per CU run beside the lane walker: with more, walker
+            // blocks dispatched first could leave a CU no room for a lane-walker wave (whose
+            // pushes they wait for).  The rest start on the lane walker's stream once it ends and
+            // take items from the same queue.
+            const uint32_t live_during = std::min<uint32_t>(live_blocks, (uint32_t)cus * 2u);
+            const uint32_t live_after = live_blocks - live_during;
+            auto wide_live = [&](uint32_t blocks, hipStream_t st2) {
+                if (wide_fast)
+                    k_chain_wide_lds<true><<<blocks, 64 * kWideWaves, 0, st2>>>(
+                        a, ws->wnodes, 0, 0xFFFFFFFFu, ws->wents, ws->onodes, ws->oents, ws->hkeys, ws->hscores,
+                        caps, ws->d_cnt, wq.order, tracing ? ws->qb[1].twork : nullptr, lq);
+                else
+                    k_chain_wide_lds<false><<<blocks, 64 * kWideWaves, 0, st2>>>(
+                        a, ws->wnodes, 0, 0xFFFFFFFFu, ws->wents, ws->onodes, ws->oents, ws->hkeys, ws->hscores,
+                        caps, ws->d_cnt, wq.order, tracing ? ws->qb[1].twork : nullptr, lq);
+            };
+            wide_live(live_during, ws->s2);
             HIP_TRY(hipGetLastError());
+            if (live_after > 0) {
+                wide_live(live_after, s);
+                HIP_TRY(hipGetLastError());
+            }
             HIP_TRY(hipEventRecord(ws->ev_join, ws->s2));
             HIP_TRY(hipStreamWaitEvent(s, ws->ev_join, 0));
             if ((st = timed(general_ms)) != ALAE_OK) return st;
