@@ -128,8 +128,78 @@ def test_trace_work_accounts_for_promoted_chains():
     lane = W[X[:, 7] == 0]
     wide = W[X[:, 7] == 1]
     assert st.promoted > 0
-    # a promoted chain's own lane rows are at most 24 entries; its work record
-    # also holds the wave walk that followed, which starts with a row above 24
+    # a promoted chain's own lane rows are short (at most 24 entries, 12 after the
+    # first); its work record also holds the wave walk that followed
     assert lane.max() > 24 + 1
     assert wide.size > 0 and lane.sum() > 0
     print(f"items {tr.count}: lane work {lane.sum():.3e} wave work {wide.sum():.3e} promoted {st.promoted}", flush=True)
+
+
+def _list_schedule(work, workers):
+    """Makespan of greedy list scheduling of `work` (in the given order) on
+    identical workers: each item goes to the first worker that is free."""
+    import heapq
+
+    heap = [0.0] * workers
+    for w in work:
+        heapq.heapreplace(heap, heap[0] + float(w))
+    return max(heap)
+
+
+def test_learned_order_gain():
+    """What the trained network gains over the method without it (queue order),
+    judged against measured work: trained on the traced work of half of the
+    lane-queue items, it ranks the other half; ordering that half by the
+    prediction is scored by the share of the measured work its predicted-heaviest
+    tenth holds, and by the makespan of list scheduling that half's measured work
+    (as many workers as make the largest item a quarter of a worker's fair
+    share) next to queue order and the order of the true work.  The device time
+    of searches with and without the learned order is printed as well."""
+    import time
+
+    import torch
+    from scipy.stats import spearmanr
+
+    T, P = _planted(51)
+    idx = alae.Index.build(T, "dna")
+    tr = alae.Trace(1 << 20)
+    alae.search(idx, P, 30, trace=tr)
+    X, W = tr.arrays()
+    y = np.log2(1 + W)
+    train, test = np.arange(0, len(y), 2), np.arange(1, len(y), 2)
+    net = alae.MLP(seed=52)
+    net.train(X[train], y[train], epochs=12, batch=1024, lr=2e-3)
+    pred = net.predict(X[test])
+    rho = float(spearmanr(pred, y[test]).correlation)
+    w = W[test]
+    workers = max(2, int(w.sum() / (4.0 * w.max())))
+    mk_queue = _list_schedule(w, workers)
+    mk_pred = _list_schedule(w[np.argsort(-pred, kind="stable")], workers)
+    mk_true = _list_schedule(np.sort(w)[::-1], workers)
+    top = np.argsort(-pred, kind="stable")[: max(1, len(w) // 10)]
+    share = float(w[top].sum() / w.sum())
+    # device time: the same search with and without the learned order (both walkers' queues)
+    ws = alae.Workspace(idx)
+    dq = torch.from_numpy(P).to("cuda")
+    sc = alae.make_scoring()
+
+    def timed(**kw):
+        ts = []
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ws.search_device(dq, 30, sc, **kw)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        return float(np.median(ts) * 1e3)
+
+    timed()
+    plain_ms, learned_ms = timed(), timed(order_model=net, order_queues=3)
+    ws.free()
+    print(f"items {len(y)}: held-out spearman {rho:.3f}; top-10% predicted items hold {share:.1%} of the work; "
+          f"makespan on {workers} workers: queue order {mk_queue:.0f}, learned order {mk_pred:.0f} "
+          f"(gain {mk_queue / mk_pred:.3f}), true order {mk_true:.0f}; device {plain_ms:.2f} ms plain, "
+          f"{learned_ms:.2f} ms learned", flush=True)
+    assert rho > 0.0
+    assert share > 0.2  # the predicted-heavy tenth carries at least twice its share of the work
+    assert mk_pred <= 1.05 * mk_queue
