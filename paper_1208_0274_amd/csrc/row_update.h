@@ -339,14 +339,20 @@ __device__ void child_row(const SearchArgs &a, const Entry *prow, uint32_t plen,
         }
     };
 
+    // parent entries k-1, k, k+1 move along in registers: one load per entry,
+    // issued an entry ahead (the row's stores may alias it for the compiler)
+    Entry p{0, kNeg, kNeg, 0, 0};
+    Entry nx{0, kNeg, kNeg, 0, 0};
+    if (plen > 0) nx = prow[0];
     for (uint32_t k = 0; k < plen; ++k) {
-        const Entry e = prow[k];
+        const Entry e = nx;
+        const bool has_next = k + 1 < plen;
+        if (has_next) nx = prow[k + 1];
         const uint32_t j = e.col;
         // diagonal from the previous parent entry, if it sits in column j-1
         int32_t D = kNeg;
         uint32_t yD = 0;
         if (k > 0) {
-            const Entry p = prow[k - 1];
             if (p.col + 1 == j && p.M > 0 && !seg_first(a, j)) {
                 D = p.M + diag_after(p.col);
                 yD = p.yM;
@@ -365,9 +371,10 @@ __device__ void child_row(const SearchArgs &a, const Entry *prow, uint32_t plen,
         }
         column(j, D, yD, Gav, yGav);
         // diagonal into column j+1 when no parent entry sits there
-        if (e.M > 0 && j + 1 < seg_end_of(a, j) && !(k + 1 < plen && prow[k + 1].col == j + 1)) {
+        if (e.M > 0 && j + 1 < seg_end_of(a, j) && !(has_next && nx.col == j + 1)) {
             column(j + 1, e.M + diag_after(j), e.yM, kNeg, 0);
         }
+        p = e;
     }
     spread_to((int64_t)a.m - 1);
 }
