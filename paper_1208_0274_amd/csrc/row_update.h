@@ -257,8 +257,6 @@ template <bool WRITE>
 __device__ void child_row(const SearchArgs &a, const Entry *prow, uint32_t plen, int c, int32_t d1, bool check_dom,
                           int64_t x, RowSink &s, const int8_t *sub = nullptr) {
     const int8_t *pc = a.prof + (size_t)c * a.m;
-    // score of the diagonal step into the column after col
-    auto diag_after = [&](uint32_t col) -> int32_t { return pc[col + 1]; };
     const int32_t open = a.sg + a.ss;  // first gap character
     const int32_t ext = a.ss;
     const int32_t rowgain = a.smax * (a.lmax - d1);
@@ -341,20 +339,32 @@ __device__ void child_row(const SearchArgs &a, const Entry *prow, uint32_t plen,
 
     // parent entries k-1, k, k+1 move along in registers: one load per entry,
     // issued an entry ahead (the row's stores may alias it for the compiler)
+    // with the score of the diagonal step after each (clamped into the row:
+    // used only where the column exists)
+    const uint32_t lastcol = a.m - 1;
+    auto diag_score = [&](uint32_t col) -> int32_t { return pc[col < lastcol ? col + 1 : lastcol]; };
     Entry p{0, kNeg, kNeg, 0, 0};
     Entry nx{0, kNeg, kNeg, 0, 0};
-    if (plen > 0) nx = prow[0];
+    int32_t p_s = 0, nx_s = 0;
+    if (plen > 0) {
+        nx = prow[0];
+        nx_s = diag_score(nx.col);
+    }
     for (uint32_t k = 0; k < plen; ++k) {
         const Entry e = nx;
+        const int32_t e_s = nx_s;
         const bool has_next = k + 1 < plen;
-        if (has_next) nx = prow[k + 1];
+        if (has_next) {
+            nx = prow[k + 1];
+            nx_s = diag_score(nx.col);
+        }
         const uint32_t j = e.col;
         // diagonal from the previous parent entry, if it sits in column j-1
         int32_t D = kNeg;
         uint32_t yD = 0;
         if (k > 0) {
             if (p.col + 1 == j && p.M > 0 && !seg_first(a, j)) {
-                D = p.M + diag_after(p.col);
+                D = p.M + p_s;
                 yD = p.yM;
             }
         }
@@ -372,9 +382,10 @@ __device__ void child_row(const SearchArgs &a, const Entry *prow, uint32_t plen,
         column(j, D, yD, Gav, yGav);
         // diagonal into column j+1 when no parent entry sits there
         if (e.M > 0 && j + 1 < seg_end_of(a, j) && !(has_next && nx.col == j + 1)) {
-            column(j + 1, e.M + diag_after(j), e.yM, kNeg, 0);
+            column(j + 1, e.M + e_s, e.yM, kNeg, 0);
         }
         p = e;
+        p_s = e_s;
     }
     spread_to((int64_t)a.m - 1);
 }
