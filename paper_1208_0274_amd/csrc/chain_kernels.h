@@ -242,16 +242,29 @@ __global__ void __launch_bounds__(kStartBlock) k_chain_start(SearchArgs a, SubTa
         row = ient + it.off;
         x = (int64_t)e_end - depth + 1;
         bool ngr = true;
+        // the text window before x is the same for every state of the row, and neighbouring
+        // states often share their start column: the last verdict is kept
+        uint32_t tw[8];
+        if (a.use_domination) load_window32(a.text, x, tw);
+        int64_t last_y = -1;
+        bool last_dom = false;
+        auto dom_at = [&](int64_t y) {
+            if (y != last_y) {
+                last_dom = dominated_tw(a, sub, tw, x, y);
+                last_y = y;
+            }
+            return last_dom;
+        };
         for (uint32_t k = 0; k < len; ++k) {
             const Entry e = row[k];
             bool aM = e.M > 0, aG = e.Ga > 0;
             if (a.use_domination) {
-                if (aM && dominated(a, sub, x, e.yM)) {
+                if (aM && dom_at(e.yM)) {
                     aM = false;
                     if (k < 32) killM |= 1u << k;
                     ++n_dom;
                 }
-                if (aG && dominated(a, sub, x, e.yGa)) {
+                if (aG && dom_at(e.yGa)) {
                     aG = false;
                     if (k < 32) killGa |= 1u << k;
                     ++n_dom;

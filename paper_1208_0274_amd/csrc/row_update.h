@@ -40,14 +40,16 @@ __device__ inline void load_window32(const uint8_t *arr, int64_t p, uint32_t w[8
 
 // Ungapped form: some suffix of T[x-k..x-1] against P[y-k..y-1] (k <= 32)
 // scores > 0.  sub is the substitution table (LDS) for matrix scoring.
-__device__ inline bool dominated(const SearchArgs &a, const int8_t *sub, int64_t x, int64_t y) {
+// tw: the text window T[x-32..x-1] (load_window32), shared by every state
+// tested at the same x.
+__device__ inline bool dominated_tw(const SearchArgs &a, const int8_t *sub, const uint32_t (&tw)[8], int64_t x,
+                                    int64_t y) {
     int64_t reach = a.dom_reach;
     if (x < reach) reach = x;
     const int64_t yl = y - (int64_t)seg_beg_of(a, (uint32_t)y);  // columns of y's query before y
     if (yl < reach) reach = yl;
     if (reach <= 0) return false;
-    uint32_t tw[8], qw[8];
-    load_window32(a.text, x, tw);
+    uint32_t qw[8];
     load_window32(a.query, y, qw);
     int32_t sum = 0;
     bool dom = false;
@@ -64,6 +66,12 @@ __device__ inline bool dominated(const SearchArgs &a, const int8_t *sub, int64_t
         }
     }
     return dom;
+}
+
+__device__ inline bool dominated(const SearchArgs &a, const int8_t *sub, int64_t x, int64_t y) {
+    uint32_t tw[8];
+    load_window32(a.text, x, tw);
+    return dominated_tw(a, sub, tw, x, y);
 }
 
 // Gapped form: the best local alignment score ending exactly at (x-1, y-1),
