@@ -32,10 +32,12 @@ hipError_t radix_sort_keys(uint64_t *keys, uint64_t *keys_alt, uint64_t n, int l
 // so that the sort reads total_bits bits only.
 hipError_t repack_hit_keys(uint64_t *keys, uint64_t n, int low_bits, int total_bits, hipStream_t s);
 // The same key with the score below it in one word when total_bits + sb <= 64:
-// ((query end << low_bits | text end) << sb) | score; the padding record is
-// 2^(total_bits + sb) - 1.  The sort then reads bits [sb, sb + total_bits).
-hipError_t pack_hit_records(uint64_t *keys, const uint32_t *scores, uint64_t n, int low_bits, int sb,
-                            int total_bits, hipStream_t s);
+// ((query end << low_bits | text end) << sb) | score, the padding record
+// 2^(total_bits + sb) - 1; then sorted by bits [sb, sb + total_bits) (the
+// packing kernel counts the first pass's digits).  Scratch as for
+// radix_sort_pairs; *result_in_alt says whether keys_alt holds the result.
+hipError_t pack_sort_hits(uint64_t *keys, const uint32_t *scores, uint64_t *keys_alt, uint64_t n, int low_bits,
+                          int sb, int total_bits, uint32_t *scratch, bool *result_in_alt, hipStream_t s);
 
 // Given hit records sorted by key, keep one record per key with the largest
 // score (Algorithm 1's "keep the larger score").  flags/pos hold n+1 words
@@ -44,7 +46,7 @@ hipError_t pack_hit_records(uint64_t *keys, const uint32_t *scores, uint64_t n, 
 hipError_t max_merge_sorted(const uint64_t *keys, const uint32_t *scores, uint64_t n, uint64_t *out_keys,
                             uint32_t *out_scores, uint32_t *flags, uint32_t *pos, uint32_t *tmp,
                             hipStream_t s, int low_bits = 0);
-// The same for records packed by pack_hit_records: tiles holds
+// The same for records packed by pack_sort_hits: tiles holds
 // merge_tile_count(n) + 1 words and receives the distinct count at index
 // merge_tile_count(n); tmp scan_scratch_words(merge_tile_count(n) + 1).
 hipError_t max_merge_packed(const uint64_t *recs, uint64_t n, int sb, int low_bits, uint64_t *out_keys,

@@ -1382,8 +1382,8 @@ static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64
         bool in_alt = false;
         const uint32_t *count_at = ws->pos + valid;  // where the merge leaves the distinct count
         if (packed) {
-            HIP_TRY(pack_hit_records(ws->hkeys, ws->hscores, emitted, tb, sb, bits, s));
-            HIP_TRY(radix_sort_keys(ws->hkeys, ws->hkeys_alt, emitted, sb, bits, ws->scratch, &in_alt, s));
+            HIP_TRY(pack_sort_hits(ws->hkeys, ws->hscores, ws->hkeys_alt, emitted, tb, sb, bits, ws->scratch,
+                                   &in_alt, s));
             const uint64_t *k = in_alt ? ws->hkeys_alt : ws->hkeys;
             HIP_TRY(max_merge_packed(k, valid, sb, tb, ws->res_keys, ws->res_scores, ws->pos, ws->scratch, s));
             count_at = ws->pos + merge_tile_count(valid);

@@ -205,13 +205,43 @@ __global__ void merge_write(const uint64_t *keys, const uint32_t *scores, uint64
 }
 
 // Hit records as one word: ((query end << low_bits | text end) << sb) | score,
-// the padding key going to `pad` (above every real record).
-__global__ void pack_records(uint64_t *keys, const uint32_t *scores, uint64_t n, int low_bits, int sb,
-                             uint64_t pad) {
-    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const uint64_t k = keys[i];
-    keys[i] = k == ~0ull ? pad : ((((k >> 32) << low_bits) | (k & 0xFFFFFFFFull)) << sb) | (uint64_t)scores[i];
+// the padding key going to `pad` (above every real record); the block also
+// counts the digits of the first radix pass (bits sb .. sb+10) of its tile,
+// so that pass needs no histogram pass of its own.
+__global__ void __launch_bounds__(kThreads) pack_records_hist(uint64_t *keys, const uint32_t *scores, uint64_t n,
+                                                              int low_bits, int sb, uint64_t pad, uint32_t *hist,
+                                                              uint32_t nblocks) {
+    __shared__ uint32_t cnt[kBins];
+    for (int b = threadIdx.x; b < kBins; b += kThreads) cnt[b] = 0;
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const uint64_t base = (uint64_t)blockIdx.x * kSortTile;
+    constexpr int kBatch = 16;
+    for (int r0 = 0; r0 < kSortItems; r0 += kBatch) {
+        uint64_t kk[kBatch];
+        uint32_t ss[kBatch];
+#pragma unroll
+        for (int j = 0; j < kBatch; ++j) {
+            const uint64_t i = base + (uint64_t)(r0 + j) * kThreads + threadIdx.x;
+            kk[j] = i < n ? keys[i] : 0ull;
+            ss[j] = i < n ? scores[i] : 0u;
+        }
+#pragma unroll
+        for (int j = 0; j < kBatch; ++j) {
+            const uint64_t i = base + (uint64_t)(r0 + j) * kThreads + threadIdx.x;
+            const bool valid = i < n;
+            const uint64_t k = kk[j];
+            const uint64_t rec =
+                k == ~0ull ? pad : ((((k >> 32) << low_bits) | (k & 0xFFFFFFFFull)) << sb) | (uint64_t)ss[j];
+            if (valid) keys[i] = rec;
+            const uint32_t d = (uint32_t)(rec >> sb) & (kBins - 1);
+            const uint64_t peers = digit_peers(d, valid);
+            if (valid && (peers & below) == 0) atomicAdd(&cnt[d], (uint32_t)__popcll(peers));
+        }
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < kBins; b += kThreads) hist[(uint64_t)b * nblocks + blockIdx.x] = cnt[b];
 }
 
 // Max-merge of packed records in two passes over tiles of kTile records
@@ -375,8 +405,9 @@ hipError_t radix_sort_pairs(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, 
     return hipSuccess;
 }
 
-hipError_t radix_sort_keys(uint64_t *keys, uint64_t *keys_alt, uint64_t n, int lo_bit, int bits, uint32_t *scratch,
-                           bool *result_in_alt, hipStream_t s) {
+// first_hist: the histogram of the first pass is already in the scratch.
+static hipError_t radix_sort_keys_impl(uint64_t *keys, uint64_t *keys_alt, uint64_t n, int lo_bit, int bits,
+                                       uint32_t *scratch, bool *result_in_alt, hipStream_t s, bool first_hist) {
     *result_in_alt = false;
     if (n <= 1 || bits <= 0) return hipSuccess;
     const uint32_t blocks = (uint32_t)ceil_div(n, kSortTile);
@@ -385,7 +416,7 @@ hipError_t radix_sort_keys(uint64_t *keys, uint64_t *keys_alt, uint64_t n, int l
     uint64_t *kin = keys, *kout = keys_alt;
     bool alt = false;
     for (int shift = lo_bit; shift < lo_bit + bits; shift += kDigit) {
-        radix_hist<<<blocks, kThreads, 0, s>>>(kin, n, shift, hist, blocks);
+        if (!(first_hist && shift == lo_bit)) radix_hist<<<blocks, kThreads, 0, s>>>(kin, n, shift, hist, blocks);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         e = scan_exclusive_u32(hist, hist, (uint64_t)kBins * blocks, tmp, s);
@@ -400,13 +431,22 @@ hipError_t radix_sort_keys(uint64_t *keys, uint64_t *keys_alt, uint64_t n, int l
     return hipSuccess;
 }
 
-hipError_t pack_hit_records(uint64_t *keys, const uint32_t *scores, uint64_t n, int low_bits, int sb,
-                            int total_bits, hipStream_t s) {
+hipError_t radix_sort_keys(uint64_t *keys, uint64_t *keys_alt, uint64_t n, int lo_bit, int bits, uint32_t *scratch,
+                           bool *result_in_alt, hipStream_t s) {
+    return radix_sort_keys_impl(keys, keys_alt, n, lo_bit, bits, scratch, result_in_alt, s, false);
+}
+
+hipError_t pack_sort_hits(uint64_t *keys, const uint32_t *scores, uint64_t *keys_alt, uint64_t n, int low_bits,
+                          int sb, int total_bits, uint32_t *scratch, bool *result_in_alt, hipStream_t s) {
+    *result_in_alt = false;
     if (n == 0) return hipSuccess;
     const int all = total_bits + sb;
     const uint64_t pad = all >= 64 ? ~0ull : ((1ull << all) - 1);
-    pack_records<<<(uint32_t)ceil_div(n, 256), 256, 0, s>>>(keys, scores, n, low_bits, sb, pad);
-    return hipGetLastError();
+    const uint32_t blocks = (uint32_t)ceil_div(n, kSortTile);
+    pack_records_hist<<<blocks, kThreads, 0, s>>>(keys, scores, n, low_bits, sb, pad, scratch, blocks);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return radix_sort_keys_impl(keys, keys_alt, n, sb, total_bits, scratch, result_in_alt, s, true);
 }
 
 hipError_t max_merge_packed(const uint64_t *recs, uint64_t n, int sb, int low_bits, uint64_t *out_keys,
