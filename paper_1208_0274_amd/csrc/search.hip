@@ -1220,11 +1220,11 @@ static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64
                                                         ws->hkeys, ws->hscores, caps, ws->d_cnt, gq.order, gq.twork,
                                                         tracing ? ws->wsrc : nullptr, ws->ready);
             HIP_TRY(hipGetLastError());
-            // At most two wave-walker blocks per CU run beside the lane walker: with more, walker
+            // At most two wave-walker waves per SIMD run beside the lane walker: with more, walker
             // blocks dispatched first could leave a CU no room for a lane-walker wave (whose
             // pushes they wait for).  The rest start on the lane walker's stream once it ends and
             // take items from the same queue.
-            const uint32_t live_during = std::min<uint32_t>(live_blocks, (uint32_t)cus * 2u);
+            const uint32_t live_during = std::min<uint32_t>(live_blocks, (uint32_t)cus * (8u / kWideWaves));
             const uint32_t live_after = live_blocks - live_during;
             auto wide_live = [&](uint32_t blocks, hipStream_t st2) {
                 if (wide_fast)
