@@ -215,12 +215,20 @@ __device__ inline bool wave_queue_alloc(Counters *cnt, unsigned long long *nodes
 // ---------------------------------------------------------------------------
 constexpr int kStartBlock = 256;
 
+// Launched right behind the level kernels that make the chains, with a grid
+// for the most chains the level can make: the count is read here, and after
+// an overflow of the level (its outputs are incomplete and the host runs the
+// level and this kernel again) nothing is done.
 __global__ void __launch_bounds__(kStartBlock) k_chain_start(SearchArgs a, SubTable subt, const Node *items,
-                                                             uint32_t nitems, const Entry *ient, ChainQueues q,
-                                                             Caps caps, Counters *cnt) {
+                                                             const Entry *ient, ChainQueues q, Caps caps,
+                                                             Counters *cnt) {
     __shared__ int8_t sub[20 * 20];
     __shared__ BlockReserveLds<5, kStartBlock / 64> s_res5;
     __shared__ BlockReserveLds<11, kStartBlock / 64> s_res11;
+    if (cnt->overflow) return;  // the whole grid: the level is run again
+    const uint64_t made = cnt->cnodes;
+    const uint32_t nitems = (uint32_t)(made < caps.cnodes ? made : caps.cnodes);
+    if ((uint64_t)blockIdx.x * kStartBlock >= nitems) return;  // the whole block
     for (int i = threadIdx.x; i < a.sigma * a.sigma; i += blockDim.x) sub[i] = subt.s[i];
     __syncthreads();
     const int lane = threadIdx.x & 63;

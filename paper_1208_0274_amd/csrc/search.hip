@@ -447,6 +447,7 @@ struct alae_workspace {
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     hipEvent_t evk0 = nullptr, evk1 = nullptr;  // around each expansion launch
     hipEvent_t evkm = nullptr;                  // after the lane kernel of a level
+    hipEvent_t evks = nullptr;                  // after all level kernels, before the chain start
 };
 
 namespace alae {
@@ -517,6 +518,7 @@ static void ws_release(alae_workspace *ws) {
     if (ws->evk0) hipEventDestroy(ws->evk0);
     if (ws->evk1) hipEventDestroy(ws->evk1);
     if (ws->evkm) hipEventDestroy(ws->evkm);
+    if (ws->evks) hipEventDestroy(ws->evks);
 }
 
 struct Scheme {
@@ -1049,7 +1051,25 @@ static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64
                 k_expand_level_wide<<<blocks, 64, 0, s>>>(a, ws->lwide[cur], (uint32_t)nlw, ws->ents[cur], d1, o,
                                                           caps, ws->d_cnt, ws->stage);
             }
-            if ((st = timed(expand_ms)) != ALAE_OK) return st;
+            // the chains this level makes, right behind it (one host round trip a level)
+            HIP_TRY(hipEventRecord(ws->evks, s));
+            {
+                const uint64_t most = std::min<uint64_t>((uint64_t)sigma * (nn + nlw), caps.cnodes);
+                if (most > 0) {
+                    ChainQueues q{ws->gnodes, ws->gents, ws->wnodes, ws->wents, ws->hkeys, ws->hscores};
+                    k_chain_start<<<(uint32_t)((most + kStartBlock - 1) / kStartBlock), kStartBlock, 0, s>>>(
+                        a, sub, ws->cnodes, ws->cents, q, caps, ws->d_cnt);
+                }
+            }
+            double unit_ms = 0.0;
+            if ((st = timed(unit_ms)) != ALAE_OK) return st;
+            {
+                float ems = 0.f, sms = 0.f;
+                HIP_TRY(hipEventElapsedTime(&ems, ws->evk0, ws->evks));
+                HIP_TRY(hipEventElapsedTime(&sms, ws->evks, ws->evk1));
+                expand_ms += ems;
+                start_ms += sms;
+            }
             ++level_launches;
             if (nn > 0) {  // the node and child phases alone (the trie-expansion kernels)
                 float lms = 0.f;
@@ -1064,25 +1084,6 @@ static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64
         }
         const uint64_t nc = ws->h_cnt->cnodes;
         const double t1 = expand_ms;
-        // chains created by this level
-        if (nc > 0) {
-            const Counters before2 = *ws->h_cnt;
-            for (;;) {
-                Counters z = before2;
-                z.overflow = 0;
-                HIP_TRY(hipMemcpyAsync(ws->d_cnt, &z, sizeof(Counters), hipMemcpyHostToDevice, s));
-                set_caps(nxt);
-                ChainQueues q{ws->gnodes, ws->gents, ws->wnodes, ws->wents, ws->hkeys, ws->hscores};
-                HIP_TRY(hipEventRecord(ws->evk0, s));
-                k_chain_start<<<(uint32_t)((nc + kStartBlock - 1) / kStartBlock), kStartBlock, 0, s>>>(a, sub, ws->cnodes, (uint32_t)nc,
-                                                                           ws->cents, q, caps, ws->d_cnt);
-                if ((st = timed(start_ms)) != ALAE_OK) return st;
-                const Counters &c = *ws->h_cnt;
-                if (!c.overflow) break;
-                ++retries;
-                if ((st = grow_overflowed(c, before2, nxt)) != ALAE_OK) return st;
-            }
-        }
         if (trace)
             fprintf(stderr,
                     "[alae] depth %d: %llu+%llu nodes -> %llu+%llu nodes, %llu entries, %llu chains "
@@ -1495,6 +1496,7 @@ alae_status alae_workspace_create(const alae_index *index, alae_workspace **out)
     HIP_TRY(hipEventCreate(&ws->evk0));
     HIP_TRY(hipEventCreate(&ws->evk1));
     HIP_TRY(hipEventCreate(&ws->evkm));
+    HIP_TRY(hipEventCreate(&ws->evks));
     HIP_TRY(hipEventCreateWithFlags(&ws->ev_fork, hipEventDisableTiming));
     HIP_TRY(hipEventCreateWithFlags(&ws->ev_join, hipEventDisableTiming));
     HIP_TRY(hipStreamCreateWithFlags(&ws->s2, hipStreamNonBlocking));
