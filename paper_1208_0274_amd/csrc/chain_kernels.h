@@ -231,7 +231,6 @@ __global__ void __launch_bounds__(kStartBlock) k_chain_start(SearchArgs a, SubTa
     if ((uint64_t)blockIdx.x * kStartBlock >= nitems) return;  // the whole block
     for (int i = threadIdx.x; i < a.sigma * a.sigma; i += blockDim.x) sub[i] = subt.s[i];
     __syncthreads();
-    const int lane = threadIdx.x & 63;
     const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
     const int32_t open = a.sg + a.ss;
     unsigned long long n_dom = 0, n_steps = 0, n_entries = 0, n_hits = 0, n_wide = 0;
