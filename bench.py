@@ -1,6 +1,6 @@
 """Benchmark of the exact local-alignment search on one MI355X.
 
-    python bench.py [--steps K] [--warmup W] [--workload c2|c1|c3] [--no-cpu]
+    python bench.py [--steps K] [--warmup W] [--workload dna|small|protein] [--no-cpu]
 
 A step is one complete search of the workload's query against the resident
 index: seeding, every trie level, hit emission, sort and max-merge, with the
@@ -31,15 +31,15 @@ def log(msg):
 def workload(name: str):
     from paper_1208_0274_amd import synth
 
-    if name == "c2":
-        w = synth.config2()
+    if name == "dna":
+        w = synth.dna_long_query()
         desc = ("DNA long query: text 1e8 i.i.d. ACGT + 1,000 planted mutated query segments "
                 "(200-2,000, 15% subs, 2% indels); query 1e5; <1,-3,-5,-2>; H=30")
-    elif name == "c1":
-        w = synth.config1()
+    elif name == "small":
+        w = synth.small_dna()
         desc = "plain method, single query: text 1e5 i.i.d. ACGT; query 1e3; <1,-3,-5,-2>; H=18"
-    elif name == "c3":
-        w = synth.config3()
+    elif name == "protein":
+        w = synth.protein_standin()
         desc = ("protein stand-in: text 5e7 uniform residues + 500 planted segments (50-500, 30% subs, "
                 "3% indels); query 5,000; <1,-3,-11,-1>; H=45")
     else:
@@ -162,7 +162,7 @@ def batched_vs_single(alae, k=64, n=100_000_000):
 
     from paper_1208_0274_amd import synth
 
-    w = synth.config4(n=n, k=k)
+    w = synth.batched_dna(n=n, k=k)
     qs = w["queries"]
     t0 = time.perf_counter()
     idx = alae.Index.build(w["text"], "dna")
@@ -242,14 +242,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--workload", default="dna")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the learned-scheduling and batching legs")
     ap.add_argument("--cpu-seconds", type=float, default=30.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the search has no multi-GPU path in this build "
-              "(sharding by text range is described in DESIGN.md)", file=sys.stderr)
+              "(it would shard by text range, one index part per GPU)", file=sys.stderr)
         sys.exit(2)
 
     import torch

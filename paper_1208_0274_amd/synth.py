@@ -92,7 +92,7 @@ def _dna_scoring():
     return dict(sa=1, sb=-3, sg=-5, ss=-2, matrix=None)
 
 
-def config1(planted: bool = False, H: int = 18):
+def small_dna(planted: bool = False, H: int = 18):
     """Plain method, single query: text 1e5 i.i.d. ACGT, query 1e3, <1,-3,-5,-2>, H=18.
 
     ``planted=True`` adds 10 query segments of 50-200 characters mutated at
@@ -108,11 +108,11 @@ def config1(planted: bool = False, H: int = 18):
             y = int(r.integers(0, query.shape[0] - L + 1))
             srcs.append(query[y:y + L])
         plants = plant_segments(r, text, srcs, 4, 0.15, 0.02)
-    return dict(name="C1" + ("-planted" if planted else ""), alphabet="dna", sigma=4, text=text,
+    return dict(name="small-dna" + ("-planted" if planted else ""), alphabet="dna", sigma=4, text=text,
                 queries=[query], H=H, plants=plants, **_dna_scoring())
 
 
-def config2(n: int = 100_000_000, m: int = 100_000, n_plants: int = 1000, H: int = 30):
+def dna_long_query(n: int = 100_000_000, m: int = 100_000, n_plants: int = 1000, H: int = 30):
     """DNA long query: text 1e8 i.i.d. ACGT with 1,000 planted mutated query
     segments (lengths 200-2,000, 15% substitutions, 2% indels); query 1e5;
     <1,-3,-5,-2>; H=30."""
@@ -126,11 +126,11 @@ def config2(n: int = 100_000_000, m: int = 100_000, n_plants: int = 1000, H: int
         y = int(r.integers(0, m - L + 1))
         srcs.append(query[y:y + L])
     plants = plant_segments(r, text, srcs, 4, 0.15, 0.02)
-    return dict(name="C2", alphabet="dna", sigma=4, text=text, queries=[query], H=H, plants=plants,
+    return dict(name="dna-long-query", alphabet="dna", sigma=4, text=text, queries=[query], H=H, plants=plants,
                 **_dna_scoring())
 
 
-def config3(n: int = 50_000_000, m: int = 5_000, n_plants: int = 500, H: int = 45, p_sub: float = 0.10):
+def protein_standin(n: int = 50_000_000, m: int = 5_000, n_plants: int = 500, H: int = 45, p_sub: float = 0.10):
     """Protein: text 5e7 residues with 500 planted mutated query segments
     (lengths 50-500, 3% indels); query 5,000 residues.
 
@@ -148,7 +148,7 @@ def config3(n: int = 50_000_000, m: int = 5_000, n_plants: int = 500, H: int = 4
         y = int(r.integers(0, m - L + 1))
         srcs.append(query[y:y + L])
     plants = plant_segments(r, text, srcs, 20, p_sub, 0.03)
-    return dict(name="C3", alphabet="protein", sigma=20, text=text, queries=[query], H=H, plants=plants,
+    return dict(name="protein-standin", alphabet="protein", sigma=20, text=text, queries=[query], H=H, plants=plants,
                 sa=1, sb=-3, sg=-11, ss=-1, matrix=None)
 
 
@@ -156,7 +156,7 @@ def loguniform_lengths(rng: np.random.Generator, k: int, lo: int, hi: int) -> np
     return np.round(np.exp(rng.uniform(np.log(lo), np.log(hi), size=k))).astype(np.int64)
 
 
-def config4(n: int = 1_000_000_000, k: int = 256, copies: int = 20, H: int = 30,
+def batched_dna(n: int = 1_000_000_000, k: int = 256, copies: int = 20, H: int = 30,
             m_lo: int = 500, m_hi: int = 50_000):
     """Batched: k DNA queries with log-uniform lengths in [500, 50000], each with
     `copies` planted mutated segments (lengths 200-2,000, 15%/2%) in an i.i.d.
@@ -177,7 +177,7 @@ def config4(n: int = 1_000_000_000, k: int = 256, copies: int = 20, H: int = 30,
             owners.append(qi)
     plants = plant_segments(r, text, srcs, 4, 0.15, 0.02)
     plants = [(st, ln, owners[idx]) for (st, ln, idx) in plants]
-    return dict(name="C4", alphabet="dna", sigma=4, text=text, queries=queries, H=H, plants=plants,
+    return dict(name="batched-dna", alphabet="dna", sigma=4, text=text, queries=queries, H=H, plants=plants,
                 **_dna_scoring())
 
 

@@ -1,11 +1,11 @@
 """Parity at the full workload sizes, in the launch configuration bench.py times
 (device-resident query and result, one workspace).
 
-Config 2 (text 1e8, query 1e5): the hits whose text end falls in a window are
+DNA long query (text 1e8, query 1e5): the hits whose text end falls in a window are
 exactly the oracle's hits on T[window start - L_max .. window end] (Theorem 1
 bounds the text span of any alignment scoring >= H), so planted-copy windows
 and random background windows are checked exactly, many in parallel.
-Config 3 (protein stand-in, text 5e7, query 5e3) is checked in full.
+The protein stand-in (text 5e7, query 5e3) is checked in full.
 """
 import concurrent.futures as cf
 import os
@@ -46,11 +46,11 @@ def check_global_properties(j, t, s, w):
     assert np.all(np.diff(key) > 0)
 
 
-def test_config2_windows():
-    w = synth.config2()
+def test_dna_long_query_windows():
+    w = synth.dna_long_query()
     T, P, H = w["text"], w["queries"][0], w["H"]
     j, t, s, st = device_search(w)
-    print(f"C2: {j.shape[0]} hits, {st.entries} entries, {st.device_ms:.1f} ms", flush=True)
+    print(f"DNA 1e8 x 1e5: {j.shape[0]} hits, {st.entries} entries, {st.device_ms:.1f} ms", flush=True)
     check_global_properties(j, t, s, w)
     sub = oracle.scoring_table(4, 1, -3)
     lmax = oracle.lmax(P.shape[0], 1, w["sg"], w["ss"], H)
@@ -81,15 +81,15 @@ def test_config2_windows():
         np.testing.assert_array_equal(gt[order], et)
         np.testing.assert_array_equal(gs[order], es)
         checked += ej.shape[0]
-    print(f"C2 windows: {len(windows)} windows, {checked} hits checked exactly", flush=True)
+    print(f"DNA 1e8 x 1e5 windows: {len(windows)} windows, {checked} hits checked exactly", flush=True)
     assert checked > 0
 
 
-def test_config3_full():
-    w = synth.config3()
+def test_protein_standin_full():
+    w = synth.protein_standin()
     T, P, H = w["text"], w["queries"][0], w["H"]
     j, t, s, st = device_search(w)
-    print(f"C3: {j.shape[0]} hits, {st.entries} entries, {st.device_ms:.1f} ms", flush=True)
+    print(f"protein 5e7 x 5e3: {j.shape[0]} hits, {st.entries} entries, {st.device_ms:.1f} ms", flush=True)
     check_global_properties(j, t, s, w)
     ej, et, es = oracle.sw_hits(T, P, oracle.scoring_table(20, 1, -3), w["sg"], w["ss"], H,
                                 threads=min(64, os.cpu_count() or 1))

@@ -164,12 +164,12 @@ def test_forced_capacity_retries():
     assert_same(got, exp)
 
 
-def test_config1_and_planted():
-    """Config 1 (text 1e5, query 1e3, <1,-3,-5,-2>, H=18) and its planted variant at lower H."""
+def test_small_dna_and_planted():
+    """The small DNA workload (text 1e5, query 1e3, <1,-3,-5,-2>, H=18) and its planted variant at lower H."""
     for planted, H in ((False, 18), (True, 18), (True, 12), (True, 10), (True, 8)):
-        w = synth.config1(planted=planted, H=H)
+        w = synth.small_dna(planted=planted, H=H)
         got, exp, st = run_pair(w["text"], w["queries"][0], (1, -3, -5, -2), H)
-        print(f"C1 planted={planted} H={H} hits={exp[0].shape[0]} entries={st.entries}", flush=True)
+        print(f"small DNA planted={planted} H={H} hits={exp[0].shape[0]} entries={st.entries}", flush=True)
         assert_same(got, exp)
 
 

@@ -143,8 +143,8 @@ def test_index_errors():
 
 def test_generator_shapes():
     """Seeded generators: determinism and the planted-segment bookkeeping."""
-    a = synth.config1(planted=True)
-    b = synth.config1(planted=True)
+    a = synth.small_dna(planted=True)
+    b = synth.small_dna(planted=True)
     np.testing.assert_array_equal(a["text"], b["text"])
     assert len(a["plants"]) == 10 and a["text"].shape[0] == 100_000
     ends = sorted((st, st + ln) for st, ln, _ in a["plants"])
