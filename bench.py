@@ -248,7 +248,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=30.0)
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: the search has no multi-GPU path in this build "
+        print("bench.py measures one GPU: the search runs on a single GPU "
               "(it would shard by text range, one index part per GPU)", file=sys.stderr)
         sys.exit(2)
 
