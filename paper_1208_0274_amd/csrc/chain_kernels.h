@@ -219,7 +219,10 @@ constexpr int kStartBlock = 256;
 // for the most chains the level can make: the count is read here, and after
 // an overflow of the level (its outputs are incomplete and the host runs the
 // level and this kernel again) nothing is done.
-__global__ void __launch_bounds__(kStartBlock) k_chain_start(SearchArgs a, SubTable subt, const Node *items,
+// Four waves per SIMD (128 VGPRs, a few spilled): the random reads of the
+// suffix array and the text need the extra waves in flight more than the
+// spilled registers cost; a fifth wave spills too much.
+__global__ void __launch_bounds__(kStartBlock, 4) k_chain_start(SearchArgs a, SubTable subt, const Node *items,
                                                              const Entry *ient, ChainQueues q, Caps caps,
                                                              Counters *cnt) {
     __shared__ int8_t sub[20 * 20];
