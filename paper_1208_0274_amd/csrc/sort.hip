@@ -299,8 +299,7 @@ __global__ void __launch_bounds__(kThreads) merge_count(const uint64_t *recs, ui
 __global__ void __launch_bounds__(kThreads) merge_emit(const uint64_t *recs, uint64_t n, int sb, int low_bits,
                                                        const uint32_t *tile_prefix, uint64_t *out_keys,
                                                        uint32_t *out_scores) {
-    __shared__ uint64_t s_rec[kTile];
-    __shared__ uint64_t s_key[kTile];
+    __shared__ uint64_t s_rec[kTile];  // the tile's records, then its output keys
     __shared__ uint32_t s_score[kTile];
     const uint64_t tile = (uint64_t)blockIdx.x * kTile;
     load_tile(recs, n, tile, s_rec);
@@ -310,8 +309,12 @@ __global__ void __launch_bounds__(kThreads) merge_emit(const uint64_t *recs, uin
     uint32_t pos = block_exclusive_scan(c, &total);
     const uint64_t smask = (1ull << sb) - 1;
     const int k0 = threadIdx.x * kItems;
+    uint64_t okey[kItems];
+    uint32_t oscore[kItems];
 #pragma unroll
     for (int k = 0; k < kItems; ++k) {
+        okey[k] = 0;
+        oscore[k] = 0;
         if (!st[k]) continue;
         const uint64_t key = s_rec[k0 + k] >> sb;
         uint64_t best = s_rec[k0 + k] & smask;
@@ -325,14 +328,21 @@ __global__ void __launch_bounds__(kThreads) merge_emit(const uint64_t *recs, uin
                 const uint64_t s = recs[g] & smask;
                 best = s > best ? s : best;
             }
-        s_key[pos] = ((key >> low_bits) << 32) | (key & ((1ull << low_bits) - 1));
-        s_score[pos] = (uint32_t)best;
+        okey[k] = ((key >> low_bits) << 32) | (key & ((1ull << low_bits) - 1));
+        oscore[k] = (uint32_t)best;
+    }
+    __syncthreads();  // every group has been read: the record tile takes the outputs
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+        if (!st[k]) continue;
+        s_rec[pos] = okey[k];
+        s_score[pos] = oscore[k];
         ++pos;
     }
     __syncthreads();
     const uint64_t out = tile_prefix[blockIdx.x];
     for (uint32_t k = threadIdx.x; k < total; k += kThreads) {
-        out_keys[out + k] = s_key[k];
+        out_keys[out + k] = s_rec[k];
         out_scores[out + k] = s_score[k];
     }
 }
