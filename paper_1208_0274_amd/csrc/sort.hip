@@ -77,12 +77,18 @@ __global__ void __launch_bounds__(kThreads) scan_add(uint32_t *out, uint64_t n, 
 }
 
 // LSD radix sort with 11-bit digits (2048 bins): a block ranks a tile of
-// kSortTile keys; ranks within a wave come from ballots, and only the bins a
+// 256 x ITEMS keys; ranks within a wave come from ballots, and only the bins a
 // round touches are updated (by one leader lane per bin and wave).
 constexpr int kDigit = 11;
 constexpr int kBins = 1 << kDigit;
+// Keys a thread takes per pass: 64 (tiles of 16384 keys), or 256 (tiles of
+// 65536) for sorts of at least kBigSort keys, where a larger tile means a
+// quarter of the per-tile histogram entries to write, scan and read back and
+// still two or more blocks per CU.
 constexpr int kSortItems = 64;
-constexpr int kSortTile = kThreads * kSortItems;
+constexpr int kSortItemsBig = 256;
+constexpr uint64_t kBigSort = 1ull << 25;
+constexpr int kSortTile = kThreads * kSortItems;  // the smallest tile (sizes the scratch)
 
 // Lanes of a wave holding the same digit: the peers mask (ballot per digit
 // bit) and this lane's rank among them.
@@ -99,6 +105,7 @@ __device__ inline uint64_t digit_peers(uint32_t d, bool valid) {
 
 // Per-block digit counts; one LDS atomic per distinct digit of a wave's keys
 // (hit keys come in runs that share digits).
+template <int ITEMS>
 __global__ void __launch_bounds__(kThreads) radix_hist(const uint64_t *keys, uint64_t n, int shift, uint32_t *hist,
                                                        uint32_t nblocks) {
     __shared__ uint32_t cnt[kBins];
@@ -106,9 +113,9 @@ __global__ void __launch_bounds__(kThreads) radix_hist(const uint64_t *keys, uin
     __syncthreads();
     const int lane = threadIdx.x & 63;
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    const uint64_t base = (uint64_t)blockIdx.x * kSortTile;
+    const uint64_t base = (uint64_t)blockIdx.x * (kThreads * ITEMS);
     constexpr int kBatch = 16;  // loads issued together
-    for (int r0 = 0; r0 < kSortItems; r0 += kBatch) {
+    for (int r0 = 0; r0 < ITEMS; r0 += kBatch) {
         uint64_t kk[kBatch];
 #pragma unroll
         for (int j = 0; j < kBatch; ++j) {
@@ -131,7 +138,7 @@ __global__ void __launch_bounds__(kThreads) radix_hist(const uint64_t *keys, uin
 // Stable scatter: elements of a tile are ranked in index order (round, wave,
 // lane); offs holds the exclusive scan of the digit-major histogram.  VALS:
 // 32-bit values move with the keys.
-template <bool VALS>
+template <bool VALS, int ITEMS>
 __global__ void __launch_bounds__(kThreads) radix_scatter(const uint64_t *kin, const uint32_t *vin, uint64_t *kout,
                                                           uint32_t *vout, uint64_t n, int shift,
                                                           const uint32_t *offs, uint32_t nblocks) {
@@ -146,16 +153,16 @@ __global__ void __launch_bounds__(kThreads) radix_scatter(const uint64_t *kin, c
         for (int w = 0; w < kWaves; ++w) wcnt[w][b] = 0;
     }
     __syncthreads();
-    const uint64_t base = (uint64_t)blockIdx.x * kSortTile;
+    const uint64_t base = (uint64_t)blockIdx.x * (kThreads * ITEMS);
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     uint64_t k_next = base + tid < n ? kin[base + tid] : 0ull;  // the next round's element, loaded early
     uint32_t v_next = (VALS && base + tid < n) ? vin[base + tid] : 0u;
-    for (int r = 0; r < kSortItems; ++r) {
+    for (int r = 0; r < ITEMS; ++r) {
         const uint64_t i = base + (uint64_t)r * kThreads + tid;
         const bool valid = i < n;
         const uint64_t k = k_next;
         const uint32_t v = v_next;
-        if (r + 1 < kSortItems) {
+        if (r + 1 < ITEMS) {
             const uint64_t i2 = i + kThreads;
             k_next = i2 < n ? kin[i2] : 0ull;
             if (VALS) v_next = i2 < n ? vin[i2] : 0u;
@@ -208,6 +215,7 @@ __global__ void merge_write(const uint64_t *keys, const uint32_t *scores, uint64
 // the padding key going to `pad` (above every real record); the block also
 // counts the digits of the first radix pass (bits sb .. sb+10) of its tile,
 // so that pass needs no histogram pass of its own.
+template <int ITEMS>
 __global__ void __launch_bounds__(kThreads) pack_records_hist(uint64_t *keys, const uint32_t *scores, uint64_t n,
                                                               int low_bits, int sb, uint64_t pad, uint32_t *hist,
                                                               uint32_t nblocks) {
@@ -216,9 +224,9 @@ __global__ void __launch_bounds__(kThreads) pack_records_hist(uint64_t *keys, co
     __syncthreads();
     const int lane = threadIdx.x & 63;
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    const uint64_t base = (uint64_t)blockIdx.x * kSortTile;
+    const uint64_t base = (uint64_t)blockIdx.x * (kThreads * ITEMS);
     constexpr int kBatch = 16;
-    for (int r0 = 0; r0 < kSortItems; r0 += kBatch) {
+    for (int r0 = 0; r0 < ITEMS; r0 += kBatch) {
         uint64_t kk[kBatch];
         uint32_t ss[kBatch];
 #pragma unroll
@@ -388,23 +396,36 @@ uint64_t radix_scratch_words(uint64_t n) {
     return hist + scan_scratch_words(hist);
 }
 
+static bool big_sort(uint64_t n) { return n >= kBigSort; }
+static uint32_t sort_blocks(uint64_t n) {
+    return (uint32_t)ceil_div(n, (uint64_t)kThreads * (big_sort(n) ? kSortItemsBig : kSortItems));
+}
+
 hipError_t radix_sort_pairs(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, uint32_t *vals_alt, uint64_t n,
                             int bits, uint32_t *scratch, bool *result_in_alt, hipStream_t s) {
     *result_in_alt = false;
     if (n <= 1 || bits <= 0) return hipSuccess;
-    const uint32_t blocks = (uint32_t)ceil_div(n, kSortTile);
+    const bool big = big_sort(n);
+    const uint32_t blocks = sort_blocks(n);
     uint32_t *hist = scratch;
     uint32_t *tmp = scratch + (uint64_t)kBins * blocks;
     uint64_t *kin = keys, *kout = keys_alt;
     uint32_t *vin = vals, *vout = vals_alt;
     bool alt = false;
     for (int shift = 0; shift < bits; shift += kDigit) {
-        radix_hist<<<blocks, kThreads, 0, s>>>(kin, n, shift, hist, blocks);
+        if (big)
+            radix_hist<kSortItemsBig><<<blocks, kThreads, 0, s>>>(kin, n, shift, hist, blocks);
+        else
+            radix_hist<kSortItems><<<blocks, kThreads, 0, s>>>(kin, n, shift, hist, blocks);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         e = scan_exclusive_u32(hist, hist, (uint64_t)kBins * blocks, tmp, s);
         if (e != hipSuccess) return e;
-        radix_scatter<true><<<blocks, kThreads, 0, s>>>(kin, vin, kout, vout, n, shift, hist, blocks);
+        if (big)
+            radix_scatter<true, kSortItemsBig><<<blocks, kThreads, 0, s>>>(kin, vin, kout, vout, n, shift, hist,
+                                                                           blocks);
+        else
+            radix_scatter<true, kSortItems><<<blocks, kThreads, 0, s>>>(kin, vin, kout, vout, n, shift, hist, blocks);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
         std::swap(kin, kout);
@@ -420,18 +441,29 @@ static hipError_t radix_sort_keys_impl(uint64_t *keys, uint64_t *keys_alt, uint6
                                        uint32_t *scratch, bool *result_in_alt, hipStream_t s, bool first_hist) {
     *result_in_alt = false;
     if (n <= 1 || bits <= 0) return hipSuccess;
-    const uint32_t blocks = (uint32_t)ceil_div(n, kSortTile);
+    const bool big = big_sort(n);
+    const uint32_t blocks = sort_blocks(n);
     uint32_t *hist = scratch;
     uint32_t *tmp = scratch + (uint64_t)kBins * blocks;
     uint64_t *kin = keys, *kout = keys_alt;
     bool alt = false;
     for (int shift = lo_bit; shift < lo_bit + bits; shift += kDigit) {
-        if (!(first_hist && shift == lo_bit)) radix_hist<<<blocks, kThreads, 0, s>>>(kin, n, shift, hist, blocks);
+        if (!(first_hist && shift == lo_bit)) {
+            if (big)
+                radix_hist<kSortItemsBig><<<blocks, kThreads, 0, s>>>(kin, n, shift, hist, blocks);
+            else
+                radix_hist<kSortItems><<<blocks, kThreads, 0, s>>>(kin, n, shift, hist, blocks);
+        }
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         e = scan_exclusive_u32(hist, hist, (uint64_t)kBins * blocks, tmp, s);
         if (e != hipSuccess) return e;
-        radix_scatter<false><<<blocks, kThreads, 0, s>>>(kin, nullptr, kout, nullptr, n, shift, hist, blocks);
+        if (big)
+            radix_scatter<false, kSortItemsBig><<<blocks, kThreads, 0, s>>>(kin, nullptr, kout, nullptr, n, shift,
+                                                                            hist, blocks);
+        else
+            radix_scatter<false, kSortItems><<<blocks, kThreads, 0, s>>>(kin, nullptr, kout, nullptr, n, shift, hist,
+                                                                         blocks);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
         std::swap(kin, kout);
@@ -452,8 +484,13 @@ hipError_t pack_sort_hits(uint64_t *keys, const uint32_t *scores, uint64_t *keys
     if (n == 0) return hipSuccess;
     const int all = total_bits + sb;
     const uint64_t pad = all >= 64 ? ~0ull : ((1ull << all) - 1);
-    const uint32_t blocks = (uint32_t)ceil_div(n, kSortTile);
-    pack_records_hist<<<blocks, kThreads, 0, s>>>(keys, scores, n, low_bits, sb, pad, scratch, blocks);
+    const uint32_t blocks = sort_blocks(n);  // the tiles of radix_sort_keys_impl's first pass
+    if (big_sort(n))
+        pack_records_hist<kSortItemsBig><<<blocks, kThreads, 0, s>>>(keys, scores, n, low_bits, sb, pad, scratch,
+                                                                      blocks);
+    else
+        pack_records_hist<kSortItems><<<blocks, kThreads, 0, s>>>(keys, scores, n, low_bits, sb, pad, scratch,
+                                                                   blocks);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return radix_sort_keys_impl(keys, keys_alt, n, sb, total_bits, scratch, result_in_alt, s, true);
