@@ -103,10 +103,9 @@ __device__ inline uint64_t digit_peers(uint32_t d, bool valid) {
     return peers;
 }
 
-// Per-block digit counts, one LDS atomic per key.  These passes see keys
-// already ordered by the lower digits, where a wave's digits rarely repeat;
-// grouping equal digits with ballots first (as the packing pass does for the
-// raw hit order, where they repeat) was slower here.
+// Per-block digit counts, one LDS atomic per key (grouping a wave's equal
+// digits with ballots first was slower: the ballots form a chain of dependent
+// instructions per key, while same-address LDS atomics are rare enough).
 template <int ITEMS>
 __global__ void __launch_bounds__(kThreads) radix_hist(const uint64_t *keys, uint64_t n, int shift, uint32_t *hist,
                                                        uint32_t nblocks) {
@@ -221,8 +220,6 @@ __global__ void __launch_bounds__(kThreads) pack_records_hist(uint64_t *keys, co
     __shared__ uint32_t cnt[kBins];
     for (int b = threadIdx.x; b < kBins; b += kThreads) cnt[b] = 0;
     __syncthreads();
-    const int lane = threadIdx.x & 63;
-    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     const uint64_t base = (uint64_t)blockIdx.x * (kThreads * ITEMS);
     constexpr int kBatch = 16;
     for (int r0 = 0; r0 < ITEMS; r0 += kBatch) {
@@ -243,8 +240,7 @@ __global__ void __launch_bounds__(kThreads) pack_records_hist(uint64_t *keys, co
                 k == ~0ull ? pad : ((((k >> 32) << low_bits) | (k & 0xFFFFFFFFull)) << sb) | (uint64_t)ss[j];
             if (valid) keys[i] = rec;
             const uint32_t d = (uint32_t)(rec >> sb) & (kBins - 1);
-            const uint64_t peers = digit_peers(d, valid);
-            if (valid && (peers & below) == 0) atomicAdd(&cnt[d], (uint32_t)__popcll(peers));
+            if (valid) atomicAdd(&cnt[d], 1u);
         }
     }
     __syncthreads();
