@@ -148,7 +148,7 @@ def _list_schedule(work, workers):
 
 def test_learned_order_gain():
     """What the trained network gains over the method without it (queue order),
-    judged against measured work: trained on the traced work of half of the
+    evaluated against measured work: trained on the traced work of half of the
     lane-queue items, it ranks the other half; ordering that half by the
     prediction is scored by the share of the measured work its predicted-heaviest
     tenth holds, and by the makespan of list scheduling that half's measured work
