@@ -82,9 +82,9 @@ __global__ void __launch_bounds__(kThreads) scan_add(uint32_t *out, uint64_t n, 
 constexpr int kDigit = 11;
 constexpr int kBins = 1 << kDigit;
 // Keys a thread takes per pass: 64 (tiles of 16384 keys), or 256 (tiles of
-// 65536) for sorts of at least kBigSort keys, where a larger tile means a
-// quarter of the per-tile histogram entries to write, scan and read back and
-// still two or more blocks per CU.
+// 65536) for key-only sorts (packed hit records) of at least kBigSort keys,
+// where a larger tile means a quarter of the per-tile histogram entries to
+// write, scan and read back and still two or more blocks per CU.
 constexpr int kSortItems = 64;
 constexpr int kSortItemsBig = 256;
 constexpr uint64_t kBigSort = 1ull << 25;
@@ -396,31 +396,25 @@ static uint32_t sort_blocks(uint64_t n) {
     return (uint32_t)ceil_div(n, (uint64_t)kThreads * (big_sort(n) ? kSortItemsBig : kSortItems));
 }
 
+// Key-value sorts (query seeds, and hits that do not fit one word) keep the
+// 64-key tiles at every size.
 hipError_t radix_sort_pairs(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, uint32_t *vals_alt, uint64_t n,
                             int bits, uint32_t *scratch, bool *result_in_alt, hipStream_t s) {
     *result_in_alt = false;
     if (n <= 1 || bits <= 0) return hipSuccess;
-    const bool big = big_sort(n);
-    const uint32_t blocks = sort_blocks(n);
+    const uint32_t blocks = (uint32_t)ceil_div(n, kSortTile);
     uint32_t *hist = scratch;
     uint32_t *tmp = scratch + (uint64_t)kBins * blocks;
     uint64_t *kin = keys, *kout = keys_alt;
     uint32_t *vin = vals, *vout = vals_alt;
     bool alt = false;
     for (int shift = 0; shift < bits; shift += kDigit) {
-        if (big)
-            radix_hist<kSortItemsBig><<<blocks, kThreads, 0, s>>>(kin, n, shift, hist, blocks);
-        else
-            radix_hist<kSortItems><<<blocks, kThreads, 0, s>>>(kin, n, shift, hist, blocks);
+        radix_hist<kSortItems><<<blocks, kThreads, 0, s>>>(kin, n, shift, hist, blocks);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         e = scan_exclusive_u32(hist, hist, (uint64_t)kBins * blocks, tmp, s);
         if (e != hipSuccess) return e;
-        if (big)
-            radix_scatter<true, kSortItemsBig><<<blocks, kThreads, 0, s>>>(kin, vin, kout, vout, n, shift, hist,
-                                                                           blocks);
-        else
-            radix_scatter<true, kSortItems><<<blocks, kThreads, 0, s>>>(kin, vin, kout, vout, n, shift, hist, blocks);
+        radix_scatter<true, kSortItems><<<blocks, kThreads, 0, s>>>(kin, vin, kout, vout, n, shift, hist, blocks);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
         std::swap(kin, kout);
