@@ -278,6 +278,33 @@ __global__ void k_seed_hits(SearchArgs a, const Node *nodes, uint32_t nn, const 
     }
 }
 
+// The tail of the frontier turned into chains: one chain item per occurrence
+// of every node (a node with r occurrences gives r items that share its row,
+// which stays in the level's entry buffer), so that the last sparse levels
+// are walked along the text like any other chain instead of one FM-index
+// level (and host round trip) per character.  The item count goes to
+// cnt->cnodes; items past caps.cnodes are not written (kOvChainNodes).
+__global__ void __launch_bounds__(256) k_split_nodes(const Node *nodes, uint32_t nn, const Node *wide, uint32_t nw,
+                                                     uint32_t depth, Node *items, Caps caps, Counters *cnt) {
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool active = t < nn + nw;
+    Node nd{0, 0, 0, 0};
+    if (active) nd = t < nn ? nodes[t] : wide[t - nn];
+    const uint32_t r = active ? nd.hi - nd.lo + 1 : 0u;
+    uint32_t tot;
+    const uint32_t pre = wave_excl_scan_u32(r, &tot);
+    unsigned long long base = 0;
+    if ((threadIdx.x & 63) == 0 && tot) base = atomicAdd(&cnt->cnodes, (unsigned long long)tot);
+    base = __shfl(base, 0, 64);
+    if (!r) return;
+    const unsigned long long first = base + pre;
+    if (first + r > caps.cnodes) {
+        atomicOr(&cnt->overflow, kOvChainNodes);
+        return;
+    }
+    for (uint32_t i = 0; i < r; ++i) items[first + i] = Node{nd.lo + i, depth, nd.off, nd.len};
+}
+
 // ---------------------------------------------------------------------------
 // Host driver
 // ---------------------------------------------------------------------------
@@ -999,7 +1026,56 @@ static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64
     };
     static const bool trace = getenv("ALAE_TRACE") != nullptr;
     uint64_t nlw = nlw0;  // nodes of the current level with long rows (in ws->lwide[cur])
+    // The frontier's tail goes to the chain walkers (k_split_nodes) once it is
+    // small (at most kSplitNodes nodes, and a 64th of its largest level, so
+    // that the levels have done the shared work) and has few occurrences.
+    constexpr uint64_t kSplitNodes = 1ull << 15, kSplitChains = 1ull << 17, kSplitShrink = 64;
+    uint64_t peak_nodes = nn + nlw, split_below = kSplitNodes;
     while ((nn > 0 || nlw > 0) && depth < lmax) {
+        peak_nodes = std::max<uint64_t>(peak_nodes, nn + nlw);
+        if (nn + nlw <= split_below && (nn + nlw) * kSplitShrink <= peak_nodes) {
+            // count and write the items (one host round trip), then decide
+            Counters z = *ws->h_cnt;
+            z.cnodes = z.centries = 0;
+            z.overflow = 0;
+            HIP_TRY(hipMemcpyAsync(ws->d_cnt, &z, sizeof(Counters), hipMemcpyHostToDevice, s));
+            set_caps(cur);
+            HIP_TRY(hipEventRecord(ws->evk0, s));
+            k_split_nodes<<<(uint32_t)((nn + nlw + 255) / 256), 256, 0, s>>>(
+                ws->nodes[cur], (uint32_t)nn, ws->lwide[cur], (uint32_t)nlw, (uint32_t)depth, ws->cnodes, caps,
+                ws->d_cnt);
+            double split_ms = 0.0;
+            if ((st = timed(split_ms)) != ALAE_OK) return st;
+            start_ms += split_ms;
+            const uint64_t items = ws->h_cnt->cnodes;
+            if (ws->h_cnt->overflow || items > kSplitChains || items == 0) {
+                split_below = (nn + nlw) / 2;  // too many occurrences: again once the frontier has halved
+            } else {
+                const Counters before = *ws->h_cnt;
+                for (;;) {
+                    Counters z2 = before;
+                    z2.overflow = 0;
+                    HIP_TRY(hipMemcpyAsync(ws->d_cnt, &z2, sizeof(Counters), hipMemcpyHostToDevice, s));
+                    set_caps(cur);
+                    const ChainQueues q{ws->gnodes, ws->gents, ws->wnodes, ws->wents, ws->hkeys, ws->hscores};
+                    HIP_TRY(hipEventRecord(ws->evk0, s));
+                    k_chain_start<<<(uint32_t)((items + kStartBlock - 1) / kStartBlock), kStartBlock, 0, s>>>(
+                        a, sub, ws->cnodes, ws->ents[cur], q, caps, ws->d_cnt);
+                    double ums = 0.0;
+                    if ((st = timed(ums)) != ALAE_OK) return st;
+                    start_ms += ums;
+                    const Counters &c = *ws->h_cnt;
+                    if (!c.overflow) break;
+                    ++retries;
+                    if ((st = grow_overflowed(c, before, cur)) != ALAE_OK) return st;
+                }
+                if (trace)
+                    fprintf(stderr, "[alae] depth %d: %llu+%llu nodes -> %llu chains (frontier tail)\n", depth,
+                            (unsigned long long)nn, (unsigned long long)nlw, (unsigned long long)items);
+                nn = nlw = 0;
+                break;
+            }
+        }
         const int32_t d1 = depth + 1;
         const int nxt = cur ^ 1;
         const double t0 = expand_ms;
