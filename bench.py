@@ -88,8 +88,8 @@ LEVEL_KERNEL = "k_level_tasks+k_expand_children"  # the trie-expansion step of o
 def measured_traffic():
     """HBM bytes per level of the trie-expansion kernels from the committed
     rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE scaled by a
-    device-copy calibration), or None when the kernel sources changed since it
-    was taken."""
+    device-copy calibration), or None when the kernel sources or the host loop
+    that decides which levels run changed since it was taken."""
     import hashlib
     import re
 
@@ -102,7 +102,7 @@ def measured_traffic():
     if not m_b or not m_h:
         return None
     h = hashlib.sha256()
-    for f in ("level_kernels.h", "row_update.h", "device_common.h"):
+    for f in ("level_kernels.h", "row_update.h", "device_common.h", "search.hip"):
         h.update(open(os.path.join(ROOT, "paper_1208_0274_amd", "csrc", f), "rb").read())
     if h.hexdigest()[:16] != m_h.group(1):
         return None
