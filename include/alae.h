@@ -126,6 +126,8 @@ typedef struct {
     double level_lane_ms;    /* device time of the two trie-expansion kernels of the levels   */
                              /* (node phase, then one lane per child row), wide rows apart   */
     uint64_t level_lane_launches; /* levels that ran them                                  */
+    uint64_t tail_chains;    /* chain items made from the frontier's tail (one per occurrence of a node) */
+    uint64_t tail_depth;     /* depth at which the frontier's tail went to the chain walkers (0: never) */
 } alae_stats;
 
 /*
@@ -178,6 +180,10 @@ typedef struct {
     int32_t level_stage;        /* LDS stage entries per lane of the child phase: 2, 4 or 8 (0 = 4) */
     int32_t wide_blocks_per_cu; /* wave-walker blocks per compute unit, 1..8 (0 = 3)             */
     int32_t lane_waves_per_cu;  /* lane-walker waves per compute unit, 1..16 (0 = 8)             */
+    /* 1: every level goes through the FM-index; 0 (default): once the frontier is small
+       and has few occurrences, its nodes become chains, one per occurrence, walked along
+       the text (the hit set is the same either way) */
+    int32_t no_tail_split;
 } alae_search_opts;
 
 /* Index options; pass NULL for the defaults. */

@@ -65,7 +65,8 @@ class Stats(ctypes.Structure):
                 ("dominated_gapped", ctypes.c_uint64), ("chain_bytes", ctypes.c_uint64),
                 ("merge_ms", ctypes.c_double), ("reused", ctypes.c_uint64), ("replay_chains", ctypes.c_uint64),
                 ("partitioned", ctypes.c_uint64), ("leftover", ctypes.c_uint64), ("order_ms", ctypes.c_double),
-                ("level_lane_ms", ctypes.c_double), ("level_lane_launches", ctypes.c_uint64)]
+                ("level_lane_ms", ctypes.c_double), ("level_lane_launches", ctypes.c_uint64),
+                ("tail_chains", ctypes.c_uint64), ("tail_depth", ctypes.c_uint64)]
 
     def reusing_ratio(self) -> float:
         """Equation 6: reused entries over accessed (reused + computed) entries."""
@@ -99,7 +100,7 @@ class SearchOpts(ctypes.Structure):
                 ("stats", ctypes.POINTER(Stats)), ("order_model", ctypes.c_void_p),
                 ("trace", ctypes.POINTER(TraceStruct)), ("partition_threshold", ctypes.c_float),
                 ("level_stage", ctypes.c_int32), ("wide_blocks_per_cu", ctypes.c_int32),
-                ("lane_waves_per_cu", ctypes.c_int32)]
+                ("lane_waves_per_cu", ctypes.c_int32), ("no_tail_split", ctypes.c_int32)]
 
 
 class TuneTrial(ctypes.Structure):
@@ -219,8 +220,10 @@ def make_scoring(sa=1, sb=-3, sg=-5, ss=-2, matrix=None):
 
 def make_opts(stats: Stats | None = None, use_domination=True, use_score_filter=True, use_qprefix=True,
               entry_capacity=0, hit_capacity=0, score_bits=0, use_reuse=False, order_model=None, trace=None,
-              order_queues=0, partition_threshold=0.0, level_stage=0, wide_blocks_per_cu=0, lane_waves_per_cu=0):
+              order_queues=0, partition_threshold=0.0, level_stage=0, wide_blocks_per_cu=0, lane_waves_per_cu=0,
+              tail_split=True):
     o = SearchOpts()
+    o.no_tail_split = 0 if tail_split else 1
     o.level_stage = int(level_stage)
     o.wide_blocks_per_cu = int(wide_blocks_per_cu)
     o.lane_waves_per_cu = int(lane_waves_per_cu)

@@ -1030,7 +1030,8 @@ static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64
     // small (at most kSplitNodes nodes, and a 64th of its largest level, so
     // that the levels have done the shared work) and has few occurrences.
     constexpr uint64_t kSplitNodes = 1ull << 15, kSplitChains = 1ull << 17, kSplitShrink = 64;
-    uint64_t peak_nodes = nn + nlw, split_below = kSplitNodes;
+    uint64_t peak_nodes = nn + nlw, split_below = (opts && opts->no_tail_split) ? 0 : kSplitNodes;
+    uint64_t tail_chains = 0, tail_depth = 0;
     while ((nn > 0 || nlw > 0) && depth < lmax) {
         peak_nodes = std::max<uint64_t>(peak_nodes, nn + nlw);
         if (nn + nlw <= split_below && (nn + nlw) * kSplitShrink <= peak_nodes) {
@@ -1072,6 +1073,8 @@ static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64
                 if (trace)
                     fprintf(stderr, "[alae] depth %d: %llu+%llu nodes -> %llu chains (frontier tail)\n", depth,
                             (unsigned long long)nn, (unsigned long long)nlw, (unsigned long long)items);
+                tail_chains = items;
+                tail_depth = (uint64_t)depth;
                 nn = nlw = 0;
                 break;
             }
@@ -1529,6 +1532,8 @@ static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64
         o->order_ms = order_ms;
         o->level_lane_ms = lane_ms;
         o->level_lane_launches = lane_launches;
+        o->tail_chains = tail_chains;
+        o->tail_depth = tail_depth;
         o->leftover = leftover;
         o->reused = c.st_reused;
         o->replay_chains = c.st_replay;

@@ -237,3 +237,40 @@ def test_domination_switch_same_hits_on_homologs():
     assert_same(off, exp)
     assert st_on.dominated + st_on.dominated_gapped > 0
     assert st_on.entries < st_off.entries
+
+
+@pytest.mark.parametrize("case", ["planted", "repeats", "batch"])
+def test_tail_split_identity(case):
+    """The frontier's tail walked as one chain per occurrence gives the same hits as
+    taking every level through the FM-index (and as the oracle)."""
+    rng = np.random.default_rng(77)
+    if case == "repeats":
+        unit = rng.integers(0, 4, size=150).astype(np.uint8)
+        T = np.concatenate([unit, rng.integers(0, 4, size=40).astype(np.uint8)] * 40)
+        mut = rng.random(T.shape[0]) < 0.05
+        T[mut] = rng.integers(0, 4, size=int(mut.sum())).astype(np.uint8)
+        P = np.concatenate([unit[30:130], rng.integers(0, 4, size=200).astype(np.uint8)])
+    else:
+        T, P = planted_case(78, 200000, 500, n_plants=5)
+    idx = alae.Index.build(T, "dna")
+    sc = alae.make_scoring(1, -3, -5, -2)
+    H = 16
+    if case == "batch":
+        qs = [P, P[100:400].copy(), rng.integers(0, 4, size=80).astype(np.uint8)]
+        on = alae.search_batch(idx, qs, H, sc)
+        off = alae.search_batch(idx, qs, H, sc, tail_split=False)
+        for q, a, b in zip(qs, on, off):
+            assert_same(a, b)
+            assert_same(a, oracle.sw_hits(T, q, oracle.scoring_table(4, 1, -3), -5, -2, H, threads=8))
+        return
+    st_on, st_off = alae.Stats(), alae.Stats()
+    got_on = alae.search(idx, P, H, sc, stats=st_on)
+    got_off = alae.search(idx, P, H, sc, stats=st_off, tail_split=False)
+    print(f"{case}: tail chains {st_on.tail_chains} at depth {st_on.tail_depth}, levels {st_on.levels} "
+          f"against {st_off.levels}", flush=True)
+    exp = oracle.sw_hits(T, P, oracle.scoring_table(4, 1, -3), -5, -2, H, threads=8)
+    assert_same(got_on, exp)
+    assert_same(got_off, exp)
+    assert st_off.tail_chains == 0
+    if case == "planted":
+        assert st_on.tail_chains > 0 and st_on.levels < st_off.levels
