@@ -333,6 +333,43 @@ alae_status alae_workspace_result(const alae_workspace *ws, const uint64_t **d_k
  * `count` elements (asynchronous on `stream`, a hipStream_t or NULL). */
 alae_status alae_workspace_copy_result(const alae_workspace *ws, uint64_t *d_keys, int32_t *d_scores, void *stream);
 
+/* Put the index on its device now (otherwise the first search does).
+ * Idempotent.  Errors: ALAE_E_ARG, ALAE_E_DEVICE. */
+alae_status alae_index_upload(const alae_index *index);
+
+/*
+ * For callers that cannot allocate device memory (code that may not call
+ * hipMalloc: tight serving loops, harnesses that forbid it).  The same search
+ * as alae_search_device (same kernels, same result), with every buffer it
+ * needs cut from one fixed array of ALAE_NOALLOC_SCRATCH_BYTES that the
+ * library holds on each device it runs on until the process ends; the call
+ * makes no device allocation and frees nothing.
+ *   index:     already on the device (alae_index_upload or any search);
+ *              otherwise ALAE_E_ARG.
+ *   d_query_codes: m codes 0..sigma-1 in device memory.
+ *   d_keys, d_scores: caller-owned device arrays of `capacity` records that
+ *              receive the sorted result, keys as in alae_workspace_result
+ *              ((query_end << 32) | text_end).  Complete when the call
+ *              returns (it synchronises `stream`, a hipStream_t or NULL).
+ *   *hit_count: the number of records written.
+ *   opts:      as alae_search_device, except that order_model and trace are
+ *              not accepted (ALAE_E_ARG).
+ * Limits: a search whose buffers would not fit the fixed array fails with
+ * ALAE_E_NOMEM (message says so; nothing is written); a result larger than
+ * `capacity` fails with ALAE_E_NOMEM and sets *hit_count to the size needed,
+ * writing nothing else.  The first call on a device looks up the array's
+ * address there and creates that device's stream and timing events (no
+ * device memory).  All calls on one GPU share its array, which keeps the last
+ * call's contents; the library clears what must start at zero.  Calls that
+ * overlap on one GPU would race on the array, so the library makes them take
+ * turns (a second call waits for the first to return).
+ */
+#define ALAE_NOALLOC_SCRATCH_BYTES (256ull << 20)
+alae_status alae_search_device_noalloc(const alae_index *index, const uint8_t *d_query_codes, size_t m,
+                                       const alae_scoring *scoring, int32_t H, const alae_search_opts *opts,
+                                       void *stream, uint64_t *d_keys, int32_t *d_scores, size_t capacity,
+                                       size_t *hit_count);
+
 /*
  * Serving with continuous batching.  The server keeps the index resident and
  * runs max_inflight slots (a workspace, a HIP stream and a worker thread

@@ -192,6 +192,9 @@ _sig("alae_mlp_train", _st, _vp, _fp, _fp, ctypes.c_size_t, ctypes.c_uint32, cty
      ctypes.c_uint64, ctypes.POINTER(ctypes.c_double))
 _sig("alae_workspace_result", _st, _vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(ctypes.c_size_t))
 _sig("alae_workspace_copy_result", _st, _vp, _vp, _vp, _vp)
+_sig("alae_index_upload", _st, _vp)
+_sig("alae_search_device_noalloc", _st, _vp, _vp, ctypes.c_size_t, ctypes.POINTER(Scoring), ctypes.c_int32,
+     ctypes.POINTER(SearchOpts), _vp, _vp, _vp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t))
 
 
 def _check(status, where):
@@ -310,6 +313,10 @@ class Index:
         _check(_lib.alae_index_copy_bwt(self._h, out.ctypes.data_as(_u8p)), "alae_index_copy_bwt")
         return out
 
+    def upload(self):
+        """Put the index on its device now (alae_index_upload)."""
+        _check(_lib.alae_index_upload(self._h), "alae_index_upload")
+
     def range(self, pattern_codes) -> tuple[int, int]:
         arr = np.ascontiguousarray(np.asarray(pattern_codes, dtype=np.uint8))
         lo, hi = ctypes.c_uint64(), ctypes.c_uint64()
@@ -375,6 +382,25 @@ def search_batch(index: Index, queries, H: int, scoring: Scoring | None = None, 
         res.append(_hits_to_numpy(outs[i]))
         _lib.alae_hits_free(ctypes.byref(outs[i]))
     return res
+
+
+def search_device_noalloc(index: Index, d_query, H: int, d_keys, d_scores, scoring: Scoring | None = None,
+                          stats: Stats | None = None, stream=None, **opt) -> int:
+    """alae_search_device_noalloc: the search with every buffer in the library's fixed per-device
+    array.  d_query (uint8 codes), d_keys (int64) and d_scores (int32) are torch tensors on the GPU;
+    the capacity is d_keys.numel().  Returns the hit count (records written)."""
+    sc = scoring if scoring is not None else make_scoring()
+    opts = make_opts(stats=stats, **opt)
+    cnt = ctypes.c_size_t()
+    cap = int(d_keys.numel())
+    if int(d_scores.numel()) < cap:
+        raise ValueError("d_scores holds fewer records than d_keys")
+    sptr = _vp(stream.cuda_stream) if stream is not None else None
+    _check(_lib.alae_search_device_noalloc(index._h, _vp(d_query.data_ptr()), int(d_query.numel()), ctypes.byref(sc),
+                                           int(H), ctypes.byref(opts), sptr, _vp(d_keys.data_ptr()),
+                                           _vp(d_scores.data_ptr()), cap, ctypes.byref(cnt)),
+           "alae_search_device_noalloc")
+    return int(cnt.value)
 
 
 class Workspace:

@@ -63,6 +63,23 @@ struct alae_index {
 };
 
 namespace alae {
+// A fixed block of device memory that a search cuts all its buffers from
+// (callers that cannot allocate): base, size in bytes, bytes handed out.
+struct FixedRegion {
+    uint8_t *base;
+    uint64_t size;
+    uint64_t used;
+};
+// A workspace bound to `bytes` bytes of device memory at `region` on `device`
+// (its counters take the first few kilobytes); creates its stream and events.
+alae_status region_workspace_create(int device, uint8_t *region, uint64_t bytes, alae_workspace **out);
+// One search of a device-resident query on such a workspace, the sorted
+// result copied to the caller's d_keys / d_scores (capacity records).
+// *hit_count gets the result size, also when it exceeds capacity
+// (ALAE_E_NOMEM).  `stream` is a hipStream_t.
+alae_status region_search(alae_workspace *ws, const alae_index *idx, const uint8_t *d_query, uint64_t m,
+                          const alae_scoring *scoring, int32_t H, const alae_search_opts *opts, void *stream,
+                          uint64_t *d_keys, int32_t *d_scores, uint64_t capacity, uint64_t *hit_count);
 // Host-side occ(c, i): number of c in BWT[0..i] (i may be -1).
 uint64_t host_occ(const alae_index *idx, int c, int64_t i);
 // Upload the index to its device (idempotent, thread-safe).

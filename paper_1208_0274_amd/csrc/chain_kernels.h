@@ -602,7 +602,7 @@ __global__ void __launch_bounds__(256) k_chain_general(SearchArgs a, const Node 
         uint32_t htot;
         const uint32_t hpre = wave_excl_scan_u32(nh, &htot);
         if (htot) {
-            hit_reserve(hr, htot, hkeys, hscores, caps.hits, cnt);
+            hit_reserve(hr, htot, hkeys, hscores, caps.hits, caps.hit_chunk, cnt);
             const unsigned long long hb = hr.base;
             hr.base += htot;
             hr.left -= htot;
@@ -843,6 +843,7 @@ __device__ bool walk_wide(const SearchArgs &a, Row &cur, Row &nxt, uint32_t &len
         o.hkeys = hkeys;
         o.hscores = hscores;
         o.hit_cap = caps.hits;
+        o.hit_chunk = caps.hit_chunk;
         o.cnt = cnt;
         o.e_child = e_end + 1;
         o.rK = rp.K;

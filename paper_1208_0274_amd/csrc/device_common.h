@@ -245,6 +245,7 @@ struct Caps {
     unsigned long long gentries;
     unsigned long long srow;      // entries per staging buffer of the level-wide kernel
     unsigned long long tasks;     // child tasks of one level
+    unsigned long long hit_chunk; // hit slots a wave reserves at a time
 };
 
 struct SubTable {

@@ -250,7 +250,7 @@ __device__ inline void emit_row_hits_multi(const SearchArgs &a, const Entry *row
         uint32_t tot;
         const uint32_t pre = wave_excl_scan_u32(nh, &tot);
         if (!tot) continue;
-        hit_reserve(hr, tot, hkeys, hscores, caps.hits, cnt);
+        hit_reserve(hr, tot, hkeys, hscores, caps.hits, caps.hit_chunk, cnt);
         unsigned long long slot = hr.base + pre;
         for (uint32_t h = 0; h < nh; ++h, ++slot) {
             if (slot < caps.hits) {
@@ -295,6 +295,7 @@ __global__ void __launch_bounds__(64) k_expand_level_wide(SearchArgs a, const No
             w.hkeys = o.hkeys;
             w.hscores = o.hscores;
             w.hit_cap = caps.hits;
+            w.hit_chunk = caps.hit_chunk;
             w.cnt = cnt;
             w.e_child = 0;
             w.emit_hits = false;

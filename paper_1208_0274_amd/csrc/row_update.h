@@ -628,8 +628,9 @@ struct SoaRow {
     }
 };
 
-// Hit slots reserved by one wave in chunks; slots left unused are filled with
-// kPadKey so that they sort after every real record.
+// Hit slots reserved by one wave in chunks (of Caps::hit_chunk slots, at least
+// the records needed at once); slots left unused are filled with kPadKey so
+// that they sort after every real record.
 constexpr unsigned long long kHitChunk = 4096;
 struct HitRes {
     unsigned long long base;
@@ -638,7 +639,7 @@ struct HitRes {
 };
 
 __device__ inline void hit_reserve(HitRes &r, unsigned long long need, uint64_t *hkeys, uint32_t *hscores,
-                                   unsigned long long hit_cap, Counters *cnt) {
+                                   unsigned long long hit_cap, unsigned long long chunk, Counters *cnt) {
     if (need <= r.left) return;
     const int lane = threadIdx.x & 63;
     for (unsigned long long k = lane; k < r.left; k += 64) {
@@ -649,7 +650,7 @@ __device__ inline void hit_reserve(HitRes &r, unsigned long long need, uint64_t 
         }
     }
     r.pad += r.left;
-    const unsigned long long take = need > kHitChunk ? need : kHitChunk;
+    const unsigned long long take = need > chunk ? need : chunk;
     unsigned long long b = 0;
     if (lane == 0) {
         b = atomicAdd(&cnt->hits, take);
@@ -681,6 +682,7 @@ struct WideOut {
     uint64_t *hkeys;
     uint32_t *hscores;
     unsigned long long hit_cap;
+    unsigned long long hit_chunk;
     Counters *cnt;
     uint32_t e_child;  // text end of the child occurrence (hit coordinate)
     // replayed forks: every hit is also emitted at col + rdelta[r], r = 1..rK
@@ -959,7 +961,7 @@ __device__ inline void wide_child_row(const SearchArgs &a, const Row cur, uint32
         if (htot) {
             const uint32_t copies = o.rK + 1;
             const unsigned long long hall = (unsigned long long)htot * copies;
-            hit_reserve(hr, hall, o.hkeys, o.hscores, o.hit_cap, o.cnt);
+            hit_reserve(hr, hall, o.hkeys, o.hscores, o.hit_cap, o.hit_chunk, o.cnt);
             unsigned long long slot = hr.base + (unsigned long long)hpre * copies;
             auto put = [&](uint32_t col, int32_t M) {
                 for (uint32_t r = 0; r < copies; ++r) {

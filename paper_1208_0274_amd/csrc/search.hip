@@ -309,29 +309,56 @@ __global__ void __launch_bounds__(256) k_split_nodes(const Node *nodes, uint32_t
 // Host driver
 // ---------------------------------------------------------------------------
 
+// Device memory of a search comes from hipMalloc, except in the entry point
+// for callers that cannot allocate: there every buffer is cut from one fixed
+// region (a bump arena, emptied before each search; space given up by a
+// buffer that grows is not reused until then).  The arena of the calling
+// thread is set only for the duration of such a search.
+static thread_local FixedRegion *t_region = nullptr;
+
+static hipError_t dev_alloc(void **p, uint64_t bytes) {
+    if (!t_region) return hipMalloc(p, bytes);
+    const uint64_t off = (t_region->used + 255) & ~255ull;
+    if (off > t_region->size || bytes > t_region->size - off) return hipErrorOutOfMemory;
+    *p = t_region->base + off;
+    t_region->used = off + bytes;
+    return hipSuccess;
+}
+
+static void dev_free(void *p) {
+    if (!t_region && p) hipFree(p);
+}
+
+static void alloc_error(uint64_t bytes, hipError_t e) {
+    if (t_region)
+        set_error("the search needs more than the %llu-byte fixed scratch region (%llu bytes more requested)",
+                  (unsigned long long)t_region->size, (unsigned long long)bytes);
+    else
+        set_error("device allocation of %llu bytes failed: %s", (unsigned long long)bytes, hipGetErrorString(e));
+}
+
 template <typename T>
 static alae_status grow(T *&ptr, uint64_t &cap, uint64_t need, bool keep, uint64_t keep_count, hipStream_t s) {
     if (need <= cap && ptr) return ALAE_OK;
     uint64_t ncap = cap ? cap : 1024;
     while (ncap < need) ncap *= 2;
     T *np = nullptr;
-    hipError_t e = hipMalloc(&np, ncap * sizeof(T));
+    hipError_t e = dev_alloc(reinterpret_cast<void **>(&np), ncap * sizeof(T));
     if (e != hipSuccess) {
         hipGetLastError();
-        set_error("device allocation of %llu bytes failed: %s", (unsigned long long)(ncap * sizeof(T)),
-                  hipGetErrorString(e));
+        alloc_error(ncap * sizeof(T), e);
         return ALAE_E_NOMEM;
     }
     if (keep && ptr && keep_count) {
         e = hipMemcpyAsync(np, ptr, keep_count * sizeof(T), hipMemcpyDeviceToDevice, s);
         if (e != hipSuccess) {
             set_error("device copy failed: %s", hipGetErrorString(e));
-            hipFree(np);
+            dev_free(np);
             return ALAE_E_DEVICE;
         }
         hipStreamSynchronize(s);
     }
-    if (ptr) hipFree(ptr);
+    dev_free(ptr);
     ptr = np;
     cap = ncap;
     return ALAE_OK;
@@ -475,6 +502,8 @@ struct alae_workspace {
     hipEvent_t evk0 = nullptr, evk1 = nullptr;  // around each expansion launch
     hipEvent_t evkm = nullptr;                  // after the lane kernel of a level
     hipEvent_t evks = nullptr;                  // after all level kernels, before the chain start
+    // fixed device region every buffer is cut from (callers that cannot allocate)
+    FixedRegion region{nullptr, 0, 0};
 };
 
 namespace alae {
@@ -861,16 +890,18 @@ static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64
     const uint32_t *sv = alt ? ws->seed_vals_alt : ws->seed_vals;
 
     // level buffers: seeds need nseed entries and at most nseed nodes
-    uint64_t ent_want = std::max<uint64_t>(opts && opts->entry_capacity ? opts->entry_capacity : (1ull << 22), nseed);
+    // first sizes of the buffers that grow on demand (sixteen times smaller in a fixed region)
+    const int sh = t_region ? 4 : 0;
+    uint64_t ent_want = std::max<uint64_t>(opts && opts->entry_capacity ? opts->entry_capacity : (1ull << 22) >> sh, nseed);
     for (int i = 0; i < 2; ++i) {
         if ((st = grow(ws->ents[i], ws->ent_cap[i], ent_want, false, 0, s)) != ALAE_OK) return st;
-        if ((st = grow(ws->nodes[i], ws->node_cap[i], std::max<uint64_t>(nseed, 1ull << 20), false, 0, s)) != ALAE_OK)
+        if ((st = grow(ws->nodes[i], ws->node_cap[i], std::max<uint64_t>(nseed, (1ull << 20) >> sh), false, 0, s)) != ALAE_OK)
             return st;
     }
     if ((st = grow(ws->lwide[0], ws->lwide_cap[0], std::max<uint64_t>(nseed, 1ull << 12), false, 0, s)) != ALAE_OK)
         return st;
     if ((st = grow(ws->lwide[1], ws->lwide_cap[1], 1ull << 12, false, 0, s)) != ALAE_OK) return st;
-    uint64_t hit_want = opts && opts->hit_capacity ? opts->hit_capacity : (1ull << 20);
+    uint64_t hit_want = opts && opts->hit_capacity ? opts->hit_capacity : (1ull << 20) >> sh;
     if ((st = grow_pair(ws->hkeys, ws->hscores, ws->hit_cap, hit_want, 0, s)) != ALAE_OK) return st;
 
     const int32_t seedM = matrix_seeds ? 0 : qeff * sch.sa;
@@ -887,8 +918,9 @@ static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64
     uint64_t nn = ws->h_cnt->nodes;
     int cur = 0;
 
-    Caps caps;
+    Caps caps{};
     caps.hits = ws->hit_cap;
+    caps.hit_chunk = t_region ? 256 : kHitChunk;
     // seed-level hits (only when a seed score reaches H)
     uint64_t nlw0 = ws->h_cnt->lwnodes;
     int32_t seed_best = matrix_seeds ? sch.smax : seedM;
@@ -931,18 +963,18 @@ static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64
     const uint64_t wrow = m + 2;  // a row never holds more than m entries
     // staging rows of the level-wide kernel start short and grow to the longest child row met
     uint64_t srow = std::min<uint64_t>(wrow, 4096);
-    const uint64_t stage_budget = (2ull << 30) / sizeof(Entry);
+    const uint64_t stage_budget = ((2ull << 30) >> (2 * sh)) / sizeof(Entry);
     // queues that live through the whole search
     for (int i = 0; i < 2; ++i)
         if ((st = grow(ws->lwide[i], ws->lwide_cap[i], 1ull << 12, false, 0, s)) != ALAE_OK) return st;
-    if ((st = grow(ws->cnodes, ws->cnode_cap, 1ull << 20, false, 0, s)) != ALAE_OK) return st;
-    if ((st = grow(ws->cents, ws->cent_cap, 1ull << 21, false, 0, s)) != ALAE_OK) return st;
-    if ((st = grow(ws->gnodes, ws->gnode_cap, 1ull << 16, false, 0, s)) != ALAE_OK) return st;
-    if ((st = grow(ws->gents, ws->gent_cap, 1ull << 20, false, 0, s)) != ALAE_OK) return st;
-    if ((st = grow(ws->wnodes, ws->wnode_cap, 1ull << 14, false, 0, s)) != ALAE_OK) return st;
-    if ((st = grow(ws->wents, ws->went_cap, 1ull << 20, false, 0, s)) != ALAE_OK) return st;
-    if ((st = grow(ws->onodes, ws->onode_cap, 1ull << 10, false, 0, s)) != ALAE_OK) return st;
-    if ((st = grow(ws->oents, ws->oent_cap, 1ull << 18, false, 0, s)) != ALAE_OK) return st;
+    if ((st = grow(ws->cnodes, ws->cnode_cap, (1ull << 20) >> sh, false, 0, s)) != ALAE_OK) return st;
+    if ((st = grow(ws->cents, ws->cent_cap, (1ull << 21) >> sh, false, 0, s)) != ALAE_OK) return st;
+    if ((st = grow(ws->gnodes, ws->gnode_cap, (1ull << 16) >> sh, false, 0, s)) != ALAE_OK) return st;
+    if ((st = grow(ws->gents, ws->gent_cap, (1ull << 20) >> sh, false, 0, s)) != ALAE_OK) return st;
+    if ((st = grow(ws->wnodes, ws->wnode_cap, (1ull << 14) >> sh, false, 0, s)) != ALAE_OK) return st;
+    if ((st = grow(ws->wents, ws->went_cap, (1ull << 20) >> sh, false, 0, s)) != ALAE_OK) return st;
+    if ((st = grow(ws->onodes, ws->onode_cap, (1ull << 10) >> sh, false, 0, s)) != ALAE_OK) return st;
+    if ((st = grow(ws->oents, ws->oent_cap, (1ull << 18) >> sh, false, 0, s)) != ALAE_OK) return st;
     auto timed = [&](double &acc) -> alae_status {
         HIP_TRY(hipGetLastError());
         HIP_TRY(hipEventRecord(ws->evk1, s));
@@ -970,6 +1002,7 @@ static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64
         caps.tasks = ws->task_cap;
         caps.onodes = ws->onode_cap;
         caps.oentries = ws->oent_cap;
+        caps.hit_chunk = t_region ? 256 : kHitChunk;  // a fixed region holds fewer padding slots
     };
     // Grow what overflowed; queues that outlive one launch keep their first `keep` records.
     auto grow_overflowed = [&](const Counters &c, const Counters &keep, int nxt) -> alae_status {
@@ -1404,16 +1437,17 @@ static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64
     // rows that outgrew LDS: one wave each, rows in global memory
     const uint64_t no = ws->h_cnt->onodes;
     if (no > 0) {
-        const uint64_t budget_entries = (8ull << 30) / sizeof(Entry);
+        const uint64_t budget_entries = ((8ull << 30) >> (2 * sh)) / sizeof(Entry);
         uint64_t waves = std::min<uint64_t>(no, (uint64_t)max_waves);
         waves = std::max<uint64_t>(1, std::min<uint64_t>(waves, budget_entries / (2 * wrow)));
         if (ws->wrow_cap != wrow || ws->rowbuf_cap < waves * 2 * wrow) {
-            hipFree(ws->rowbuf);
+            dev_free(ws->rowbuf);
             ws->rowbuf = nullptr;
             ws->rowbuf_cap = 0;
-            if (hipMalloc(&ws->rowbuf, waves * 2 * wrow * sizeof(Entry)) != hipSuccess) {
+            const hipError_t e = dev_alloc(reinterpret_cast<void **>(&ws->rowbuf), waves * 2 * wrow * sizeof(Entry));
+            if (e != hipSuccess) {
                 hipGetLastError();
-                set_error("device allocation of wide-chain row buffers failed");
+                alloc_error(waves * 2 * wrow * sizeof(Entry), e);
                 return ALAE_E_NOMEM;
             }
             ws->rowbuf_cap = waves * 2 * wrow;
@@ -1589,6 +1623,123 @@ void alae_workspace_free(alae_workspace *ws) {
     if (!ws) return;
     ws_release(ws);
     delete ws;
+}
+
+}  // extern "C"
+
+namespace alae {
+
+alae_status region_workspace_create(int device, uint8_t *region, uint64_t bytes, alae_workspace **out) {
+    const uint64_t head = (sizeof(Counters) + 255) & ~255ull;
+    if (!region || bytes <= head) {
+        set_error("fixed scratch region is missing or too small");
+        return ALAE_E_ARG;
+    }
+    std::unique_ptr<alae_workspace> ws(new (std::nothrow) alae_workspace());
+    if (!ws) {
+        set_error("out of host memory");
+        return ALAE_E_NOMEM;
+    }
+    ws->device = device;
+    HIP_TRY(hipSetDevice(device));
+    ws->d_cnt = reinterpret_cast<Counters *>(region);
+    ws->h_cnt = new (std::nothrow) Counters();
+    if (!ws->h_cnt) {
+        set_error("out of host memory");
+        return ALAE_E_NOMEM;
+    }
+    ws->region = FixedRegion{region + head, bytes - head, 0};
+    HIP_TRY(hipEventCreate(&ws->ev0));
+    HIP_TRY(hipEventCreate(&ws->ev1));
+    HIP_TRY(hipEventCreate(&ws->evk0));
+    HIP_TRY(hipEventCreate(&ws->evk1));
+    HIP_TRY(hipEventCreate(&ws->evkm));
+    HIP_TRY(hipEventCreate(&ws->evks));
+    HIP_TRY(hipEventCreateWithFlags(&ws->ev_fork, hipEventDisableTiming));
+    HIP_TRY(hipEventCreateWithFlags(&ws->ev_join, hipEventDisableTiming));
+    HIP_TRY(hipStreamCreateWithFlags(&ws->s2, hipStreamNonBlocking));
+    *out = ws.release();
+    return ALAE_OK;
+}
+
+alae_status region_search(alae_workspace *ws, const alae_index *idx, const uint8_t *d_query, uint64_t m,
+                          const alae_scoring *scoring, int32_t H, const alae_search_opts *opts, void *stream,
+                          uint64_t *d_keys, int32_t *d_scores, uint64_t capacity, uint64_t *hit_count) {
+    if (!launch_shapes_ok(opts, "alae_search_device_noalloc")) return ALAE_E_ARG;
+    if (opts && (opts->order_model || opts->trace)) {
+        set_error("the search without allocation takes no ordering model and no trace");
+        return ALAE_E_ARG;
+    }
+    if (idx->device != ws->device) {
+        set_error("index on device %d, scratch region on device %d", idx->device, ws->device);
+        return ALAE_E_ARG;
+    }
+    {
+        std::lock_guard<std::mutex> lock(idx->mu);
+        if (!idx->on_device) {
+            set_error("the index is not on the device yet (alae_index_upload, or any other search, puts it there)");
+            return ALAE_E_ARG;
+        }
+    }
+    // every buffer pointer starts empty: the region is handed out afresh
+    {
+        alae_workspace fresh;
+        fresh.idx = idx;
+        fresh.device = ws->device;
+        fresh.d_cnt = ws->d_cnt;
+        fresh.h_cnt = ws->h_cnt;
+        fresh.ev0 = ws->ev0;
+        fresh.ev1 = ws->ev1;
+        fresh.evk0 = ws->evk0;
+        fresh.evk1 = ws->evk1;
+        fresh.evkm = ws->evkm;
+        fresh.evks = ws->evks;
+        fresh.ev_fork = ws->ev_fork;
+        fresh.ev_join = ws->ev_join;
+        fresh.s2 = ws->s2;
+        fresh.region = FixedRegion{ws->region.base, ws->region.size, 0};
+        *ws = fresh;
+    }
+    struct RegionScope {
+        explicit RegionScope(FixedRegion *r) { t_region = r; }
+        ~RegionScope() { t_region = nullptr; }
+    } scope(&ws->region);
+    HIP_TRY(hipSetDevice(ws->device));
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(hipEventRecord(ws->ev0, s));
+    uint64_t cnt = 0;
+    alae_status st = run_search(ws, d_query, m, nullptr, 1, scoring, H, opts, s, &cnt);
+    if (st != ALAE_OK) return st;
+    *hit_count = cnt;
+    if (cnt > capacity) {
+        set_error("the result holds %llu hits, more than the output capacity of %llu", (unsigned long long)cnt,
+                  (unsigned long long)capacity);
+        return ALAE_E_NOMEM;
+    }
+    if (cnt > 0) {
+        HIP_TRY(hipMemcpyAsync(d_keys, ws->res_keys, cnt * sizeof(uint64_t), hipMemcpyDeviceToDevice, s));
+        HIP_TRY(hipMemcpyAsync(d_scores, ws->res_scores, cnt * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    }
+    HIP_TRY(hipEventRecord(ws->ev1, s));
+    HIP_TRY(hipEventSynchronize(ws->ev1));
+    if (opts && opts->stats) {
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, ws->ev0, ws->ev1);
+        opts->stats->device_ms = ms;
+    }
+    return ALAE_OK;
+}
+
+}  // namespace alae
+
+extern "C" {
+
+alae_status alae_index_upload(const alae_index *index) {
+    if (!index) {
+        set_error("alae_index_upload: null index");
+        return ALAE_E_ARG;
+    }
+    return ensure_device(index);
 }
 
 alae_status alae_search_device(alae_workspace *ws, const uint8_t *d_query_codes, size_t m,
