@@ -189,7 +189,10 @@ typedef struct {
 /* Index options; pass NULL for the defaults. */
 typedef struct {
     int32_t device;            /* HIP device ordinal used when the index goes to the GPU */
-    int32_t reserved;
+    int32_t builder;           /* 1: build on the host (SA-IS); 2: build on the GPU (prefix
+                                  doubling) and keep the arrays resident there; 0 (default): the
+                                  GPU for texts of 2^22 characters or more when the device exists,
+                                  else the host.  Both give the same index. */
 } alae_index_opts;
 
 typedef struct alae_index alae_index;

@@ -114,7 +114,7 @@ class TuneReport(ctypes.Structure):
 
 
 class IndexOpts(ctypes.Structure):
-    _fields_ = [("device", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+    _fields_ = [("device", ctypes.c_int32), ("builder", ctypes.c_int32)]
 
 
 class IndexInfo(ctypes.Structure):
@@ -267,11 +267,14 @@ class Index:
         self._h = _vp(handle)
         self.alphabet = alphabet
 
+    BUILDERS = {"auto": 0, "host": 1, "gpu": 2}
+
     @classmethod
-    def build(cls, text, alphabet="dna", device: int = 0):
-        """text: str/bytes of letters, or a uint8 array of codes."""
+    def build(cls, text, alphabet="dna", device: int = 0, builder: str = "auto"):
+        """text: str/bytes of letters, or a uint8 array of codes.  builder: "host" (SA-IS),
+        "gpu" (prefix doubling on the device) or "auto" (the GPU for texts of 2^22 or more)."""
         a = _alpha(alphabet)
-        opts = IndexOpts(device, 0)
+        opts = IndexOpts(device, cls.BUILDERS[builder])
         h = _vp()
         if isinstance(text, np.ndarray):
             arr = np.ascontiguousarray(text, dtype=np.uint8)

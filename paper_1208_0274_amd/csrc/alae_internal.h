@@ -80,6 +80,12 @@ alae_status region_workspace_create(int device, uint8_t *region, uint64_t bytes,
 alae_status region_search(alae_workspace *ws, const alae_index *idx, const uint8_t *d_query, uint64_t m,
                           const alae_scoring *scoring, int32_t H, const alae_search_opts *opts, void *stream,
                           uint64_t *d_keys, int32_t *d_scores, uint64_t capacity, uint64_t *hit_count);
+// True when HIP device `device` exists.
+bool device_present(int device);
+// Build the suffix array, BWT, occ blocks and C of `idx` (text, n, sigma and
+// device set) on its GPU; the device arrays stay resident and the host
+// arrays are filled from them.
+alae_status build_index_on_device(alae_index *idx);
 // Host-side occ(c, i): number of c in BWT[0..i] (i may be -1).
 uint64_t host_occ(const alae_index *idx, int c, int64_t i);
 // Upload the index to its device (idempotent, thread-safe).

@@ -304,9 +304,16 @@ alae_status alae_index_build_codes(const uint8_t *codes, size_t n, alae_alphabet
     idx->sigma = sigma;
     idx->alphabet = alphabet;
     idx->device = opts ? opts->device : 0;
+    // builder: 1 = host, 2 = GPU, 0 = the GPU for texts of 2^22 characters or more when one is present
+    const int builder = opts ? opts->builder : 0;
+    if (builder < 0 || builder > 2) {
+        set_error("alae_index_build: builder must be 0, 1 or 2 (got %d)", builder);
+        return ALAE_E_ARG;
+    }
+    const bool on_gpu = builder == 2 || (builder == 0 && n >= (1ull << 22) && device_present(idx->device));
     alae_status st;
     try {
-        st = build_from_codes(idx);
+        st = on_gpu ? build_index_on_device(idx.get()) : build_from_codes(idx);
     } catch (const std::bad_alloc &) {
         set_error("alae_index_build: out of host memory");
         return ALAE_E_NOMEM;
