@@ -96,7 +96,7 @@ typedef struct {
     uint64_t emitted;        /* hit records emitted before the max-merge               */
     uint64_t hits;           /* distinct (query end, text end) pairs reported          */
     uint64_t levels;         /* trie depths visited                                    */
-    uint64_t retries;        /* capacity or int16-saturation re-runs                    */
+    uint64_t retries;        /* launches run again with larger buffers after an overflow */
     uint64_t max_depth;      /* deepest trie node with a live entry                    */
     double device_ms;        /* device time of the search (events around the work)      */
     /* traffic and time per kernel family (roofline accounting) */
@@ -162,7 +162,11 @@ typedef struct {
 
 /* Search options; pass NULL for the defaults. */
 typedef struct {
-    int32_t score_bits;        /* 0 = automatic, 16 or 32                                  */
+    int32_t zero_floor_only;   /* 1: BWT-SW's rule alone (Section 2.4): every trie row is expanded
+                                  while it holds a positive entry; no length filter (Theorem 1),
+                                  score filter (Theorem 2), q-prefix seeding (Theorem 3, seeds at
+                                  depth 1) or domination (Section 3.2).  Same hits, more work: the
+                                  baseline of the filtering ratio (Equation 5).  Default 0.   */
     int32_t use_domination;    /* Section 3.2 domination test (default 1)                  */
     int32_t use_score_filter;  /* Theorem 2 (default 1)                                     */
     int32_t use_qprefix;       /* Theorem 3 q-prefix seeding (default 1)                    */
@@ -184,6 +188,9 @@ typedef struct {
        and has few occurrences, its nodes become chains, one per occurrence, walked along
        the text (the hit set is the same either way) */
     int32_t no_tail_split;
+    /* batched searches: queries are taken in order in groups of at most this many columns
+       (a longer query alone), one trie traversal per group; 0 = 2^19 */
+    uint64_t batch_columns;
 } alae_search_opts;
 
 /* Index options; pass NULL for the defaults. */

@@ -93,14 +93,15 @@ class TraceStruct(ctypes.Structure):
 
 
 class SearchOpts(ctypes.Structure):
-    _fields_ = [("score_bits", ctypes.c_int32), ("use_domination", ctypes.c_int32),
+    _fields_ = [("zero_floor_only", ctypes.c_int32), ("use_domination", ctypes.c_int32),
                 ("use_score_filter", ctypes.c_int32), ("use_qprefix", ctypes.c_int32),
                 ("use_reuse", ctypes.c_int32), ("order_queues", ctypes.c_int32),
                 ("entry_capacity", ctypes.c_uint64), ("hit_capacity", ctypes.c_uint64),
                 ("stats", ctypes.POINTER(Stats)), ("order_model", ctypes.c_void_p),
                 ("trace", ctypes.POINTER(TraceStruct)), ("partition_threshold", ctypes.c_float),
                 ("level_stage", ctypes.c_int32), ("wide_blocks_per_cu", ctypes.c_int32),
-                ("lane_waves_per_cu", ctypes.c_int32), ("no_tail_split", ctypes.c_int32)]
+                ("lane_waves_per_cu", ctypes.c_int32), ("no_tail_split", ctypes.c_int32),
+                ("batch_columns", ctypes.c_uint64)]
 
 
 class TuneTrial(ctypes.Structure):
@@ -222,10 +223,11 @@ def make_scoring(sa=1, sb=-3, sg=-5, ss=-2, matrix=None):
 
 
 def make_opts(stats: Stats | None = None, use_domination=True, use_score_filter=True, use_qprefix=True,
-              entry_capacity=0, hit_capacity=0, score_bits=0, use_reuse=False, order_model=None, trace=None,
+              entry_capacity=0, hit_capacity=0, zero_floor_only=False, use_reuse=False, order_model=None, trace=None,
               order_queues=0, partition_threshold=0.0, level_stage=0, wide_blocks_per_cu=0, lane_waves_per_cu=0,
-              tail_split=True):
+              tail_split=True, batch_columns=0):
     o = SearchOpts()
+    o.batch_columns = int(batch_columns)
     o.no_tail_split = 0 if tail_split else 1
     o.level_stage = int(level_stage)
     o.wide_blocks_per_cu = int(wide_blocks_per_cu)
@@ -235,7 +237,7 @@ def make_opts(stats: Stats | None = None, use_domination=True, use_score_filter=
     o.use_reuse = 1 if use_reuse else 0
     o.order_model = order_model._h.value if order_model is not None else None
     o.trace = ctypes.pointer(trace._s) if trace is not None else None
-    o.score_bits = int(score_bits)
+    o.zero_floor_only = 1 if zero_floor_only else 0
     o.use_domination = 1 if use_domination else 0
     o.use_score_filter = 1 if use_score_filter else 0
     o.use_qprefix = 1 if use_qprefix else 0

@@ -428,6 +428,10 @@ struct alae_workspace {
     uint32_t *res_scores = nullptr;
     uint64_t res_cap = 0;
     uint64_t res_count = 0;
+    // results of a batch run in several groups, appended group by group
+    uint64_t *acc_keys = nullptr;
+    uint32_t *acc_scores = nullptr;
+    uint64_t acc_cap = 0;
     // query
     uint8_t *d_query = nullptr;
     uint64_t q_cap = 0;
@@ -523,6 +527,8 @@ static void ws_release(alae_workspace *ws) {
     hipFree(ws->pos);
     hipFree(ws->res_keys);
     hipFree(ws->res_scores);
+    hipFree(ws->acc_keys);
+    hipFree(ws->acc_scores);
     hipFree(ws->d_query);
     hipFree(ws->qpad);
     hipFree(ws->prof);
@@ -779,10 +785,14 @@ static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64
         }
     }
     const int sigma = idx->sigma;
-    const bool use_score_filter = opts ? opts->use_score_filter != 0 : true;
-    const bool use_dom = opts ? opts->use_domination != 0 : true;
-    const bool use_q = opts ? opts->use_qprefix != 0 : true;
-    const int64_t lmax = lmax_of((int64_t)mlong, sch.smax, scoring->sg, scoring->ss, H);
+    // BWT-SW's rule alone (Section 2.4): rows are kept while they hold a positive entry.  The
+    // length filter then prunes nothing more: with threshold 1 in Equation 1, L_max bounds every
+    // alignment of positive score, so no row with a positive entry is deeper.
+    const bool zero_floor_only = opts && opts->zero_floor_only;
+    const bool use_score_filter = !zero_floor_only && (opts ? opts->use_score_filter != 0 : true);
+    const bool use_dom = !zero_floor_only && (opts ? opts->use_domination != 0 : true);
+    const bool use_q = !zero_floor_only && (opts ? opts->use_qprefix != 0 : true);
+    const int64_t lmax = lmax_of((int64_t)mlong, sch.smax, scoring->sg, scoring->ss, zero_floor_only ? 1 : H);
     if ((int64_t)sch.smax * (lmax + 2) > (1ll << 28)) {
         set_error("scores could exceed the 32-bit range of the kernels (m too long for this scheme)");
         return ALAE_E_TOO_LONG;
@@ -1844,6 +1854,57 @@ alae_status alae_autotune(alae_workspace *ws, const uint8_t *d_query_codes, size
     return ALAE_OK;
 }
 
+}  // extern "C"
+
+namespace alae {
+
+// Statistics of several searches added up (the deepest depths kept).
+static void add_stats(alae_stats &to, const alae_stats &x) {
+#define ALAE_ADD(f) to.f += x.f
+    ALAE_ADD(nodes);
+    ALAE_ADD(entries);
+    ALAE_ADD(entries_diag);
+    ALAE_ADD(entries_gap2);
+    ALAE_ADD(entries_gap3);
+    ALAE_ADD(dominated);
+    ALAE_ADD(emitted);
+    ALAE_ADD(hits);
+    ALAE_ADD(levels);
+    ALAE_ADD(retries);
+    ALAE_ADD(occ_reads);
+    ALAE_ADD(sa_reads);
+    ALAE_ADD(text_reads);
+    ALAE_ADD(frontier_bytes);
+    ALAE_ADD(level_launches);
+    ALAE_ADD(level_ms);
+    ALAE_ADD(start_ms);
+    ALAE_ADD(general_ms);
+    ALAE_ADD(wide_ms);
+    ALAE_ADD(chain_steps);
+    ALAE_ADD(wide_steps);
+    ALAE_ADD(promoted);
+    ALAE_ADD(dominated_gapped);
+    ALAE_ADD(chain_bytes);
+    ALAE_ADD(merge_ms);
+    ALAE_ADD(reused);
+    ALAE_ADD(replay_chains);
+    ALAE_ADD(partitioned);
+    ALAE_ADD(leftover);
+    ALAE_ADD(order_ms);
+    ALAE_ADD(level_lane_ms);
+    ALAE_ADD(level_lane_launches);
+    ALAE_ADD(tail_chains);
+#undef ALAE_ADD
+    to.max_depth = std::max(to.max_depth, x.max_depth);
+    to.tail_depth = std::max(to.tail_depth, x.tail_depth);
+}
+
+constexpr uint64_t kBatchColumns = 1ull << 19;
+
+}  // namespace alae
+
+extern "C" {
+
 alae_status alae_search_device_batch(alae_workspace *ws, const uint8_t *d_query_codes, const size_t *lens, size_t k,
                                      const alae_scoring *scoring, int32_t H, const alae_search_opts *opts,
                                      void *stream, size_t *hit_count) {
@@ -1858,14 +1919,80 @@ alae_status alae_search_device_batch(alae_workspace *ws, const uint8_t *d_query_
         seg.push_back((uint64_t)lens[i]);
         m += lens[i];
     }
+    // groups of consecutive queries of at most `budget` columns share one traversal: the
+    // frontier of a traversal grows with the columns it serves
+    const uint64_t budget = (opts && opts->batch_columns) ? opts->batch_columns : kBatchColumns;
+    std::vector<uint64_t> gfirst;  // first query of every group
+    {
+        uint64_t cols = 0;
+        for (uint64_t i = 0; i < k; ++i) {
+            if (i == 0 || (cols > 0 && cols + seg[i] > budget)) {
+                gfirst.push_back(i);
+                cols = 0;
+            }
+            cols += seg[i];
+        }
+        gfirst.push_back(k);
+    }
     HIP_TRY(hipSetDevice(ws->device));
     hipStream_t s = (hipStream_t)stream;
     HIP_TRY(hipEventRecord(ws->ev0, s));
     uint64_t cnt = 0;
-    alae_status st = run_search(ws, d_query_codes, m, seg.data(), (uint64_t)k, scoring, H, opts, s, &cnt);
-    if (st != ALAE_OK) return st;
-    if (k == 1) {  // a batch of one is a plain search
-        ws->h_off.assign({0, cnt});
+    alae_status st;
+    const size_t ngroups = gfirst.size() - 1;
+    if (ngroups == 1) {
+        st = run_search(ws, d_query_codes, m, seg.data(), (uint64_t)k, scoring, H, opts, s, &cnt);
+        if (st != ALAE_OK) return st;
+        if (k == 1) {  // a batch of one is a plain search
+            ws->h_off.assign({0, cnt});
+        }
+    } else {
+        // every group's result is appended to the accumulated result, in query order
+        alae_stats total;
+        memset(&total, 0, sizeof(total));
+        alae_stats one;
+        if (opts && opts->trace) {
+            set_error("alae_search_device_batch: a trace needs the batch in one traversal (raise batch_columns)");
+            return ALAE_E_ARG;
+        }
+        alae_search_opts o = opts ? *opts : alae_search_opts{};
+        if (!opts) {
+            o.use_domination = o.use_score_filter = o.use_qprefix = 1;
+        }
+        o.stats = &one;
+        std::vector<uint64_t> off;
+        off.reserve(k + 1);
+        uint64_t col0 = 0;
+        for (size_t g = 0; g < ngroups; ++g) {
+            const uint64_t q0 = gfirst[g], q1 = gfirst[g + 1];
+            uint64_t mg = 0;
+            for (uint64_t i = q0; i < q1; ++i) mg += seg[i];
+            memset(&one, 0, sizeof(one));
+            uint64_t cg = 0;
+            st = run_search(ws, d_query_codes + col0, mg, seg.data() + q0, q1 - q0, scoring, H, &o, s, &cg);
+            if (st != ALAE_OK) return st;
+            if (q1 - q0 == 1) ws->h_off.assign({0, cg});
+            if ((st = grow_pair(ws->acc_keys, ws->acc_scores, ws->acc_cap, cnt + cg, cnt, s)) != ALAE_OK) return st;
+            if (cg > 0) {
+                HIP_TRY(hipMemcpyAsync(ws->acc_keys + cnt, ws->res_keys, cg * sizeof(uint64_t),
+                                       hipMemcpyDeviceToDevice, s));
+                HIP_TRY(hipMemcpyAsync(ws->acc_scores + cnt, ws->res_scores, cg * sizeof(uint32_t),
+                                       hipMemcpyDeviceToDevice, s));
+            }
+            for (uint64_t i = 0; i < q1 - q0; ++i) off.push_back(cnt + ws->h_off[i]);
+            cnt += cg;
+            col0 += mg;
+            add_stats(total, one);
+        }
+        off.push_back(cnt);
+        HIP_TRY(hipStreamSynchronize(s));
+        std::swap(ws->res_keys, ws->acc_keys);
+        std::swap(ws->res_scores, ws->acc_scores);
+        std::swap(ws->res_cap, ws->acc_cap);
+        ws->res_count = cnt;
+        ws->h_off = off;
+        ws->nseg = k;
+        if (opts && opts->stats) *opts->stats = total;
     }
     HIP_TRY(hipEventRecord(ws->ev1, s));
     HIP_TRY(hipEventSynchronize(ws->ev1));

@@ -157,3 +157,36 @@ def test_batch_uneven_many_queries():
     res = alae.search_batch(idx, qs, 20)
     for i, (q, r) in enumerate(zip(qs, res)):
         assert_same(r, oracle_hits(T, q, (1, -3, -5, -2), 20), f"query {i} (m={q.shape[0]})")
+
+
+@pytest.mark.parametrize("columns", [1, 700, 2500])
+def test_batch_column_groups(columns):
+    """A batch split into traversals of at most `columns` query columns (a longer
+    query alone) gives, query by query, the one-traversal result and the oracle's;
+    the device result keeps query order and per-query offsets."""
+    import torch
+
+    T, qs = boundary_case(5, k=9)
+    idx = alae.Index.build(T, "dna")
+    sc = alae.make_scoring(1, -3, -5, -2)
+    H = 14
+    one = alae.search_batch(idx, qs, H, sc)
+    grouped = alae.search_batch(idx, qs, H, sc, batch_columns=columns)
+    for i, (q, a, b) in enumerate(zip(qs, one, grouped)):
+        assert_same(b, a, f"query {i}")
+        assert_same(b, oracle_hits(T, q, (1, -3, -5, -2), H), f"query {i} vs oracle")
+    ws = alae.Workspace(idx)
+    lens = [q.shape[0] for q in qs]
+    d = torch.from_numpy(np.concatenate(qs)).to("cuda")
+    st = alae.Stats()
+    cnt = ws.search_device_batch(d, lens, H, sc, stats=st, batch_columns=columns)
+    off = ws.batch_offsets()
+    assert off[0] == 0 and off[-1] == cnt and np.all(np.diff(off) >= 0)
+    keys, scores = ws.result_torch()
+    keys = keys.cpu().numpy().view(np.uint64)
+    for i in range(len(qs)):
+        kk = keys[off[i]:off[i + 1]]
+        np.testing.assert_array_equal((kk >> np.uint64(32)).astype(np.int64), one[i][0])
+        np.testing.assert_array_equal((kk & np.uint64(0xFFFFFFFF)).astype(np.int64), one[i][1])
+    assert st.hits == cnt
+    ws.free()
