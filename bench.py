@@ -1,11 +1,22 @@
 """Benchmark of the exact local-alignment search on one MI355X.
 
-    python bench.py [--steps K] [--warmup W] [--workload dna|small|protein] [--no-cpu]
+    python bench.py [--steps K] [--warmup W] [--no-cpu] [--no-extras]
 
-A step is one complete search of the workload's query against the resident
-index: seeding, every trie level, hit emission, sort and max-merge, with the
-sorted hit set left in device memory.  The query is already in HBM when the
-timed region starts.  Prints one JSON line.
+Headline workload (batched DNA): 256 queries with log-uniform lengths
+500-50,000, each with 20 planted mutated copies of its segments (200-2,000
+bases, 15% substitutions, 2% indels) in a 1e9-base i.i.d. text;
+<1,-3,-5,-2>, H=30.  A step is one batched search of all 256 queries against
+the resident index: seeding, every trie level, chains, hit emission, sort and
+max-merge, with every query's sorted hits left in device memory.  The queries
+are in HBM when the timed region starts; value = sum(m) * n / step time.
+
+Beside the headline the JSON line carries: the same step with the hits copied
+to pinned host memory (to_host), the looped single-query searches of the same
+256 queries (batched speedup), the roofline of the trie-expansion kernels at
+this size, the filtering ratio of Equation 5 (the same search under BWT-SW's
+zero-floor rule), the DNA long-query search (text 1e8, query 1e5) with its
+autotuner and learned-ordering legs, serving with Poisson arrivals on the 1e9
+index, and the CPU oracle timed on the host's cores.  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -13,6 +24,7 @@ import argparse
 import json
 import os
 import sys
+import threading
 import time
 
 import numpy as np
@@ -22,78 +34,46 @@ sys.path.insert(0, ROOT)
 
 METRIC = "effective m*n cell-updates/s + DP entries/s at exact hits; p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
+LEVEL_KERNEL = "k_level_tasks+k_expand_children"  # the trie-expansion step of one level (node phase, child phase)
+TRAFFIC_PROFILE = "trie_expansion_traffic_batched_dna.md"
+# Under BWT-SW's zero-floor rule the rows kept do not depend on H (no score or length filter
+# reads it), so its entry count is taken with a threshold no score reaches: without the
+# domination test every start inside a planted homolog re-emits that homolog's hit cells, and
+# those duplicate records would not fit the 32-bit record offsets at these sizes.
+NO_OUTPUT_H = 1 << 20
+ZERO_FLOOR_NOTE = ("entries under BWT-SW's zero-floor rule counted with hit output off (the rows it keeps do not "
+                   "depend on H); its time excludes emitting and merging hits, so the speedup is a lower bound")
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def workload(name: str):
-    from paper_1208_0274_amd import synth
-
-    if name == "dna":
-        w = synth.dna_long_query()
-        desc = ("DNA long query: text 1e8 i.i.d. ACGT + 1,000 planted mutated query segments "
-                "(200-2,000, 15% subs, 2% indels); query 1e5; <1,-3,-5,-2>; H=30")
-    elif name == "small":
-        w = synth.small_dna()
-        desc = "plain method, single query: text 1e5 i.i.d. ACGT; query 1e3; <1,-3,-5,-2>; H=18"
-    elif name == "protein":
-        w = synth.protein_standin()
-        desc = ("protein stand-in: text 5e7 uniform residues + 500 planted segments (50-500, 30% subs, "
-                "3% indels); query 5,000; <1,-3,-11,-1>; H=45")
-    else:
-        raise SystemExit(f"unknown workload {name}")
-    return w, desc
+def host_cores() -> int:
+    """Cores this process may run on (its CPU share), at most 16 (the share of one GPU)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
 
 
-def cpu_baseline(w, budget_s: float):
-    """The oracle as it stands, on a bounded slice of the same text.
-
-    The chunked oracle recomputes L_max text rows in front of every thread's
-    chunk (that overlap makes it exact), so the thread count is chosen to keep
-    that overlap at most half of each thread's rows; with too small a budget
-    the oracle runs on one thread without chunking."""
-    import oracle
-
-    T, P = w["text"], w["queries"][0]
-    m = P.shape[0]
-    cores = os.cpu_count() or 1
-    sub = oracle.scoring_table(w["sigma"], w["sa"], w["sb"])
-    lmax = oracle.lmax(m, int(sub.max()), w["sg"], w["ss"], w["H"])
-    # single-thread rate on a short slice
-    L = max(1000, int(1e8 // m))
+def timed(fn, sync):
+    sync()
     t0 = time.perf_counter()
-    oracle.sw_hits(T[:L], P, sub, w["sg"], w["ss"], w["H"], threads=1)
-    r1 = m * L / max(time.perf_counter() - t0, 1e-6)
-    rows_per_thread = r1 * budget_s / m
-    threads = min(cores, 64) if rows_per_thread >= 2 * lmax else 1
-    if threads > 1:
-        L2 = int(threads * (rows_per_thread - lmax))
-    else:
-        L2 = int(rows_per_thread)
-    L2 = max(L, min(T.shape[0], L2))
-    t0 = time.perf_counter()
-    oracle.sw_hits(T[:L2], P, sub, w["sg"], w["ss"], w["H"], threads=threads)
-    dt = time.perf_counter() - t0
-    return {"value": m * L2 / dt, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
-            "sample": f"full query (m={m}) against the first {L2} text characters in {dt:.1f} s "
-                      f"({threads} thread(s); L_max={lmax} rows recomputed in front of each chunk); "
-                      f"host has {cores} cores"}
-
-
-LEVEL_KERNEL = "k_level_tasks+k_expand_children"  # the trie-expansion step of one level (node phase, child phase)
+    out = fn()
+    sync()
+    return out, time.perf_counter() - t0
 
 
 def measured_traffic():
-    """HBM bytes per level of the trie-expansion kernels from the committed
-    rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE scaled by a
-    device-copy calibration), or None when the kernel sources or the host loop
-    that decides which levels run changed since it was taken."""
+    """HBM bytes per level of the trie-expansion kernels on the batched workload from the
+    committed rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE scaled by a device-copy
+    calibration), or None when the kernel sources or the host loop changed since."""
     import hashlib
     import re
 
-    path = os.path.join(ROOT, "profiles", "trie_expansion_traffic.md")
+    path = os.path.join(ROOT, "profiles", TRAFFIC_PROFILE)
     if not os.path.exists(path):
         return None
     text = open(path).read()
@@ -109,11 +89,158 @@ def measured_traffic():
     return int(m_b.group(1))
 
 
-def learned_scheduling(alae, ws, dq, H, sc, steps, plain_ms):
-    """Trace one search, train the work predictor on the GPU, then time the
-    search with the learned order + partition of the walkers' queues."""
-    import torch
+def roofline(stats_list):
+    level_ms = float(np.mean([s.level_lane_ms for s in stats_list]))
+    st = stats_list[-1]
+    launches = max(1, st.level_lane_launches)
+    alg = st.level_alg_bytes()
+    achieved = alg / (level_ms * 1e-3) / 1e9 if level_ms > 0 else 0.0
+    traffic = measured_traffic()
+    return {"kernel": LEVEL_KERNEL, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "traffic_GBps": (traffic / (level_ms / launches * 1e-3) / 1e9) if traffic else None,
+            "alg_bytes_per_launch": alg / launches, "avg_launch_ms": level_ms / launches,
+            "launches_per_step": int(st.level_lane_launches)}
 
+
+def kernels_ms(stats_list):
+    f = lambda k: float(np.mean([getattr(s, k) for s in stats_list]))  # noqa: E731
+    return {"level": f("level_ms"), "level_lane": f("level_lane_ms"), "chain_start": f("start_ms"),
+            "chain_lane_with_live_wave_pass": f("general_ms"), "chain_wave_leftover": f("wide_ms"),
+            "sort_merge": f("merge_ms")}
+
+
+def batched_leg(alae, torch, args):
+    """The headline: one batched search of 256 queries against the 1e9-base index."""
+    from paper_1208_0274_amd import synth
+
+    t0 = time.perf_counter()
+    w = synth.batched_dna()
+    T, qs, H = w["text"], w["queries"], int(w["H"])
+    n = int(T.shape[0])
+    lens = [int(q.shape[0]) for q in qs]
+    sum_m = int(sum(lens))
+    log(f"batched workload: n={n} queries={len(qs)} sum_m={sum_m} ({time.perf_counter() - t0:.1f} s)")
+    t0 = time.perf_counter()
+    idx = alae.Index.build(T, "dna")
+    build_s = time.perf_counter() - t0
+    log(f"index of 1e9 bases built on the GPU in {build_s:.1f} s")
+    sc = alae.make_scoring(w["sa"], w["sb"], w["sg"], w["ss"])
+    ws = alae.Workspace(idx)
+    cat = torch.from_numpy(np.concatenate(qs)).to("cuda")
+    sync = torch.cuda.synchronize
+    for i in range(args.warmup):
+        st = alae.Stats()
+        (cnt, dt) = timed(lambda: ws.search_device_batch(cat, lens, H, sc, stats=st), sync)
+        log(f"warmup {i}: {dt * 1e3:.1f} ms hits={cnt} entries={st.entries}")
+    times, stats = [], []
+    for i in range(args.steps):
+        st = alae.Stats()
+        (cnt, dt) = timed(lambda: ws.search_device_batch(cat, lens, H, sc, stats=st), sync)
+        times.append(dt)
+        stats.append(st)
+        log(f"step {i}: {dt * 1e3:.1f} ms hits={cnt}")
+    ms = float(np.mean(times) * 1e3)
+    st = stats[-1]
+    res = {"ms": ms, "times": times, "stats": stats, "hits": int(cnt), "sum_m": sum_m, "n": n, "H": H,
+           "index_build_s": build_s}
+    # the same step with the hits taken to pinned host memory
+    keys_h = torch.empty(cnt, dtype=torch.int64, pin_memory=True)
+    scores_h = torch.empty(cnt, dtype=torch.int32, pin_memory=True)
+    host_times = []
+    for i in range(min(3, args.steps)):
+        def step():
+            ws.search_device_batch(cat, lens, H, sc)
+            return ws.copy_result(keys_h, scores_h)
+
+        (c2, dt) = timed(step, sync)
+        host_times.append(dt)
+        log(f"to host {i}: {dt * 1e3:.1f} ms ({c2} hits, {c2 * 12 / 1e9:.2f} GB)")
+    hms = float(np.mean(host_times) * 1e3)
+    res["to_host"] = {"ms_per_step": hms, "value": sum_m * n / (hms * 1e-3), "hit_bytes": int(cnt) * 12,
+                      "note": "launch to sorted hits in pinned host memory (PCIe included)"}
+    del keys_h, scores_h
+    if not args.no_extras:
+        # the plain single-query form: the 256 searches one after another on the same workspace
+        dqs = [torch.from_numpy(np.ascontiguousarray(q)).to("cuda") for q in qs]
+        ws.search_device(dqs[0], H, sc)
+
+        def loop():
+            return sum(ws.search_device(d, H, sc) for d in dqs)
+
+        (tot, dt) = timed(loop, sync)
+        if tot != cnt:
+            raise SystemExit(f"single-query searches found {tot} hits, the batch {cnt}")
+        res["single_query_loop"] = {"ms": dt * 1e3, "speedup_batched": dt * 1e3 / ms}
+        log(f"single-query loop: {dt * 1e3:.1f} ms, batched speedup {dt * 1e3 / ms:.2f}")
+        # Equation 5 on a sample of the batch: the first 16 queries under ALAE's filters and
+        # under BWT-SW's zero-floor rule alone
+        k = 16
+        sub = cat[:sum(lens[:k])]
+        st_a, st_b = alae.Stats(), alae.Stats()
+        (ca, ta) = timed(lambda: ws.search_device_batch(sub, lens[:k], H, sc, stats=st_a), sync)
+        (cb, tb) = timed(lambda: ws.search_device_batch(sub, lens[:k], NO_OUTPUT_H, sc, stats=st_b,
+                                                        zero_floor_only=True), sync)
+        res["filtering"] = {"sample": f"the first {k} queries of the batch (sum m = {sum(lens[:k])}) on the 1e9 text",
+                            "entries_alae": int(st_a.entries), "entries_zero_floor_only": int(st_b.entries),
+                            "filtering_ratio": (st_b.entries - st_a.entries) / max(1, st_b.entries),
+                            "ms_alae": ta * 1e3, "ms_zero_floor_only_no_output": tb * 1e3, "speedup_at_least": tb / ta,
+                            "note": ZERO_FLOOR_NOTE}
+        log(f"filtering (batched sample): {res['filtering']}")
+        del dqs
+    ws.free()
+    res["idx"] = idx
+    res["T"] = T
+    res["queries"] = qs
+    return res
+
+
+def long_query_leg(alae, torch, args):
+    """DNA long query (text 1e8 + 1,000 planted segments, query 1e5, H=30): one search a step."""
+    from paper_1208_0274_amd import synth
+
+    w = synth.dna_long_query()
+    T, P, H = w["text"], w["queries"][0], int(w["H"])
+    idx = alae.Index.build(T, "dna")
+    sc = alae.make_scoring(w["sa"], w["sb"], w["sg"], w["ss"])
+    ws = alae.Workspace(idx)
+    dq = torch.from_numpy(P).to("cuda")
+    sync = torch.cuda.synchronize
+    for _ in range(2):
+        ws.search_device(dq, H, sc)
+    times, stats = [], []
+    for _ in range(max(3, args.steps // 2)):
+        st = alae.Stats()
+        (cnt, dt) = timed(lambda: ws.search_device(dq, H, sc, stats=st), sync)
+        times.append(dt)
+        stats.append(st)
+    ms = float(np.mean(times) * 1e3)
+    out = {"workload": "DNA long query: text 1e8 i.i.d. ACGT + 1,000 planted mutated query segments "
+                       "(200-2,000, 15% subs, 2% indels); query 1e5; <1,-3,-5,-2>; H=30",
+           "ms_per_search": ms, "cells_per_s": P.shape[0] * T.shape[0] / (ms * 1e-3), "hits": int(cnt),
+           "dp_entries_per_s": float(np.mean([s.entries / t for s, t in zip(stats, times)])),
+           "kernels_ms": kernels_ms(stats), "roofline_trie_expansion": roofline(stats)}
+    st_b = alae.Stats()
+    (cb, tb) = timed(lambda: ws.search_device(dq, NO_OUTPUT_H, sc, stats=st_b, zero_floor_only=True), sync)
+    out["filtering"] = {"entries_alae": int(stats[-1].entries), "entries_zero_floor_only": int(st_b.entries),
+                        "filtering_ratio": (st_b.entries - stats[-1].entries) / max(1, st_b.entries),
+                        "ms_alae": ms, "ms_zero_floor_only_no_output": tb * 1e3, "speedup_at_least": tb * 1e3 / ms,
+                        "note": ZERO_FLOOR_NOTE}
+    log(f"long query: {ms:.1f} ms; filtering {out['filtering']}")
+    if not args.no_extras:
+        shapes, rep = ws.autotune(dq, H, sc, reps=2)
+        tuned = [timed(lambda: ws.search_device(dq, H, sc, **shapes), sync)[1] for _ in range(3)]
+        out["autotune"] = {"shapes": shapes, "default_device_ms": rep["default_ms"], "best_device_ms": rep["best_ms"],
+                           "trials": len(rep["trials"]), "tuned_step_ms": float(np.mean(tuned) * 1e3)}
+        out["learned_scheduling"] = learned_scheduling(alae, torch, ws, dq, H, sc, ms)
+    ws.free()
+    idx.free()
+    return out
+
+
+def learned_scheduling(alae, torch, ws, dq, H, sc, plain_ms, reps=5):
+    """Trace one search, train the work predictor on the GPU, then time the search with the
+    learned order + partition of the walkers' queues."""
     t0 = time.perf_counter()
     tr = alae.Trace(1 << 23)
     ws.search_device(dq, H, sc, trace=tr)
@@ -134,16 +261,13 @@ def learned_scheduling(alae, ws, dq, H, sc, steps, plain_ms):
     rho = float(spearmanr(pred, y[perm[ntr:]]).correlation)
     out = {"trace_items": int(tr.count), "train_samples": int(len(sel)), "train_s": train_s, "train_loss": loss,
            "heldout_spearman": rho, "plain_ms": plain_ms}
+    sync = torch.cuda.synchronize
     for name, kw in (("order_ms", dict(order_model=net, order_queues=2)),
                      ("order_partition_ms", dict(order_model=net, order_queues=2, partition_threshold=9.0))):
         times = []
-        for _ in range(steps):
+        for _ in range(reps):
             st = alae.Stats()
-            torch.cuda.synchronize()
-            t2 = time.perf_counter()
-            ws.search_device(dq, H, sc, stats=st, **kw)
-            torch.cuda.synchronize()
-            times.append(time.perf_counter() - t2)
+            times.append(timed(lambda: ws.search_device(dq, H, sc, stats=st, **kw), sync)[1])
         out[name] = float(np.mean(times) * 1e3)
         out[name.replace("_ms", "_moved")] = int(st.partitioned)
     out["gain_order"] = plain_ms / out["order_ms"]
@@ -153,55 +277,10 @@ def learned_scheduling(alae, ws, dq, H, sc, steps, plain_ms):
     return out
 
 
-def batched_vs_single(alae, k=64, n=100_000_000):
-    """The batched workload's shape on a smaller text: k independent DNA queries
-    (log-uniform lengths 500-50,000), each with 20 planted mutated segments
-    (200-2,000, 15% substitutions, 2% indels) in an i.i.d. text of n bases.
-    One batched search against k single-query searches on one workspace."""
-    import torch
-
-    from paper_1208_0274_amd import synth
-
-    w = synth.batched_dna(n=n, k=k)
-    qs = w["queries"]
-    t0 = time.perf_counter()
-    idx = alae.Index.build(w["text"], "dna")
-    build_s = time.perf_counter() - t0
-    sc = alae.make_scoring(w["sa"], w["sb"], w["sg"], w["ss"])
-    ws = alae.Workspace(idx)
-    lens = [q.shape[0] for q in qs]
-    cat = torch.from_numpy(np.concatenate(qs)).to("cuda")
-    dqs = [torch.from_numpy(np.ascontiguousarray(q)).to("cuda") for q in qs]
-    ws.search_device_batch(cat, lens, w["H"], sc)  # warm-up
-    for d in dqs[:4]:
-        ws.search_device(d, w["H"], sc)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    nb = ws.search_device_batch(cat, lens, w["H"], sc)
-    torch.cuda.synchronize()
-    tb = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    ns = 0
-    for d in dqs:
-        ns += ws.search_device(d, w["H"], sc)
-    torch.cuda.synchronize()
-    tsing = time.perf_counter() - t0
-    ws.free()
-    idx.free()
-    if nb != ns:
-        raise SystemExit(f"batched hits {nb} != single-query hits {ns}")
-    return {"workload": f"{k} queries, log-uniform 500-50,000, 20 planted copies each, text {n:.0e}",
-            "queries": k, "sum_m": int(sum(lens)), "index_build_s": build_s, "batched_ms": tb * 1e3,
-            "single_ms": tsing * 1e3, "speedup": tsing / tb, "hits": int(nb),
-            "batched_cells_per_s": float(sum(lens)) * n / tb}
-
-
-def serving(alae, idx, T, rates=(10.0, 100.0, 1000.0), count=48):
-    """Poisson arrivals of queries with log-uniform lengths 100-100,000 (half
-    carrying a mutated 200-2,000 text segment) against the resident index;
-    per rate: completed requests per second and submit-to-completion p50/p99."""
-    import threading
-
+def serving(alae, idx, T, rates=(10.0, 30.0, 100.0, 300.0, 1000.0), count=200):
+    """Poisson arrivals of queries with log-uniform lengths 100-100,000 (half carrying a mutated
+    200-2,000 text segment) against the resident 1e9 index; per rate: completed requests per second
+    and submit-to-completion p50/p99 over `count` requests."""
     from paper_1208_0274_amd import synth
 
     sc = alae.make_scoring()
@@ -237,62 +316,59 @@ def serving(alae, idx, T, rates=(10.0, 100.0, 1000.0), count=48):
     return out
 
 
+def cpu_baseline(T, qs, budget_s: float):
+    """The oracle as it stands, on every core of this host's share, on a bounded sample of the
+    batched workload: the median-length query against the first rows of the text, cut into one
+    chunk per thread, each chunk recomputing L_max rows in front of it (exact by Theorem 1) and
+    at least 2 L_max rows long."""
+    import oracle
+
+    lens = np.array([q.shape[0] for q in qs])
+    P = qs[int(np.argsort(lens)[len(lens) // 2])]
+    m = int(P.shape[0])
+    cores = host_cores()
+    sub = oracle.scoring_table(4, 1, -3)
+    lmax = oracle.lmax(m, 1, -5, -2, 30)
+    L = 4 * lmax  # single-thread rate on a short slice
+    t0 = time.perf_counter()
+    oracle.sw_hits(T[:L], P, sub, -5, -2, 30, threads=1)
+    r1 = m * L / max(time.perf_counter() - t0, 1e-6)
+    rows_per_thread = max(2 * lmax, int(r1 * budget_s / m) - lmax)
+    rows = min(int(T.shape[0]), cores * rows_per_thread)
+    t0 = time.perf_counter()
+    _, cells = oracle.sw_hits(T[:rows], P, sub, -5, -2, 30, threads=cores, return_cells=True)
+    dt = time.perf_counter() - t0
+    return {"value": m * rows / dt, "unit": "cell-updates/s", "cores": cores, "kind": "oracle",
+            "per_core": m * rows / dt / cores, "wall_s": dt, "cells_computed": int(cells),
+            "sample": f"median-length query of the batch (m={m}) against the first {rows} text characters, "
+                      f"{cores} threads of {rows // cores} text rows each plus L_max={lmax} rows of overlap, "
+                      f"{dt:.1f} s; value counts the m x {rows} cells of the sample"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="dna")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-extras", action="store_true", help="skip the learned-scheduling and batching legs")
-    ap.add_argument("--cpu-seconds", type=float, default=30.0)
+    ap.add_argument("--no-extras", action="store_true", help="only the headline and its to-host timing")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: the search runs on a single GPU "
-              "(it would shard by text range, one index part per GPU)", file=sys.stderr)
+        print("bench.py measures one GPU; the search would shard by text range, one index part per GPU",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
 
     from paper_1208_0274_amd import alae
 
-    w, desc = workload(args.workload)
-    T, P = w["text"], w["queries"][0]
-    n, m, H = int(T.shape[0]), int(P.shape[0]), int(w["H"])
-    log(f"workload {w['name']}: n={n} m={m} H={H}")
-    t0 = time.perf_counter()
-    idx = alae.Index.build(T, w["alphabet"])
-    log(f"index built in {time.perf_counter() - t0:.1f} s")
-    sc = alae.make_scoring(w["sa"], w["sb"], w["sg"], w["ss"])
-    ws = alae.Workspace(idx)
-    dq = torch.from_numpy(P).to("cuda")
-    stream = torch.cuda.current_stream()
-    for i in range(args.warmup):
-        st = alae.Stats()
-        cnt = ws.search_device(dq, H, sc, stats=st, stream=stream)
-        log(f"warmup {i}: hits={cnt} entries={st.entries} levels={st.levels} {st.device_ms:.1f} ms")
-    torch.cuda.synchronize()
-    times, stats = [], []
-    for i in range(args.steps):
-        st = alae.Stats()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        cnt = ws.search_device(dq, H, sc, stats=st, stream=stream)
-        torch.cuda.synchronize()
-        times.append(time.perf_counter() - t0)
-        stats.append(st)
-        log(f"step {i}: {times[-1] * 1e3:.2f} ms hits={cnt}")
-    ms = float(np.mean(times) * 1e3)
-    st = stats[-1]
-    entries_per_s = float(np.mean([s.entries / t for s, t in zip(stats, times)]))
-    level_ms = float(np.mean([s.level_lane_ms for s in stats]))  # the two trie-expansion kernels of every level
-    launches = max(1, st.level_lane_launches)
-    alg_bytes = st.level_alg_bytes()
-    achieved = alg_bytes / (level_ms * 1e-3) / 1e9 if level_ms > 0 else 0.0
-    traffic = measured_traffic()  # HBM bytes per launch, rocprofv3 counters
+    b = batched_leg(alae, torch, args)
+    stats, times = b["stats"], b["times"]
+    ms = b["ms"]
     out = {
         "metric": METRIC,
-        "value": m * n / (ms * 1e-3),
+        "value": b["sum_m"] * b["n"] / (ms * 1e-3),
         "unit": "cell-updates/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -303,44 +379,33 @@ def main():
         "vs_baseline": None,
         "dtype": "int32",
         "data": "synthetic",
-        "config": {"workload": desc, "n": n, "m": m, "H": H},
-        "dp_entries_per_s": entries_per_s,
+        "config": {"workload": "batched DNA: 256 queries (log-uniform 500-50,000), 20 planted mutated segments of "
+                               "each (200-2,000, 15% subs, 2% indels) in a 1e9 i.i.d. ACGT text; <1,-3,-5,-2>; "
+                               "H=30", "n": b["n"], "queries": 256, "sum_m": b["sum_m"], "H": b["H"],
+                   "batch_columns": 1 << 19},
+        "dp_entries_per_s": float(np.mean([s.entries / t for s, t in zip(stats, times)])),
         "p50_ms": float(np.percentile(times, 50) * 1e3),
         "p99_ms": float(np.percentile(times, 99) * 1e3),
-        "hits": int(cnt),
-        "kernels_ms": {"level": float(np.mean([s.level_ms for s in stats])), "level_lane": level_ms,
-                       "chain_start": float(np.mean([s.start_ms for s in stats])),
-                       "chain_lane_with_live_wave_pass": float(np.mean([s.general_ms for s in stats])),
-                       "chain_wave_leftover": float(np.mean([s.wide_ms for s in stats])),
-                       "sort_merge": float(np.mean([s.merge_ms for s in stats]))},
-        "search_stats": {k: (float(v) if isinstance(v, float) else int(v)) for k, v in st.as_dict().items()},
-        "roofline": {"kernel": LEVEL_KERNEL, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "traffic_GBps": (traffic / (level_ms / launches * 1e-3) / 1e9) if traffic else None,
-                     "alg_bytes_per_launch": alg_bytes / launches, "avg_launch_ms": level_ms / launches,
-                     "launches_per_step": int(st.level_lane_launches)},
+        "hits": b["hits"],
+        "to_host": b["to_host"],
+        "index_build_s": b["index_build_s"],
+        "kernels_ms": kernels_ms(stats),
+        "search_stats": {k: (float(v) if isinstance(v, float) else int(v)) for k, v in stats[-1].as_dict().items()},
+        "roofline": roofline(stats),
     }
+    for k in ("single_query_loop", "filtering"):
+        if k in b:
+            out[k] = b[k]
     if not args.no_extras:
-        log("autotuner: launch shapes")
-        shapes, rep = ws.autotune(dq, H, sc, reps=2)
-        tuned = []
-        for _ in range(args.steps):
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            ws.search_device(dq, H, sc, **shapes)
-            torch.cuda.synchronize()
-            tuned.append(time.perf_counter() - t0)
-        out["autotune"] = {"shapes": shapes, "default_device_ms": rep["default_ms"], "best_device_ms": rep["best_ms"],
-                           "trials": len(rep["trials"]), "tuned_step_ms": float(np.mean(tuned) * 1e3)}
-        log("learned scheduling: trace, train, timed searches")
-        out["learned_scheduling"] = learned_scheduling(alae, ws, dq, H, sc, args.steps, ms)
-        log("serving: Poisson arrivals")
-        out["serving"] = serving(alae, idx, T)
-        log("batched search against single-query searches")
-        out["batched"] = batched_vs_single(alae)
+        log("serving: Poisson arrivals on the 1e9 index")
+        out["serving"] = serving(alae, b["idx"], b["T"])
+    b["idx"].free()
+    if not args.no_extras:
+        log("DNA long query")
+        out["dna_long_query"] = long_query_leg(alae, torch, args)
     if not args.no_cpu:
         log("timing the CPU oracle on a bounded sample")
-        out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(b["T"], b["queries"], args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 

@@ -339,8 +339,9 @@ alae_status alae_search_device_batch(alae_workspace *ws, const uint8_t *d_query_
 alae_status alae_workspace_batch_offsets(const alae_workspace *ws, size_t *offsets, size_t k);
 alae_status alae_workspace_result(const alae_workspace *ws, const uint64_t **d_keys, const int32_t **d_scores,
                                   size_t *count);
-/* Copy the workspace result into caller-owned device buffers of at least
- * `count` elements (asynchronous on `stream`, a hipStream_t or NULL). */
+/* Copy the workspace result into caller-owned buffers of at least `count`
+ * elements: device memory, or pinned host memory (hipHostMalloc) to take the
+ * hits off the GPU (asynchronous on `stream`, a hipStream_t or NULL). */
 alae_status alae_workspace_copy_result(const alae_workspace *ws, uint64_t *d_keys, int32_t *d_scores, void *stream);
 
 /* Put the index on its device now (otherwise the first search does).
@@ -385,12 +386,15 @@ alae_status alae_search_device_noalloc(const alae_index *index, const uint8_t *d
  * runs max_inflight slots (a workspace, a HIP stream and a worker thread
  * each) at once, so the kernels of different requests overlap on the device.
  * A request is admitted when a slot is free and the device-memory budget has
- * room for its estimated rows (64 rows of m 20-byte entries plus the
- * profile); requests are admitted in arrival order, and a slot takes the head
- * of the queue together with the requests right behind it that share its
- * scoring and threshold (up to max_batch requests and 2^20 query columns),
- * running them as one batched search.  Every request's result is exactly
- * what alae_search returns for it alone.
+ * room for its estimated rows (two trie levels of m columns with
+ * max(64, 2000 (n/1e9)^0.6) live 20-byte entries per column, n the text
+ * length, plus the profile); requests are admitted in arrival order, and a
+ * slot takes the head of the queue together with the requests right behind
+ * it that share its scoring and threshold (up to max_batch requests, 2^20
+ * query columns and a slot's share of the budget), running them as one
+ * batched search.  After a search that held more than half a slot's share
+ * the slot frees the buffers it grew.  Every request's result is exactly what
+ * alae_search returns for it alone.
  *   submit: copies the query; *req_id identifies it.  ALAE_E_ADMISSION if
  *           its estimate exceeds the whole budget (it could never run).
  *   poll:   ALAE_OK with the result (library-allocated, free with

@@ -480,6 +480,22 @@ class Workspace:
                    "alae_workspace_copy_result")
         return keys, scores
 
+    def copy_result(self, keys, scores, stream=None) -> int:
+        """Copy the sorted result into caller tensors (device, or pinned host memory) of at least the
+        result's size: keys int64 ((query_end << 32) | text_end), scores int32.  Asynchronous on
+        `stream`; returns the record count."""
+        k, s, n = _vp(), _vp(), ctypes.c_size_t()
+        _check(_lib.alae_workspace_result(self._h, ctypes.byref(k), ctypes.byref(s), ctypes.byref(n)),
+               "alae_workspace_result")
+        cnt = int(n.value)
+        if keys.numel() < cnt or scores.numel() < cnt:
+            raise ValueError(f"result of {cnt} records does not fit the buffers")
+        if cnt:
+            sptr = _vp(stream.cuda_stream) if stream is not None else None
+            _check(_lib.alae_workspace_copy_result(self._h, _vp(keys.data_ptr()), _vp(scores.data_ptr()), sptr),
+                   "alae_workspace_copy_result")
+        return cnt
+
     def free(self):
         if self._h:
             _lib.alae_workspace_free(self._h)

@@ -80,6 +80,8 @@ alae_status region_workspace_create(int device, uint8_t *region, uint64_t bytes,
 alae_status region_search(alae_workspace *ws, const alae_index *idx, const uint8_t *d_query, uint64_t m,
                           const alae_scoring *scoring, int32_t H, const alae_search_opts *opts, void *stream,
                           uint64_t *d_keys, int32_t *d_scores, uint64_t capacity, uint64_t *hit_count);
+// Free the buffers a workspace has grown (they grow again on the next search).
+void workspace_trim(alae_workspace *ws);
 // True when HIP device `device` exists.
 bool device_present(int device);
 // Build the suffix array, BWT, occ blocks and C of `idx` (text, n, sigma and

@@ -512,7 +512,26 @@ struct alae_workspace {
 
 namespace alae {
 
+static void ws_release_buffers(alae_workspace *ws);
+
 static void ws_release(alae_workspace *ws) {
+    ws_release_buffers(ws);
+    hipFree(ws->d_cnt);
+    if (ws->h_cnt) hipHostFree(ws->h_cnt);
+    if (ws->s2) hipStreamDestroy(ws->s2);
+    if (ws->ev_fork) hipEventDestroy(ws->ev_fork);
+    if (ws->ev_join) hipEventDestroy(ws->ev_join);
+    if (ws->ev0) hipEventDestroy(ws->ev0);
+    if (ws->ev1) hipEventDestroy(ws->ev1);
+    if (ws->evk0) hipEventDestroy(ws->evk0);
+    if (ws->evk1) hipEventDestroy(ws->evk1);
+    if (ws->evkm) hipEventDestroy(ws->evkm);
+    if (ws->evks) hipEventDestroy(ws->evks);
+}
+
+// Free the buffers a workspace grew (frontier, queues, hits, sort, result);
+// its counters, stream and events stay.  The next search grows them again.
+static void ws_release_buffers(alae_workspace *ws) {
     hipSetDevice(ws->device);
     for (int i = 0; i < 2; ++i) {
         hipFree(ws->nodes[i]);
@@ -566,21 +585,30 @@ static void ws_release(alae_workspace *ws) {
     hipFree(ws->ready);
     hipFree(ws->missed);
     hipFree(ws->left);
-    if (ws->s2) hipStreamDestroy(ws->s2);
-    if (ws->ev_fork) hipEventDestroy(ws->ev_fork);
-    if (ws->ev_join) hipEventDestroy(ws->ev_join);
     hipFree(ws->tasks);
     hipFree(ws->qord);
     hipFree(ws->segbeg);
     hipFree(ws->d_off);
-    hipFree(ws->d_cnt);
-    if (ws->h_cnt) hipHostFree(ws->h_cnt);
-    if (ws->ev0) hipEventDestroy(ws->ev0);
-    if (ws->ev1) hipEventDestroy(ws->ev1);
-    if (ws->evk0) hipEventDestroy(ws->evk0);
-    if (ws->evk1) hipEventDestroy(ws->evk1);
-    if (ws->evkm) hipEventDestroy(ws->evkm);
-    if (ws->evks) hipEventDestroy(ws->evks);
+    alae_workspace fresh;
+    fresh.idx = ws->idx;
+    fresh.device = ws->device;
+    fresh.d_cnt = ws->d_cnt;
+    fresh.h_cnt = ws->h_cnt;
+    fresh.ev0 = ws->ev0;
+    fresh.ev1 = ws->ev1;
+    fresh.evk0 = ws->evk0;
+    fresh.evk1 = ws->evk1;
+    fresh.evkm = ws->evkm;
+    fresh.evks = ws->evks;
+    fresh.ev_fork = ws->ev_fork;
+    fresh.ev_join = ws->ev_join;
+    fresh.s2 = ws->s2;
+    fresh.region = ws->region;
+    *ws = fresh;
+}
+
+void workspace_trim(alae_workspace *ws) {
+    if (ws && !ws->region.base) ws_release_buffers(ws);
 }
 
 struct Scheme {
@@ -2038,8 +2066,8 @@ alae_status alae_workspace_copy_result(const alae_workspace *ws, uint64_t *d_key
     }
     if (ws->res_count == 0) return ALAE_OK;
     hipStream_t s = (hipStream_t)stream;
-    HIP_TRY(hipMemcpyAsync(d_keys, ws->res_keys, ws->res_count * sizeof(uint64_t), hipMemcpyDeviceToDevice, s));
-    HIP_TRY(hipMemcpyAsync(d_scores, ws->res_scores, ws->res_count * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipMemcpyAsync(d_keys, ws->res_keys, ws->res_count * sizeof(uint64_t), hipMemcpyDefault, s));
+    HIP_TRY(hipMemcpyAsync(d_scores, ws->res_scores, ws->res_count * sizeof(int32_t), hipMemcpyDefault, s));
     return ALAE_OK;
 }
 

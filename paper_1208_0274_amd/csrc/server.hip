@@ -10,6 +10,8 @@
 // Each request retires as soon as its own batch is done.
 #include <hip/hip_runtime.h>
 
+#include <cmath>
+
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
@@ -49,9 +51,13 @@ struct Request {
 };
 
 // Device bytes a request's search is expected to hold at its widest level:
-// about 64 live rows of m entries of 20 bytes, the profile and the query.
-uint64_t row_memory_estimate(uint64_t m, int sigma) {
-    return 64ull * m * 20ull + (uint64_t)sigma * m + 16ull * m;
+// two frontier levels of 20-byte entries, with about max(64, 2000 (n/1e9)^0.6)
+// live entries per query column at the widest one (the frontier of a trie
+// level grows with the text roughly as the entry count of Section 6 does;
+// 2000 is what i.i.d. DNA of 1e9 bases shows), the profile and the query.
+uint64_t row_memory_estimate(uint64_t m, int sigma, uint64_t n) {
+    const double per_col = std::max(64.0, 2000.0 * std::pow((double)n / 1e9, 0.6));
+    return (uint64_t)((double)m * 40.0 * per_col) + (uint64_t)sigma * m + 16ull * m;
 }
 
 bool same_scheme(const Request &a, const Request &b) {
@@ -187,8 +193,10 @@ static void worker_loop(alae_server *srv, size_t si) {
             uint64_t cols = 0;
             while (!srv->queue.empty() && (int)batch.size() < srv->max_batch) {
                 auto &r = srv->queue.front();
+                // a batch holds at most a slot's share of the budget (the head request alone may hold more)
                 if (!batch.empty() && (!same_scheme(*batch[0], *r) || cols + r->codes.size() > kBatchColumns ||
-                                       srv->reserved_bytes + need + r->need > srv->budget))
+                                       srv->reserved_bytes + need + r->need > srv->budget ||
+                                       need + r->need > srv->budget / srv->slots.size()))
                     break;
                 cols += r->codes.size();
                 need += r->need;
@@ -200,6 +208,9 @@ static void worker_loop(alae_server *srv, size_t si) {
             srv->batched += batch.size();
         }
         run_batch(srv, slot, batch);
+        // a slot's workspace keeps what its largest search grew; after a search that held
+        // more than half a slot's share, give that memory back
+        if (need > srv->budget / (2 * srv->slots.size())) workspace_trim(slot.ws);
         {
             std::lock_guard<std::mutex> lk(srv->mu);
             const auto now = Clock::now();
@@ -297,7 +308,7 @@ alae_status alae_server_submit(alae_server *srv, const char *query, size_t m, co
     }
     req->scoring.matrix = nullptr;
     req->H = H;
-    req->need = row_memory_estimate(m, srv->idx->sigma);
+    req->need = row_memory_estimate(m, srv->idx->sigma, srv->idx->n);
     req->t_submit = Clock::now();
     std::lock_guard<std::mutex> lk(srv->mu);
     if (req->need > srv->budget) {
