@@ -211,10 +211,11 @@ typedef struct {
     uint64_t n;                /* text length                                    */
     int32_t sigma;             /* 4 (DNA) or 20 (protein)                        */
     int32_t alphabet;          /* alae_alphabet                                  */
-    uint64_t C[21];            /* C[c] = 1 + #(text chars < c); C[sigma] = n + 1  */
+    uint64_t C[21];            /* C[c] = 1 + separators + #(text chars < c); C[sigma] = n + 1 */
     uint64_t dollar_row;       /* BWT row holding the terminator                 */
     uint64_t host_bytes;       /* bytes held on the host                         */
     uint64_t device_bytes;     /* bytes held on the device (0 until uploaded)    */
+    uint64_t records;          /* records of the text (1 unless built from records) */
 } alae_index_info;
 
 /*
@@ -224,7 +225,7 @@ typedef struct {
  * BWT row, the 0-based text position where that occurrence ends (Section 5,
  * search (2): the start is the stored end minus |X| plus one); row 0 is the
  * terminator.  The index lives on the host until a search first needs it on
- * the device.  Errors: ALAE_E_ARG (null, n == 0), ALAE_E_ALPHABET,
+ * the device (the GPU builder leaves it there at once).  Errors: ALAE_E_ARG (null, n == 0), ALAE_E_ALPHABET,
  * ALAE_E_TOO_LONG (n >= 2^31 - 1), ALAE_E_NOMEM.
  */
 alae_status alae_index_build(const char *text, size_t n, alae_alphabet alphabet, const alae_index_opts *opts,
@@ -233,6 +234,24 @@ alae_status alae_index_build(const char *text, size_t n, alae_alphabet alphabet,
 /* Same, from already encoded characters (codes 0..sigma-1). */
 alae_status alae_index_build_codes(const uint8_t *codes, size_t n, alae_alphabet alphabet,
                                    const alae_index_opts *opts, alae_index **out);
+
+/*
+ * A database of k records (Section 2.2 concatenates the sequences of a
+ * database into one text): the records' codes lie end to end in `codes`
+ * (lens[r] > 0 codes each) and the library joins them with a separator that
+ * no alignment crosses, so every hit lies inside one record and is exactly
+ * what a search of that record alone reports.  Text positions (hit text ends,
+ * alae_index_range, the suffix array) count the separators: record r starts
+ * at sum(lens[0..r-1]) + r.  The separator sorts after the terminator and
+ * before every character; the occ blocks hold one byte per BWT character.
+ * Errors as alae_index_build_codes, and ALAE_E_ARG for an empty record.
+ */
+alae_status alae_index_build_records(const uint8_t *codes, const size_t *lens, size_t k, alae_alphabet alphabet,
+                                     const alae_index_opts *opts, alae_index **out);
+
+/* The record holding text position text_pos and the offset inside it.
+ * ALAE_E_ARG for a separator or a position past the text. */
+alae_status alae_index_record_of(const alae_index *index, uint64_t text_pos, uint64_t *record, uint64_t *offset);
 
 /* Write / read a versioned binary image of the index.  Errors: ALAE_E_IO, ALAE_E_NOMEM. */
 alae_status alae_index_save(const alae_index *index, const char *path);

@@ -121,7 +121,7 @@ class IndexOpts(ctypes.Structure):
 class IndexInfo(ctypes.Structure):
     _fields_ = [("n", ctypes.c_uint64), ("sigma", ctypes.c_int32), ("alphabet", ctypes.c_int32),
                 ("C", ctypes.c_uint64 * 21), ("dollar_row", ctypes.c_uint64), ("host_bytes", ctypes.c_uint64),
-                ("device_bytes", ctypes.c_uint64)]
+                ("device_bytes", ctypes.c_uint64), ("records", ctypes.c_uint64)]
 
 
 _vp = ctypes.c_void_p
@@ -194,6 +194,9 @@ _sig("alae_mlp_train", _st, _vp, _fp, _fp, ctypes.c_size_t, ctypes.c_uint32, cty
 _sig("alae_workspace_result", _st, _vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(ctypes.c_size_t))
 _sig("alae_workspace_copy_result", _st, _vp, _vp, _vp, _vp)
 _sig("alae_index_upload", _st, _vp)
+_sig("alae_index_build_records", _st, _u8p, ctypes.POINTER(ctypes.c_size_t), ctypes.c_size_t, ctypes.c_int,
+     ctypes.POINTER(IndexOpts), ctypes.POINTER(_vp))
+_sig("alae_index_record_of", _st, _vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64))
 _sig("alae_search_device_noalloc", _st, _vp, _vp, ctypes.c_size_t, ctypes.POINTER(Scoring), ctypes.c_int32,
      ctypes.POINTER(SearchOpts), _vp, _vp, _vp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t))
 
@@ -288,6 +291,26 @@ class Index:
         return cls(h.value, a)
 
     @classmethod
+    def build_records(cls, records, alphabet="dna", device: int = 0, builder: str = "auto"):
+        """A database of records (uint8 code arrays), joined by a separator no alignment crosses;
+        text positions count the separators (record r starts at sum of earlier lengths + r)."""
+        a = _alpha(alphabet)
+        arr = np.ascontiguousarray(np.concatenate([np.asarray(r, dtype=np.uint8) for r in records]))
+        lens = (ctypes.c_size_t * len(records))(*[int(len(r)) for r in records])
+        opts = IndexOpts(device, cls.BUILDERS[builder])
+        h = _vp()
+        _check(_lib.alae_index_build_records(arr.ctypes.data_as(_u8p), lens, len(records), a, ctypes.byref(opts),
+                                             ctypes.byref(h)), "alae_index_build_records")
+        return cls(h.value, a)
+
+    def record_of(self, text_pos: int) -> tuple[int, int]:
+        """(record, offset inside it) of a text position."""
+        r, o = ctypes.c_uint64(), ctypes.c_uint64()
+        _check(_lib.alae_index_record_of(self._h, int(text_pos), ctypes.byref(r), ctypes.byref(o)),
+               "alae_index_record_of")
+        return int(r.value), int(o.value)
+
+    @classmethod
     def load(cls, path: str, device: int = 0):
         opts = IndexOpts(device, 0)
         h = _vp()
@@ -303,7 +326,8 @@ class Index:
         inf = IndexInfo()
         _check(_lib.alae_index_get_info(self._h, ctypes.byref(inf)), "alae_index_get_info")
         return {"n": inf.n, "sigma": inf.sigma, "alphabet": inf.alphabet, "C": list(inf.C)[:inf.sigma + 1],
-                "dollar_row": inf.dollar_row, "host_bytes": inf.host_bytes, "device_bytes": inf.device_bytes}
+                "dollar_row": inf.dollar_row, "host_bytes": inf.host_bytes, "device_bytes": inf.device_bytes,
+                "records": inf.records}
 
     def sa_end(self) -> np.ndarray:
         n = self.info()["n"]

@@ -32,6 +32,10 @@ struct GenOccBlock {
 static_assert(sizeof(GenOccBlock) == 128, "protein occ block must be 128 bytes");
 
 constexpr uint32_t kNoPos = 0xFFFFFFFFu;
+// Code of the record separator in the text of a multi-record index (Section
+// 2.2 concatenates the database's sequences into one text; the separator keeps
+// every alignment inside one record).  Never a character of a query.
+constexpr uint8_t kSepCode = 0xFE;
 
 void set_error(const char *fmt, ...);
 int alphabet_sigma(int alphabet);
@@ -51,6 +55,12 @@ struct alae_index {
     uint64_t nblocks = 0;
     uint64_t C[21] = {0};
     uint64_t dollar_row = 0;
+    // multi-record texts: separators (kSepCode) between records, record starts
+    uint64_t nsep = 0;
+    std::vector<uint64_t> rec_start;
+    // occ blocks: packed DNA (2-bit, DnaOccBlock) or one byte a character (GenOccBlock,
+    // protein and every text with separators)
+    bool occ_packed = true;
 
     // Device copy, created on first use.
     mutable std::mutex mu;

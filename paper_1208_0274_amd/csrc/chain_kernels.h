@@ -410,6 +410,7 @@ __global__ void __launch_bounds__(kStartBlock, 4) k_chain_start(SearchArgs a, Su
                 tpos = 0;
             }
             const uint32_t c = (uint32_t)(tw >> (8 * tpos)) & 0xFFu;
+            if (c >= (uint32_t)a.sigma) break;  // a record separator: the record ends here
             const int32_t rowgain = a.smax * (a.lmax - d1);
             uint32_t nalive = 0;
             bool fgoe = false;
@@ -560,7 +561,8 @@ __global__ void __launch_bounds__(256) k_chain_general(SearchArgs a, const Node 
         uint32_t nlen = 0;
         if (active) {
             const int32_t d1 = depth + 1;
-            if (d1 > a.lmax || (uint64_t)e_end + 1 >= a.n) {
+            // the chain ends at the text's end and at a record separator
+            if (d1 > a.lmax || (uint64_t)e_end + 1 >= a.n || a.text[e_end + 1] >= (uint32_t)a.sigma) {
                 active = false;
             } else {
                 my_work += 1.f;
@@ -837,6 +839,7 @@ __device__ bool walk_wide(const SearchArgs &a, Row &cur, Row &nxt, uint32_t &len
         }
         const int c = __shfl(txt, tpos, 64);
         ++tpos;
+        if (c >= a.sigma) return true;  // a record separator: the record ends here
         WideOut o;
         o.emit_hits = true;
         o.cap = cap;
@@ -1134,7 +1137,10 @@ __global__ void k_item_features(SearchArgs a, const Node *items, uint32_t n, con
                 }
             } else {
                 for (uint32_t k = 1 + w0; k <= w0 + 32 && k <= avail; ++k)
-                    cnt32 += a.prof[(size_t)a.text[e + k] * a.m + best + k] > 0;
+                    {
+                    const uint32_t tc = a.text[e + k];  // a separator scores nothing
+                    cnt32 += tc < (uint32_t)a.sigma && a.prof[(size_t)tc * a.m + best + k] > 0;
+                }
             }
             if (w0 == 0)
                 near = cnt32;

@@ -71,6 +71,7 @@ struct SearchArgs {
     const uint32_t *segbeg;  // per query: first column
     const uint32_t *segend;  // per query: one past its last column
     uint32_t C[21];
+    int32_t occ_packed;      // occ blocks are packed DNA (else one byte a character)
 };
 
 // Query segments (batched search).  Single-query searches never read the arrays.

@@ -12,6 +12,7 @@
 //                             (Section 5, search (3)); '$' when SA[h] = 0.
 // C[c] = 1 + #(text characters < c).  Backward search appends a character c
 // to the right of X:  [l, r] -> [C[c] + occ(c, l-1), C[c] + occ(c, r) - 1].
+#include <algorithm>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -161,7 +162,7 @@ bool encode(const char *s, size_t len, int alphabet, uint8_t *out) {
 
 uint64_t host_occ(const alae_index *idx, int c, int64_t i) {
     if (i < 0) return 0;
-    if (idx->sigma == 4) {
+    if (idx->occ_packed) {
         const DnaOccBlock *b = reinterpret_cast<const DnaOccBlock *>(idx->occ.data()) + i / kDnaBlockChars;
         int off = (int)(i % kDnaBlockChars);
         uint64_t cnt = b->cnt[c];
@@ -187,7 +188,7 @@ static alae_status build_from_codes(std::unique_ptr<alae_index> &idx) {
     const uint8_t *t = idx->text.data();
     const int64_t N = (int64_t)n + 1;
 
-    // S = reversed text + terminator; symbols shifted by one so that '$' = 0.
+    // S = reversed text + terminator: '$' = 0, a record separator 1, characters 2..sigma+1.
     std::vector<uint8_t> S;
     std::vector<int32_t> SA;
     try {
@@ -197,18 +198,25 @@ static alae_status build_from_codes(std::unique_ptr<alae_index> &idx) {
         set_error("out of host memory building the suffix array (n=%llu)", (unsigned long long)n);
         return ALAE_E_NOMEM;
     }
-    for (uint64_t k = 0; k < n; ++k) S[k] = (uint8_t)(t[n - 1 - k] + 1);
+    for (uint64_t k = 0; k < n; ++k) {
+        const uint8_t x = t[n - 1 - k];
+        S[k] = x == kSepCode ? 1 : (uint8_t)(x + 2);
+    }
     S[n] = 0;
-    induced_sort<uint8_t>(S.data(), SA.data(), (int32_t)N, sigma + 1);
+    induced_sort<uint8_t>(S.data(), SA.data(), (int32_t)N, sigma + 2);
 
+    // C[c] = 1 + separators + characters below c (the rows of '$' and of the
+    // separators come first)
     uint64_t counts[21] = {0};
-    for (uint64_t i = 0; i < n; ++i) counts[t[i]]++;
-    uint64_t acc = 1;
+    for (uint64_t i = 0; i < n; ++i)
+        if (t[i] != kSepCode) counts[t[i]]++;
+    uint64_t acc = 1 + idx->nsep;
     for (int c = 0; c < sigma; ++c) {
         idx->C[c] = acc;
         acc += counts[c];
     }
     idx->C[sigma] = acc;
+    idx->occ_packed = sigma == 4 && idx->nsep == 0;
 
     idx->sa_end.resize(N);
     std::vector<uint8_t> bwt(N);
@@ -219,7 +227,7 @@ static alae_status build_from_codes(std::unique_ptr<alae_index> &idx) {
             bwt[h] = 0xFF;
             idx->dollar_row = (uint64_t)h;
         } else {
-            bwt[h] = (uint8_t)(S[p - 1] - 1);
+            bwt[h] = S[p - 1] == 1 ? kSepCode : (uint8_t)(S[p - 1] - 2);
         }
     }
     SA.clear();
@@ -227,7 +235,7 @@ static alae_status build_from_codes(std::unique_ptr<alae_index> &idx) {
     S.clear();
     S.shrink_to_fit();
 
-    if (sigma == 4) {
+    if (idx->occ_packed) {
         idx->nblocks = (uint64_t)(N + kDnaBlockChars - 1) / kDnaBlockChars;
         idx->occ.assign(idx->nblocks * sizeof(DnaOccBlock), 0);
         DnaOccBlock *blk = reinterpret_cast<DnaOccBlock *>(idx->occ.data());
@@ -254,7 +262,7 @@ static alae_status build_from_codes(std::unique_ptr<alae_index> &idx) {
                 uint64_t h = b * kGenBlockChars + k;
                 uint8_t c = (h < (uint64_t)N) ? bwt[h] : 0xFF;
                 blk[b].ch[k] = c;
-                if (h < (uint64_t)N && c != 0xFF) run[c]++;
+                if (h < (uint64_t)N && c < 20) run[c]++;
             }
         }
     }
@@ -270,6 +278,39 @@ extern "C" {
 const char *alae_last_error(void) { return alae::last_error_text(); }
 
 const char *alae_version(void) { return "alae-mi355x 0.1 (gfx950)"; }
+
+}  // extern "C"
+
+namespace alae {
+
+// The index of idx->text (codes, separators included; n, sigma, alphabet, nsep
+// and rec_start set) by the builder the options pick.
+static alae_status build_index(std::unique_ptr<alae_index> &idx, const alae_index_opts *opts, alae_index **out) {
+    const uint64_t n = idx->n;
+    idx->device = opts ? opts->device : 0;
+    // builder: 1 = host, 2 = GPU, 0 = the GPU for texts of 2^22 characters or more when one is present
+    const int builder = opts ? opts->builder : 0;
+    if (builder < 0 || builder > 2) {
+        set_error("alae_index_build: builder must be 0, 1 or 2 (got %d)", builder);
+        return ALAE_E_ARG;
+    }
+    const bool on_gpu = builder == 2 || (builder == 0 && n >= (1ull << 22) && device_present(idx->device));
+    idx->occ_packed = idx->sigma == 4 && idx->nsep == 0;
+    alae_status st;
+    try {
+        st = on_gpu ? build_index_on_device(idx.get()) : build_from_codes(idx);
+    } catch (const std::bad_alloc &) {
+        set_error("alae_index_build: out of host memory");
+        return ALAE_E_NOMEM;
+    }
+    if (st != ALAE_OK) return st;
+    *out = idx.release();
+    return ALAE_OK;
+}
+
+}  // namespace alae
+
+extern "C" {
 
 alae_status alae_index_build_codes(const uint8_t *codes, size_t n, alae_alphabet alphabet,
                                    const alae_index_opts *opts, alae_index **out) {
@@ -296,6 +337,7 @@ alae_status alae_index_build_codes(const uint8_t *codes, size_t n, alae_alphabet
     try {
         idx.reset(new alae_index());
         idx->text.assign(codes, codes + n);
+        idx->rec_start.assign(1, 0);
     } catch (const std::bad_alloc &) {
         set_error("alae_index_build: out of host memory");
         return ALAE_E_NOMEM;
@@ -303,23 +345,79 @@ alae_status alae_index_build_codes(const uint8_t *codes, size_t n, alae_alphabet
     idx->n = n;
     idx->sigma = sigma;
     idx->alphabet = alphabet;
-    idx->device = opts ? opts->device : 0;
-    // builder: 1 = host, 2 = GPU, 0 = the GPU for texts of 2^22 characters or more when one is present
-    const int builder = opts ? opts->builder : 0;
-    if (builder < 0 || builder > 2) {
-        set_error("alae_index_build: builder must be 0, 1 or 2 (got %d)", builder);
+    return build_index(idx, opts, out);
+}
+
+alae_status alae_index_build_records(const uint8_t *codes, const size_t *lens, size_t k, alae_alphabet alphabet,
+                                     const alae_index_opts *opts, alae_index **out) {
+    if (!codes || !lens || !out || k == 0) {
+        set_error("alae_index_build_records: null argument or no record");
         return ALAE_E_ARG;
     }
-    const bool on_gpu = builder == 2 || (builder == 0 && n >= (1ull << 22) && device_present(idx->device));
-    alae_status st;
+    const int sigma = alphabet_sigma(alphabet);
+    if (!sigma) {
+        set_error("alae_index_build_records: unknown alphabet %d", (int)alphabet);
+        return ALAE_E_ARG;
+    }
+    uint64_t total = 0;
+    for (size_t r = 0; r < k; ++r) {
+        if (lens[r] == 0) {
+            set_error("alae_index_build_records: record %zu is empty", r);
+            return ALAE_E_ARG;
+        }
+        total += lens[r];
+    }
+    const uint64_t n = total + (k - 1);
+    if (n >= 0x7FFFFFFEull) {
+        set_error("alae_index_build_records: %llu characters with separators exceed the 32-bit suffix array",
+                  (unsigned long long)n);
+        return ALAE_E_TOO_LONG;
+    }
+    for (uint64_t i = 0; i < total; ++i) {
+        if (codes[i] >= sigma) {
+            set_error("alae_index_build_records: code %u at %llu outside the alphabet", codes[i],
+                      (unsigned long long)i);
+            return ALAE_E_ALPHABET;
+        }
+    }
+    std::unique_ptr<alae_index> idx;
     try {
-        st = on_gpu ? build_index_on_device(idx.get()) : build_from_codes(idx);
+        idx.reset(new alae_index());
+        idx->text.resize(n);
+        idx->rec_start.resize(k);
     } catch (const std::bad_alloc &) {
-        set_error("alae_index_build: out of host memory");
+        set_error("alae_index_build_records: out of host memory");
         return ALAE_E_NOMEM;
     }
-    if (st != ALAE_OK) return st;
-    *out = idx.release();
+    uint64_t at = 0, src = 0;
+    for (size_t r = 0; r < k; ++r) {
+        if (r > 0) idx->text[at++] = kSepCode;
+        idx->rec_start[r] = at;
+        memcpy(idx->text.data() + at, codes + src, lens[r]);
+        at += lens[r];
+        src += lens[r];
+    }
+    idx->n = n;
+    idx->sigma = sigma;
+    idx->alphabet = alphabet;
+    idx->nsep = k - 1;
+    return build_index(idx, opts, out);
+}
+
+alae_status alae_index_record_of(const alae_index *index, uint64_t text_pos, uint64_t *record, uint64_t *offset) {
+    if (!index || !record || !offset) {
+        set_error("alae_index_record_of: null argument");
+        return ALAE_E_ARG;
+    }
+    if (text_pos >= index->n || index->text[text_pos] == kSepCode) {
+        set_error("alae_index_record_of: position %llu is not a character of a record",
+                  (unsigned long long)text_pos);
+        return ALAE_E_ARG;
+    }
+    const auto &rs = index->rec_start;
+    const size_t r = (size_t)(std::upper_bound(rs.begin(), rs.end(), text_pos) - rs.begin()) - 1;
+    *record = r;
+    *offset = text_pos - rs[r];
     return ALAE_OK;
 }
 
@@ -364,6 +462,7 @@ alae_status alae_index_get_info(const alae_index *index, alae_index_info *out) {
     out->alphabet = index->alphabet;
     for (int c = 0; c <= index->sigma; ++c) out->C[c] = index->C[c];
     out->dollar_row = index->dollar_row;
+    out->records = index->rec_start.size();
     out->host_bytes = index->text.size() + index->sa_end.size() * 4 + index->occ.size();
     out->device_bytes = index->on_device ? out->host_bytes : 0;
     return ALAE_OK;
@@ -389,7 +488,7 @@ alae_status alae_index_copy_bwt(const alae_index *index, uint8_t *bwt) {
             bwt[h] = 0xFF;
             continue;
         }
-        if (index->sigma == 4) {
+        if (index->occ_packed) {
             const DnaOccBlock *b = reinterpret_cast<const DnaOccBlock *>(index->occ.data()) + h / kDnaBlockChars;
             int k = (int)(h % kDnaBlockChars);
             bwt[h] = (uint8_t)((b->bits[k / 16] >> (2 * (k % 16))) & 3);
@@ -427,7 +526,7 @@ alae_status alae_index_range(const alae_index *index, const uint8_t *pattern, si
 }
 
 // ---- persistence -----------------------------------------------------------
-static const char kMagic[8] = {'A', 'L', 'A', 'E', 'I', 'D', 'X', '1'};
+static const char kMagic[8] = {'A', 'L', 'A', 'E', 'I', 'D', 'X', '2'};
 
 alae_status alae_index_save(const alae_index *index, const char *path) {
     if (!index || !path) {
@@ -439,11 +538,14 @@ alae_status alae_index_save(const alae_index *index, const char *path) {
         set_error("alae_index_save: cannot open %s", path);
         return ALAE_E_IO;
     }
-    uint64_t hdr[6] = {index->n, (uint64_t)index->sigma, (uint64_t)index->alphabet, index->nblocks,
-                       index->dollar_row, (uint64_t)index->occ.size()};
+    uint64_t hdr[9] = {index->n, (uint64_t)index->sigma, (uint64_t)index->alphabet, index->nblocks,
+                       index->dollar_row, (uint64_t)index->occ.size(), index->nsep,
+                       (uint64_t)index->rec_start.size(), (uint64_t)(index->occ_packed ? 1 : 0)};
     f.write(kMagic, 8);
     f.write(reinterpret_cast<const char *>(hdr), sizeof(hdr));
     f.write(reinterpret_cast<const char *>(index->C), sizeof(index->C));
+    f.write(reinterpret_cast<const char *>(index->rec_start.data()),
+            (std::streamsize)(index->rec_start.size() * sizeof(uint64_t)));
     f.write(reinterpret_cast<const char *>(index->text.data()), (std::streamsize)index->text.size());
     f.write(reinterpret_cast<const char *>(index->sa_end.data()), (std::streamsize)(index->sa_end.size() * 4));
     f.write(reinterpret_cast<const char *>(index->occ.data()), (std::streamsize)index->occ.size());
@@ -465,7 +567,7 @@ alae_status alae_index_load(const char *path, const alae_index_opts *opts, alae_
         return ALAE_E_IO;
     }
     char magic[8];
-    uint64_t hdr[6];
+    uint64_t hdr[9];
     f.read(magic, 8);
     f.read(reinterpret_cast<char *>(hdr), sizeof(hdr));
     if (!f || memcmp(magic, kMagic, 8) != 0) {
@@ -480,11 +582,16 @@ alae_status alae_index_load(const char *path, const alae_index_opts *opts, alae_
         idx->alphabet = (int)hdr[2];
         idx->nblocks = hdr[3];
         idx->dollar_row = hdr[4];
-        if (alphabet_sigma(idx->alphabet) != idx->sigma || idx->n == 0 || idx->n >= 0x7FFFFFFEull) {
+        idx->nsep = hdr[6];
+        idx->occ_packed = hdr[8] != 0;
+        if (alphabet_sigma(idx->alphabet) != idx->sigma || idx->n == 0 || idx->n >= 0x7FFFFFFEull ||
+            hdr[7] != idx->nsep + 1 || (idx->occ_packed && (idx->sigma != 4 || idx->nsep != 0))) {
             set_error("alae_index_load: corrupt header in %s", path);
             return ALAE_E_IO;
         }
         f.read(reinterpret_cast<char *>(idx->C), sizeof(idx->C));
+        idx->rec_start.resize(hdr[7]);
+        f.read(reinterpret_cast<char *>(idx->rec_start.data()), (std::streamsize)(hdr[7] * sizeof(uint64_t)));
         idx->text.resize(idx->n);
         idx->sa_end.resize(idx->n + 1);
         idx->occ.resize(hdr[5]);

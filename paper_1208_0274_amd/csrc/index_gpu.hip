@@ -43,14 +43,19 @@ constexpr uint32_t kTB = 256;
 inline uint32_t grid_for(uint64_t n) { return (uint32_t)((n + kTB - 1) / kTB); }
 
 // Round 0 keys: suffix i of S' (length N = n + 1) packed as `per` symbols of
-// `bits` bits, the first symbol highest.
+// `bits` bits, the first symbol highest: '$' (and past the end) 0, a record
+// separator 1, character c as c + 2.
 __global__ void k_sa_init(const uint8_t *text, uint64_t n, int bits, int per, uint64_t *keys, uint32_t *vals) {
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i > n) return;
     uint64_t key = 0;
     for (int k = 0; k < per; ++k) {
         const uint64_t p = i + (uint64_t)k;
-        const uint32_t sym = p < n ? (uint32_t)text[n - 1 - p] + 1u : 0u;
+        uint32_t sym = 0u;
+        if (p < n) {
+            const uint32_t x = text[n - 1 - p];
+            sym = x == kSepCode ? 1u : x + 2u;
+        }
         key = (key << bits) | sym;
     }
     keys[i] = key;
@@ -130,7 +135,7 @@ __global__ void k_rows(const uint32_t *sa, const uint8_t *text, uint64_t n, uint
     }
 }
 
-// Per occ block: count of every code (the terminator is not counted).
+// Per occ block: count of every code (the terminator and separators are not counted).
 // counts[c * nblocks + b].
 __global__ void k_block_counts(const uint8_t *bwt, uint64_t N, int per_block, int sigma, uint64_t nblocks,
                                uint32_t *counts) {
@@ -151,11 +156,11 @@ __global__ void k_block_counts(const uint8_t *bwt, uint64_t N, int per_block, in
 // Occ blocks: counts before the block (prefix[c * nblocks + b]), then the
 // block's characters (DNA: 2-bit codes, the terminator as 0; protein: bytes,
 // 0xFF for the terminator and for rows past the end).
-__global__ void k_write_blocks(const uint8_t *bwt, uint64_t N, int sigma, uint64_t nblocks, const uint32_t *prefix,
-                               uint8_t *occ) {
+__global__ void k_write_blocks(const uint8_t *bwt, uint64_t N, int sigma, bool packed, uint64_t nblocks,
+                               const uint32_t *prefix, uint8_t *occ) {
     const uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= nblocks) return;
-    if (sigma == 4) {
+    if (packed) {
         DnaOccBlock blk;
         for (int c = 0; c < 4; ++c) blk.cnt[c] = prefix[(uint64_t)c * nblocks + b];
         for (int w = 0; w < 12; ++w) blk.bits[w] = 0;
@@ -252,7 +257,8 @@ alae_status build_index_on_device(alae_index *idx) {
     GPU_TRY(hipMemsetAsync(text_alloc, 0, n + 2 * 64, s));
     GPU_TRY(hipMemcpyAsync(d_text, idx->text.data(), n, hipMemcpyHostToDevice, s));
 
-    const int bits = sigma == 4 ? 3 : 5;
+    const bool packed = idx->occ_packed;
+    const int bits = sigma == 4 ? 3 : 5;  // symbols 0 .. sigma + 1
     const int per = 63 / bits;
     const int B = std::max(1, bit_len(N));  // ranks are below N
     uint64_t *keys, *keys_alt;
@@ -356,9 +362,9 @@ alae_status build_index_on_device(alae_index *idx) {
     GPU_TRY(hipMemcpyAsync(&dollar_row, d_dollar, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
 
     // occ blocks: per-block counts, a scan per code, then the blocks
-    const int per_block = sigma == 4 ? kDnaBlockChars : kGenBlockChars;
+    const int per_block = packed ? kDnaBlockChars : kGenBlockChars;
     const uint64_t nblocks = (N + per_block - 1) / per_block;
-    const uint64_t occ_bytes = nblocks * (sigma == 4 ? sizeof(DnaOccBlock) : sizeof(GenOccBlock));
+    const uint64_t occ_bytes = nblocks * (packed ? sizeof(DnaOccBlock) : sizeof(GenOccBlock));
     uint32_t *counts = nullptr, *prefix = nullptr;
     GPU_TRY(b.get(&counts, (uint64_t)sigma * nblocks));
     GPU_TRY(b.get(&prefix, (uint64_t)sigma * nblocks));
@@ -375,7 +381,7 @@ alae_status build_index_on_device(alae_index *idx) {
     for (int c = 0; c < sigma; ++c)
         GPU_TRY(scan_exclusive_u32(counts + (uint64_t)c * nblocks, prefix + (uint64_t)c * nblocks, nblocks, scratch + 2,
                                    s));
-    k_write_blocks<<<grid_for(nblocks), kTB, 0, s>>>(bwt, N, sigma, nblocks, prefix, d_occ);
+    k_write_blocks<<<grid_for(nblocks), kTB, 0, s>>>(bwt, N, sigma, packed, nblocks, prefix, d_occ);
     GPU_TRY(hipGetLastError());
     // C from the code totals
     std::vector<uint32_t> last_pre(sigma), last_cnt(sigma);
@@ -396,7 +402,7 @@ alae_status build_index_on_device(alae_index *idx) {
     GPU_TRY(hipMemcpyAsync(idx->sa_end.data(), d_sa_end, N * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     GPU_TRY(hipMemcpyAsync(idx->occ.data(), d_occ, occ_bytes, hipMemcpyDeviceToHost, s));
     GPU_TRY(hipStreamSynchronize(s));
-    uint64_t acc = 1;
+    uint64_t acc = 1 + idx->nsep;  // the rows of '$' and of the separators come first
     for (int c = 0; c < sigma; ++c) {
         idx->C[c] = acc;
         acc += (uint64_t)last_pre[c] + last_cnt[c];

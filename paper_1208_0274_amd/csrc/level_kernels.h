@@ -70,7 +70,7 @@ __global__ void __launch_bounds__(kTaskBlock) k_level_tasks(SearchArgs a, const 
     if (active) {
         nd = nodes[t];
         nin = (uint32_t)(sizeof(Node) + nd.len * sizeof(Entry));
-        if (a.sigma == 4) {
+        if (a.occ_packed) {
             occ4_dna(a, (int64_t)nd.lo - 1, o_lo);
             occ4_dna(a, (int64_t)nd.hi, o_hi);
 #pragma unroll
@@ -97,7 +97,7 @@ __global__ void __launch_bounds__(kTaskBlock) k_level_tasks(SearchArgs a, const 
     unsigned long long bases[4];
     block_reserve<4, kTaskBlock / 64, 1>(s_res, ctr, wtot, cap, ovb, &cnt->overflow, bases);
     unsigned long long base = bases[0] + pre;
-    if (a.sigma == 4) {
+    if (a.occ_packed) {
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
             if (!(mask & (1u << c))) continue;
@@ -276,13 +276,13 @@ __global__ void __launch_bounds__(64) k_expand_level_wide(SearchArgs a, const No
     for (uint32_t item = blockIdx.x; item < nw; item += gridDim.x) {
         const Node nd = wnodes[item];
         uint32_t o1[4] = {0, 0, 0, 0}, o2[4] = {0, 0, 0, 0};
-        if (a.sigma == 4) {
+        if (a.occ_packed) {
             occ4_dna(a, (int64_t)nd.lo - 1, o1);
             occ4_dna(a, (int64_t)nd.hi, o2);
         }
         for (int c = 0; c < a.sigma; ++c) {
             int64_t l, r;
-            if (a.sigma == 4) {
+            if (a.occ_packed) {
                 l = (int64_t)a.C[c] + o1[c];
                 r = (int64_t)a.C[c] + o2[c] - 1;
             } else {

@@ -53,14 +53,17 @@ __device__ inline bool dominated_tw(const SearchArgs &a, const int8_t *sub, cons
     load_window32(a.query, y, qw);
     int32_t sum = 0;
     bool dom = false;
+    bool sep = false;  // an alignment never reaches across a record separator
 #pragma unroll
     for (int k = 1; k <= 32; ++k) {
         const int j = 32 - k;
         const uint32_t tc = (tw[j >> 2] >> (8 * (j & 3))) & 0xFFu;
         const uint32_t pc = (qw[j >> 2] >> (8 * (j & 3))) & 0xFFu;
-        const int32_t d = a.matrix_mode ? (int32_t)sub[tc * (uint32_t)a.sigma + pc]
-                                        : (tc == pc ? a.s_match : a.s_mismatch);
-        if (k <= reach) {
+        sep |= tc >= (uint32_t)a.sigma;
+        const uint32_t tcs = sep ? 0u : tc;  // a separator is never scored
+        const int32_t d = a.matrix_mode ? (int32_t)sub[tcs * (uint32_t)a.sigma + pc]
+                                        : (tcs == pc ? a.s_match : a.s_mismatch);
+        if (k <= reach && !sep) {
             sum += d;
             dom |= sum > 0;
         }
@@ -86,8 +89,15 @@ constexpr int kGapBand = 8;
 __device__ inline bool dominated_gapped(const SearchArgs &a, int64_t x, int64_t y) {
     constexpr int W = kGapBand, B = 2 * kGapBand + 1;
     const int64_t yl = y - (int64_t)seg_beg_of(a, (uint32_t)y);
-    const int R = (int)(x < kGapWindow ? x : kGapWindow);
+    int R = (int)(x < kGapWindow ? x : kGapWindow);
     const int C = (int)(yl < kGapWindow ? yl : kGapWindow);
+    // the window's text rows stop at a record separator (no alignment crosses one)
+    for (int i = 1; i <= R; ++i) {
+        if (a.text[x - i] >= (uint32_t)a.sigma) {
+            R = i - 1;
+            break;
+        }
+    }
     if (R == 0 || C == 0) return false;
     const int32_t open = a.sg + a.ss;
     const int off = C - R;           // column of band cell 0 in row i is i + off

@@ -198,7 +198,7 @@ __global__ void k_seed_keys(const uint8_t *q, uint32_t m, int sigma, int qeff, i
 
 __device__ inline void backward_step(const SearchArgs &a, int c, int64_t &l, int64_t &r) {
     uint32_t ol, orr;
-    if (a.sigma == 4) {
+    if (a.occ_packed) {
         uint32_t o1[4], o2[4];
         occ4_dna(a, l - 1, o1);
         occ4_dna(a, r, o2);
@@ -872,7 +872,9 @@ static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64
     a.use_domination = use_dom ? 1 : 0;
     a.u_closed = sch.matrix_mode ? 0 : 1;
     a.ngr_walk = getenv("ALAE_NO_NGR") ? 0 : 1;
-    a.use_reuse = (opts && opts->use_reuse && !multi) ? 1 : 0;
+    // reuse replays forks along text the copies share; it is kept to texts without separators
+    a.use_reuse = (opts && opts->use_reuse && !multi && idx->nsep == 0) ? 1 : 0;
+    a.occ_packed = idx->occ_packed ? 1 : 0;
     a.matrix_mode = sch.matrix_mode;
     a.s_match = sch.matrix_mode ? 0 : scoring->sa;
     a.s_mismatch = sch.matrix_mode ? 0 : scoring->sb;

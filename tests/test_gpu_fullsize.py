@@ -96,3 +96,65 @@ def test_protein_standin_full():
     np.testing.assert_array_equal(j, ej)
     np.testing.assert_array_equal(t, et)
     np.testing.assert_array_equal(s, es)
+
+
+def _device_digest_check(keys, scores, golden_rows, edges):
+    """Digest the device result per bin of text ends on the GPU and compare with the
+    oracle's stored digests."""
+    import torch
+
+    from hitdigest import record_hashes, record_hashes_torch, unsigned
+
+    # the GPU form of the hash agrees with the numpy form that wrote the golden file
+    rng = np.random.default_rng(1)
+    jj, tt, ss = (rng.integers(0, 1 << 20, 1000), rng.integers(0, 1 << 31, 1000), rng.integers(30, 1 << 20, 1000))
+    g1, _ = record_hashes_torch(*(torch.from_numpy(x.astype(np.int64)).cuda() for x in (jj, tt, ss)))
+    n1, _ = record_hashes(jj, tt, ss)
+    assert [unsigned(int(v)) for v in g1.cpu()] == [int(v) for v in n1]
+    j = keys >> 32
+    t = keys & 0xFFFFFFFF
+    h1, h2 = record_hashes_torch(j, t, scores.to(torch.int64))
+    e = torch.tensor(edges, dtype=torch.int64, device=keys.device)
+    b = torch.searchsorted(e, t, right=True) - 1
+    nb = len(edges) - 1
+    inside = (b >= 0) & (b < nb)
+    b = torch.where(inside, b, torch.full_like(b, nb))
+    cnt = torch.bincount(b, minlength=nb + 1).cpu().tolist()
+    s1 = torch.zeros(nb + 1, dtype=torch.int64, device=keys.device).index_add_(0, b, h1).cpu().tolist()
+    s2 = torch.zeros(nb + 1, dtype=torch.int64, device=keys.device).index_add_(0, b, h2).cpu().tolist()
+    bad = []
+    for k, row in enumerate(golden_rows):
+        got = (cnt[k], unsigned(s1[k]), unsigned(s2[k]))
+        if got != tuple(row[-3:]):
+            bad.append((row[0], row[1], got, tuple(row[-3:])))
+    return bad, cnt[nb]
+
+
+def test_dna_long_query_all_hits():
+    """Every hit of the DNA long query (2.1e8) against the oracle: digests of 1,000 bins of
+    100,000 text ends, written by tests/golden/make_digests.py from the oracle alone."""
+    import torch
+
+    from hitdigest import read_digest_file
+
+    rows = read_digest_file(os.path.join(os.path.dirname(__file__), "golden", "dna_long_query_digests.txt"))
+    rows = sorted({r[0]: r for r in rows}.values())
+    edges = [r[0] for r in rows] + [rows[-1][1]]
+    assert len(rows) == 1000 and edges[0] == 0 and edges[-1] == 100_000_000
+    assert all(rows[k][1] == rows[k + 1][0] for k in range(len(rows) - 1))
+    w = synth.dna_long_query()
+    T, P, H = w["text"], w["queries"][0], w["H"]
+    idx = alae.Index.build(T, w["alphabet"])
+    ws = alae.Workspace(idx)
+    dq = torch.from_numpy(P).to("cuda")
+    cnt = ws.search_device(dq, H, alae.make_scoring(w["sa"], w["sb"], w["sg"], w["ss"]))
+    keys, scores = ws.result_torch()
+    bad, outside = _device_digest_check(keys, scores, rows, edges)
+    total = sum(r[2] for r in rows)
+    print(f"DNA 1e8 x 1e5: {cnt} device hits, oracle {total}; {len(rows) - len(bad)}/{len(rows)} bins equal",
+          flush=True)
+    assert outside == 0
+    assert not bad, bad[:5]
+    assert cnt == total
+    ws.free()
+    idx.free()

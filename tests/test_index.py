@@ -149,3 +149,85 @@ def test_generator_shapes():
     assert len(a["plants"]) == 10 and a["text"].shape[0] == 100_000
     ends = sorted((st, st + ln) for st, ln, _ in a["plants"])
     assert all(ends[i][1] <= ends[i + 1][0] for i in range(len(ends) - 1))
+
+
+# ---- databases of several records (separator between records) ----------------
+
+def _records(seed, k, sigma, lo=1, hi=60):
+    rng = np.random.default_rng(seed)
+    return [rng.integers(0, sigma, int(rng.integers(lo, hi)), dtype=np.uint8) for _ in range(k)]
+
+
+def _naive_records_sa(recs):
+    """Suffix array of reverse(R0 # R1 # ...) + $ by direct sorting: '$' < '#' < characters."""
+    text = []
+    for r, rec in enumerate(recs):
+        if r:
+            text.append(-1)  # separator
+        text.extend(int(c) for c in rec)
+    n = len(text)
+    S = [(1 if x == -1 else x + 2) for x in reversed(text)] + [0]
+    sa = sorted(range(n + 1), key=lambda i: S[i:])
+    return text, sa
+
+
+@pytest.mark.parametrize("seed,k,sigma", [(1, 1, 4), (2, 5, 4), (3, 12, 4), (4, 7, 20), (5, 30, 4)])
+def test_records_index_against_naive_sort(seed, k, sigma):
+    recs = _records(seed, k, sigma)
+    idx = alae.Index.build_records(recs, "dna" if sigma == 4 else "protein", builder="host")
+    text, sa = _naive_records_sa(recs)
+    n = len(text)
+    assert idx.info()["n"] == n and idx.info()["records"] == k
+    expect = [NOPOS if p == n else n - 1 - p for p in sa]
+    assert idx.sa_end().tolist() == expect
+    # BWT: the character after each occurrence's end in the text (254: separator, 255: terminator)
+    bwt = idx.bwt().tolist()
+    for h, p in enumerate(sa):
+        e = n - 1 - p  # text end of row h (p == n: the terminator row's own suffix)
+        if p == 0:
+            assert bwt[h] == 255
+        else:
+            nxt = text[e + 1]
+            assert bwt[h] == (254 if nxt == -1 else nxt)
+
+
+@pytest.mark.parametrize("sigma", [4, 20])
+def test_records_ranges_count_occurrences_inside_records(sigma):
+    recs = _records(7, 9, sigma, lo=5, hi=80)
+    idx = alae.Index.build_records(recs, "dna" if sigma == 4 else "protein", builder="host")
+    rng = np.random.default_rng(8)
+    for _ in range(300):
+        L = int(rng.integers(1, 6))
+        r = recs[int(rng.integers(0, len(recs)))]
+        if r.shape[0] >= L and rng.random() < 0.7:
+            a = int(rng.integers(0, r.shape[0] - L + 1))
+            pat = r[a:a + L]
+        else:
+            pat = rng.integers(0, sigma, L, dtype=np.uint8)
+        want = sum(1 for rec in recs for a in range(rec.shape[0] - L + 1) if np.array_equal(rec[a:a + L], pat))
+        lo, hi = idx.range(pat)
+        assert hi + 1 - lo == want
+
+
+def test_records_positions_and_persistence():
+    recs = _records(9, 6, 4, lo=3, hi=20)
+    idx = alae.Index.build_records(recs, "dna", builder="host")
+    pos = 0
+    for r, rec in enumerate(recs):
+        for o in range(rec.shape[0]):
+            assert idx.record_of(pos + o) == (r, o)
+        pos += rec.shape[0]
+        if r + 1 < len(recs):
+            with pytest.raises(alae.AlaeError):
+                idx.record_of(pos)  # the separator
+            pos += 1
+    with pytest.raises(alae.AlaeError):
+        alae.Index.build_records([recs[0], np.zeros(0, np.uint8)], "dna")
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "rec.idx")
+        idx.save(path)
+        back = alae.Index.load(path)
+        assert back.info() == idx.info()
+        assert back.sa_end().tolist() == idx.sa_end().tolist()
+        assert back.bwt().tolist() == idx.bwt().tolist()
+        assert back.record_of(pos - 1) == idx.record_of(pos - 1)
