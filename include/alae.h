@@ -253,6 +253,28 @@ alae_status alae_index_build_records(const uint8_t *codes, const size_t *lens, s
  * ALAE_E_ARG for a separator or a position past the text. */
 alae_status alae_index_record_of(const alae_index *index, uint64_t text_pos, uint64_t *record, uint64_t *offset);
 
+/*
+ * Text-sharded index: the text is cut into shards of shard_len text ends,
+ * each indexed from `overlap` characters before its first end (one FM-index
+ * per shard, built as alae_index_build_codes builds one).  A search runs on
+ * every shard and keeps each shard's hits whose text end it owns; by
+ * Theorem 1 (Equation 1) this is exactly the whole text's hit set when the
+ * query's L_max is at most overlap + 1, which alae_sharded_search checks
+ * (ALAE_E_TOO_LONG otherwise).  Text ends are global (up to 2^36).  With
+ * max_resident > 0 at most that many shards keep their device copy between
+ * searches; the others stay in host memory and are uploaded for their turn
+ * and released after it.  The union of the shards' hits is sorted on the GPU.
+ * Errors as alae_index_build_codes and alae_search.
+ */
+typedef struct alae_sharded alae_sharded;
+alae_status alae_sharded_build(const uint8_t *codes, uint64_t n, alae_alphabet alphabet, uint64_t shard_len,
+                               uint64_t overlap, uint32_t max_resident, const alae_index_opts *opts,
+                               alae_sharded **out);
+void alae_sharded_free(alae_sharded *sharded);
+alae_status alae_sharded_search(const alae_sharded *sharded, const char *query, size_t m,
+                                const alae_scoring *scoring, int32_t H, const alae_search_opts *opts,
+                                alae_hits *out);
+
 /* Write / read a versioned binary image of the index.  Errors: ALAE_E_IO, ALAE_E_NOMEM. */
 alae_status alae_index_save(const alae_index *index, const char *path);
 alae_status alae_index_load(const char *path, const alae_index_opts *opts, alae_index **out);

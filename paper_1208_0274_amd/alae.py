@@ -194,6 +194,11 @@ _sig("alae_mlp_train", _st, _vp, _fp, _fp, ctypes.c_size_t, ctypes.c_uint32, cty
 _sig("alae_workspace_result", _st, _vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(ctypes.c_size_t))
 _sig("alae_workspace_copy_result", _st, _vp, _vp, _vp, _vp)
 _sig("alae_index_upload", _st, _vp)
+_sig("alae_sharded_build", _st, _u8p, ctypes.c_uint64, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32,
+     ctypes.POINTER(IndexOpts), ctypes.POINTER(_vp))
+_sig("alae_sharded_free", None, _vp)
+_sig("alae_sharded_search", _st, _vp, ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(Scoring), ctypes.c_int32,
+     ctypes.POINTER(SearchOpts), ctypes.POINTER(Hits))
 _sig("alae_index_build_records", _st, _u8p, ctypes.POINTER(ctypes.c_size_t), ctypes.c_size_t, ctypes.c_int,
      ctypes.POINTER(IndexOpts), ctypes.POINTER(_vp))
 _sig("alae_index_record_of", _st, _vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64))
@@ -430,6 +435,46 @@ def search_device_noalloc(index: Index, d_query, H: int, d_keys, d_scores, scori
                                            _vp(d_scores.data_ptr()), cap, ctypes.byref(cnt)),
            "alae_search_device_noalloc")
     return int(cnt.value)
+
+
+class ShardedIndex:
+    """A text cut into shards of `shard_len` text ends, each indexed from `overlap` characters
+    before its first end (exact for queries whose L_max is at most overlap + 1)."""
+
+    def __init__(self, text, alphabet="dna", shard_len=1 << 28, overlap=1 << 20, max_resident=0, device=0,
+                 builder="auto"):
+        a = _alpha(alphabet)
+        arr = np.ascontiguousarray(np.asarray(text, dtype=np.uint8))
+        opts = IndexOpts(device, Index.BUILDERS[builder])
+        self._h = _vp()
+        self.alphabet = a
+        _check(_lib.alae_sharded_build(arr.ctypes.data_as(_u8p), arr.shape[0], a, int(shard_len), int(overlap),
+                                       int(max_resident), ctypes.byref(opts), ctypes.byref(self._h)),
+               "alae_sharded_build")
+
+    def search(self, query, H: int, scoring: Scoring | None = None, stats: Stats | None = None, **opt):
+        """(query_end, text_end, score) int64 arrays sorted by (query_end, text_end), text ends global."""
+        sc = scoring if scoring is not None else make_scoring()
+        q = _query_bytes(query, self.alphabet)
+        opts = make_opts(stats=stats, **opt)
+        h = Hits()
+        _check(_lib.alae_sharded_search(self._h, q, len(q), ctypes.byref(sc), int(H), ctypes.byref(opts),
+                                        ctypes.byref(h)), "alae_sharded_search")
+        try:
+            return _hits_to_numpy(h)
+        finally:
+            _lib.alae_hits_free(ctypes.byref(h))
+
+    def free(self):
+        if self._h:
+            _lib.alae_sharded_free(self._h)
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
 
 
 class Workspace:
