@@ -491,6 +491,29 @@ alae_status alae_mlp_loss_grad(alae_mlp *net, const float *x, const float *t, si
 alae_status alae_mlp_train(alae_mlp *net, const float *x, const float *t, size_t n, uint32_t epochs,
                            uint32_t batch, float lr, uint64_t seed, double *final_loss);
 
+/*
+ * Threshold from an E-value (Section 7: H = ceil((ln(K m n) - ln E) / lambda),
+ * with E = K m n exp(-lambda S)).  alae_karlin_altschul computes lambda, K and
+ * the relative entropy H of ungapped local alignment scores (Karlin and
+ * Altschul 1990) for a scoring scheme and a residue background (sigma
+ * frequencies, normalised; NULL = uniform): lambda is the positive root of
+ * sum p_a p_b exp(lambda s(a,b)) = 1 and K comes from the series of Karlin and
+ * Altschul.  Gap scores are not used: for gapped scoring these are the
+ * ungapped statistics (BLAST's gapped tables are not part of this library),
+ * whose threshold is lower than a gapped one, so no hit a gapped threshold
+ * reports is lost.  ALAE_E_SCORING unless the expected pair score is negative
+ * and some pair score positive.  alae_evalue_threshold gives H (at least 1)
+ * for query length m, text length n and E-value evalue > 0.
+ */
+typedef struct {
+    double lambda;
+    double K;
+    double H;  /* relative entropy, nats per aligned pair */
+} alae_karlin;
+alae_status alae_karlin_altschul(const alae_scoring *scoring, alae_alphabet alphabet, const double *background,
+                                 alae_karlin *out);
+alae_status alae_evalue_threshold(const alae_karlin *stats, uint64_t m, uint64_t n, double evalue, int32_t *H);
+
 /* Message for the last failing call on this thread. */
 const char *alae_last_error(void);
 

@@ -194,6 +194,16 @@ _sig("alae_mlp_train", _st, _vp, _fp, _fp, ctypes.c_size_t, ctypes.c_uint32, cty
 _sig("alae_workspace_result", _st, _vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(ctypes.c_size_t))
 _sig("alae_workspace_copy_result", _st, _vp, _vp, _vp, _vp)
 _sig("alae_index_upload", _st, _vp)
+
+
+class Karlin(ctypes.Structure):
+    _fields_ = [("lambda_", ctypes.c_double), ("K", ctypes.c_double), ("H", ctypes.c_double)]
+
+
+_sig("alae_karlin_altschul", _st, ctypes.POINTER(Scoring), ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+     ctypes.POINTER(Karlin))
+_sig("alae_evalue_threshold", _st, ctypes.POINTER(Karlin), ctypes.c_uint64, ctypes.c_uint64, ctypes.c_double,
+     ctypes.POINTER(ctypes.c_int32))
 _sig("alae_sharded_build", _st, _u8p, ctypes.c_uint64, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32,
      ctypes.POINTER(IndexOpts), ctypes.POINTER(_vp))
 _sig("alae_sharded_free", None, _vp)
@@ -475,6 +485,27 @@ class ShardedIndex:
             self.free()
         except Exception:
             pass
+
+
+def karlin_altschul(scoring: Scoring | None = None, alphabet="dna", background=None) -> dict:
+    """Ungapped Karlin-Altschul lambda, K and relative entropy H of a scoring scheme."""
+    sc = scoring if scoring is not None else make_scoring()
+    bg = None
+    if background is not None:
+        arr = np.ascontiguousarray(np.asarray(background, dtype=np.float64))
+        bg = arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    k = Karlin()
+    _check(_lib.alae_karlin_altschul(ctypes.byref(sc), _alpha(alphabet), bg, ctypes.byref(k)), "alae_karlin_altschul")
+    return {"lambda": k.lambda_, "K": k.K, "H": k.H}
+
+
+def evalue_threshold(stats: dict, m: int, n: int, evalue: float) -> int:
+    """H = ceil((ln(K m n) - ln E) / lambda) (Section 7), at least 1."""
+    k = Karlin(stats["lambda"], stats["K"], stats["H"])
+    h = ctypes.c_int32()
+    _check(_lib.alae_evalue_threshold(ctypes.byref(k), int(m), int(n), float(evalue), ctypes.byref(h)),
+           "alae_evalue_threshold")
+    return int(h.value)
 
 
 class Workspace:
