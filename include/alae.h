@@ -492,6 +492,44 @@ alae_status alae_mlp_train(alae_mlp *net, const float *x, const float *t, size_t
                            uint32_t batch, float lr, uint64_t seed, double *final_loss);
 
 /*
+ * Alignment starts and transcripts of reported cells (the paper's A(i,j).pos,
+ * Section 2.1, Table 1; Algorithm 1 keeps the position with the maximum).
+ * For each cell k (query_ends[k], text_ends[k], scores[k]) -- typically
+ * records of a search result -- the optimal local alignment ending there is
+ * located: among the alignments scoring A(i,j) the one with the largest text
+ * start, then the largest query start (this makes .pos unique).  Its
+ * transcript lists one op per alignment column from the start: 'M' a text
+ * and a query character aligned, 'D' a text character against a gap, 'I' a
+ * query character against a gap; its score (substitutions plus sg + r*ss per
+ * maximal gap run) is A(i,j).  Runs on the index's GPU (one wave per cell).
+ *   out->aln[k].status: ALAE_OK; ALAE_E_ARG when the cell's score is not
+ *     A(i,j) (or the position is outside the text or query or a separator);
+ *     ALAE_E_TOO_LONG when the search window (2^30 cells) or the transcript's
+ *     matrices (2 GiB) would exceed the limits (the start is kept for the
+ *     latter, with no ops).
+ * Arrays are library-allocated; free with alae_alignments_free.  Errors of
+ * the whole call: ALAE_E_ARG, ALAE_E_ALPHABET, ALAE_E_SCORING, ALAE_E_DEVICE.
+ */
+typedef struct {
+    uint64_t text_start;   /* 0-based first text position of the alignment  */
+    uint32_t query_start;  /* 0-based first query position                  */
+    int32_t score;         /* A(i,j) as given                               */
+    uint64_t ops_offset;   /* first op of the transcript in alae_alignments.ops */
+    uint32_t ops_len;
+    int32_t status;
+} alae_alignment;
+typedef struct {
+    alae_alignment *aln;
+    size_t count;
+    char *ops;
+    uint64_t ops_count;
+} alae_alignments;
+alae_status alae_traceback(const alae_index *index, const char *query, size_t m, const alae_scoring *scoring,
+                           const uint32_t *query_ends, const uint64_t *text_ends, const int32_t *scores, size_t k,
+                           alae_alignments *out);
+void alae_alignments_free(alae_alignments *alignments);
+
+/*
  * Threshold from an E-value (Section 7: H = ceil((ln(K m n) - ln E) / lambda),
  * with E = K m n exp(-lambda S)).  alae_karlin_altschul computes lambda, K and
  * the relative entropy H of ungapped local alignment scores (Karlin and

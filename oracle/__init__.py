@@ -68,6 +68,9 @@ def _lib():
         lib.oracle_sw_matrix.restype = ctypes.c_int
         lib.oracle_lmax.argtypes = [ctypes.c_int64] * 5
         lib.oracle_lmax.restype = ctypes.c_int64
+        lib.oracle_global_suffix.argtypes = [u8p, ctypes.c_int64, u8p, ctypes.c_int64, i32p, ctypes.c_int32,
+                                             ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)]
+        lib.oracle_global_suffix.restype = ctypes.c_int
         lib.oracle_hits_free.argtypes = [ctypes.POINTER(_Hits)]
         lib.oracle_hits_free.restype = None
         _LIB = lib
@@ -134,6 +137,45 @@ def sw_hits(T, P, sub, sg: int, ss: int, H: int, t_lo: int = 0, t_hi: int | None
     if return_cells:
         return res, cells
     return res
+
+
+def global_suffix(T, P, sub, sg: int, ss: int) -> np.ndarray:
+    """G[a, b] = sim(T[-a:], P[-b:]) (the empty suffix for a or b = 0): the best global
+    alignment score of the last a text and last b query characters (Section 2.1)."""
+    lib = _lib()
+    T, Tp = _u8(T)
+    P, Pp = _u8(P)
+    sub = np.ascontiguousarray(sub, dtype=np.int32)
+    a, b = int(T.shape[0]), int(P.shape[0])
+    out = np.zeros((a + 1) * (b + 1), dtype=np.int64)
+    rc = lib.oracle_global_suffix(Tp, a, Pp, b, sub.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), int(sub.shape[0]),
+                                  int(sg), int(ss), out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
+    if rc != 0:
+        raise RuntimeError(f"oracle_global_suffix failed with code {rc}")
+    return out.reshape(a + 1, b + 1)
+
+
+def alignment_start(T, P, sub, sg: int, ss: int, t: int, j: int):
+    """The start (x, y) of the optimal local alignment ending at text end t and query end j
+    with the largest x, and among those the largest y (the paper's A(i,j).pos, one reading of
+    it made unique), and its score A(t, j).  Every alignment scoring A(t, j) >= 1 spans at
+    most L_max text characters (Equation 1 with the j + 1 query characters available), so
+    only that many text characters before t are looked at (with threshold 1, which bounds
+    every alignment of positive score).  Returns None when A(t, j) = 0."""
+    P = np.asarray(P)
+    T = np.asarray(T)
+    smax = int(np.max(sub))
+    L = lmax(j + 1, smax, sg, ss, 1)
+    lo = max(0, t - L + 1)
+    G = global_suffix(T[lo:t + 1], P[:j + 1], sub, sg, ss)
+    S = int(G.max())
+    if S <= 0:
+        return None
+    cand = np.argwhere(G == S)
+    cand = cand[(cand[:, 0] > 0) & (cand[:, 1] > 0)]
+    a = int(cand[:, 0].min())
+    b = int(cand[cand[:, 0] == a][:, 1].min())
+    return t - a + 1, j - b + 1, S
 
 
 def sw_matrix(T, P, sub, sg: int, ss: int) -> np.ndarray:

@@ -250,6 +250,46 @@ int oracle_sw_matrix(const uint8_t *T, int64_t n, const uint8_t *P, int64_t m,
     return 0;
 }
 
+/* G[a*(p_len+1) + b] = sim(T[t_len-a .. t_len-1], P[p_len-b .. p_len-1]): the best
+ * global alignment score of the last a text and last b query characters
+ * (Section 2.1: substitution scores, a maximal gap run of r characters costs
+ * sg + r*ss), for every a <= t_len, b <= p_len.  Textbook Gotoh over the
+ * reversed strings, with the state that ends in a text gap (E), a query gap
+ * (F) or an aligned pair. */
+int oracle_global_suffix(const uint8_t *T, int64_t t_len, const uint8_t *P, int64_t p_len, const int32_t *sub,
+                         int32_t sigma, int32_t sg, int32_t ss, int64_t *G) {
+    if (t_len < 0 || p_len < 0 || ss >= 0 || sg > 0) return -2;
+    const int64_t w = p_len + 1;
+    int64_t *E = (int64_t *)malloc((size_t)(t_len + 1) * (size_t)w * sizeof(int64_t));
+    int64_t *F = (int64_t *)malloc((size_t)(t_len + 1) * (size_t)w * sizeof(int64_t));
+    if (!E || !F) {
+        free(E);
+        free(F);
+        return -1;
+    }
+    for (int64_t a = 0; a <= t_len; a++) {
+        for (int64_t b = 0; b <= p_len; b++) {
+            const int64_t at = a * w + b;
+            if (a == 0 && b == 0) {
+                G[at] = 0;
+                E[at] = F[at] = ORACLE_NEG_INF;
+                continue;
+            }
+            int64_t e = ORACLE_NEG_INF, f = ORACLE_NEG_INF, m = ORACLE_NEG_INF;
+            if (a > 0) e = max2(E[at - w] + ss, G[at - w] + sg + ss);
+            if (b > 0) f = max2(F[at - 1] + ss, G[at - 1] + sg + ss);
+            if (a > 0 && b > 0)
+                m = G[at - w - 1] + sub[(size_t)T[t_len - a] * sigma + P[p_len - b]];
+            E[at] = e;
+            F[at] = f;
+            G[at] = max2(m, max2(e, f));
+        }
+    }
+    free(E);
+    free(F);
+    return 0;
+}
+
 void oracle_hits_free(oracle_hits *h) {
     free(h->qend);
     free(h->tend);

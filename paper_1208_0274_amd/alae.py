@@ -196,6 +196,22 @@ _sig("alae_workspace_copy_result", _st, _vp, _vp, _vp, _vp)
 _sig("alae_index_upload", _st, _vp)
 
 
+class Alignment(ctypes.Structure):
+    _fields_ = [("text_start", ctypes.c_uint64), ("query_start", ctypes.c_uint32), ("score", ctypes.c_int32),
+                ("ops_offset", ctypes.c_uint64), ("ops_len", ctypes.c_uint32), ("status", ctypes.c_int32)]
+
+
+class Alignments(ctypes.Structure):
+    _fields_ = [("aln", ctypes.POINTER(Alignment)), ("count", ctypes.c_size_t), ("ops", ctypes.POINTER(ctypes.c_char)),
+                ("ops_count", ctypes.c_uint64)]
+
+
+_sig("alae_traceback", _st, _vp, ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(Scoring),
+     ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_int32), ctypes.c_size_t,
+     ctypes.POINTER(Alignments))
+_sig("alae_alignments_free", None, ctypes.POINTER(Alignments))
+
+
 class Karlin(ctypes.Structure):
     _fields_ = [("lambda_", ctypes.c_double), ("K", ctypes.c_double), ("H", ctypes.c_double)]
 
@@ -485,6 +501,31 @@ class ShardedIndex:
             self.free()
         except Exception:
             pass
+
+
+def traceback(index: Index, query, query_ends, text_ends, scores, scoring: Scoring | None = None):
+    """Start and transcript of the optimal alignment (largest text start, then largest query
+    start) of each cell; returns a list of dicts (text_start, query_start, score, ops, status)."""
+    sc = scoring if scoring is not None else make_scoring()
+    q = _query_bytes(query, index.alphabet)
+    j = np.ascontiguousarray(np.asarray(query_ends, dtype=np.uint32))
+    t = np.ascontiguousarray(np.asarray(text_ends, dtype=np.uint64))
+    s = np.ascontiguousarray(np.asarray(scores, dtype=np.int32))
+    out = Alignments()
+    _check(_lib.alae_traceback(index._h, q, len(q), ctypes.byref(sc), j.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
+                               t.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                               s.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), j.shape[0], ctypes.byref(out)),
+           "alae_traceback")
+    try:
+        ops = ctypes.string_at(out.ops, out.ops_count).decode() if out.ops_count else ""
+        res = []
+        for k in range(out.count):
+            a = out.aln[k]
+            res.append({"text_start": int(a.text_start), "query_start": int(a.query_start), "score": int(a.score),
+                        "ops": ops[a.ops_offset:a.ops_offset + a.ops_len], "status": int(a.status)})
+        return res
+    finally:
+        _lib.alae_alignments_free(ctypes.byref(out))
 
 
 def karlin_altschul(scoring: Scoring | None = None, alphabet="dna", background=None) -> dict:

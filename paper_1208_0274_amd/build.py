@@ -17,7 +17,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libalae.so")
 
-SOURCES = ["index_build.cpp", "stats.cpp", "sort.hip", "search.hip", "server.hip", "mlp.hip", "noalloc.hip", "index_gpu.hip", "sharded.hip"]
+SOURCES = ["index_build.cpp", "stats.cpp", "sort.hip", "search.hip", "server.hip", "mlp.hip", "noalloc.hip", "index_gpu.hip", "sharded.hip", "traceback.hip"]
 ARCH = os.environ.get("ALAE_OFFLOAD_ARCH", "gfx950")
 
 
