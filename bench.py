@@ -285,7 +285,7 @@ def serving(alae, idx, T, rates=(10.0, 30.0, 100.0, 300.0, 1000.0), count=200):
 
     sc = alae.make_scoring()
     out = []
-    srv = alae.Server(idx, slots=4, max_batch=16)
+    srv = alae.Server(idx, max_batch=16)  # default slots: two on a text this large
     qs = synth.serving_queries(T, count)
     for rate in rates:
         arrivals = synth.poisson_arrivals(rate, count)

@@ -425,16 +425,18 @@ alae_status alae_search_device_noalloc(const alae_index *index, const uint8_t *d
 /*
  * Serving with continuous batching.  The server keeps the index resident and
  * runs max_inflight slots (a workspace, a HIP stream and a worker thread
- * each) at once, so the kernels of different requests overlap on the device.
+ * each; default 4, or 2 for texts of 2^28 characters or more, where one
+ * search already fills the GPU) at once, so the kernels of different
+ * requests overlap on the device.
  * A request is admitted when a slot is free and the device-memory budget has
  * room for its estimated rows (two trie levels of m columns with
  * max(64, 2000 (n/1e9)^0.6) live 20-byte entries per column, n the text
- * length, plus the profile); requests are admitted in arrival order, and a
+ * length, doubled for buffer growth, plus the profile); requests are admitted in arrival order, and a
  * slot takes the head of the queue together with the requests right behind
  * it that share its scoring and threshold (up to max_batch requests, 2^20
  * query columns and a slot's share of the budget), running them as one
- * batched search.  After a search that held more than half a slot's share
- * the slot frees the buffers it grew.  Every request's result is exactly what
+ * batched search.  After a search that held more than a slot's share (one
+ * request larger than that) the slot frees the buffers it grew.  Every request's result is exactly what
  * alae_search returns for it alone.
  *   submit: copies the query; *req_id identifies it.  ALAE_E_ADMISSION if
  *           its estimate exceeds the whole budget (it could never run).
@@ -449,7 +451,7 @@ alae_status alae_search_device_noalloc(const alae_index *index, const uint8_t *d
  */
 typedef struct {
     uint64_t memory_budget;    /* device bytes for in-flight rows, 0 = half the free memory */
-    int32_t max_inflight;      /* slots running at once (1..16), 0 = 4                      */
+    int32_t max_inflight;      /* slots running at once (1..16), 0 = 4 (2 for n >= 2^28)   */
     int32_t max_batch;         /* requests per batched search, 0 = 16                       */
 } alae_server_opts;
 

@@ -51,13 +51,15 @@ struct Request {
 };
 
 // Device bytes a request's search is expected to hold at its widest level:
-// two frontier levels of 20-byte entries, with about max(64, 2000 (n/1e9)^0.6)
+// two frontier levels of 20-byte entries (with the slack of buffers that grow
+// by doubling), with about max(64, 2000 (n/1e9)^0.6)
 // live entries per query column at the widest one (the frontier of a trie
 // level grows with the text roughly as the entry count of Section 6 does;
 // 2000 is what i.i.d. DNA of 1e9 bases shows), the profile and the query.
 uint64_t row_memory_estimate(uint64_t m, int sigma, uint64_t n) {
     const double per_col = std::max(64.0, 2000.0 * std::pow((double)n / 1e9, 0.6));
-    return (uint64_t)((double)m * 40.0 * per_col) + (uint64_t)sigma * m + 16ull * m;
+    // buffers grow by doubling: up to twice what the rows need
+    return (uint64_t)((double)m * 80.0 * per_col) + (uint64_t)sigma * m + 16ull * m;
 }
 
 bool same_scheme(const Request &a, const Request &b) {
@@ -208,9 +210,10 @@ static void worker_loop(alae_server *srv, size_t si) {
             srv->batched += batch.size();
         }
         run_batch(srv, slot, batch);
-        // a slot's workspace keeps what its largest search grew; after a search that held
-        // more than half a slot's share, give that memory back
-        if (need > srv->budget / (2 * srv->slots.size())) workspace_trim(slot.ws);
+        // a slot's workspace keeps what its largest search grew (freeing synchronises the
+        // device, which stalls the other slots); only a search beyond a slot's share of the
+        // budget (a single request larger than that) gives its memory back
+        if (need > srv->budget / srv->slots.size()) workspace_trim(slot.ws);
         {
             std::lock_guard<std::mutex> lk(srv->mu);
             const auto now = Clock::now();
@@ -258,7 +261,9 @@ alae_status alae_server_create(const alae_index *index, const alae_server_opts *
         return ALAE_E_NOMEM;
     }
     srv->idx = index;
-    const int nslots = (opts && opts->max_inflight > 0) ? std::min(opts->max_inflight, 16) : 4;
+    // a search over a large text fills the GPU by itself: two slots there, four otherwise
+    const int nslots = (opts && opts->max_inflight > 0) ? std::min(opts->max_inflight, 16)
+                                                          : (index->n >= (1ull << 28) ? 2 : 4);
     srv->max_batch = (opts && opts->max_batch > 0) ? opts->max_batch : 16;
     srv->slots.resize((size_t)nslots);
     for (auto &s : srv->slots) {
