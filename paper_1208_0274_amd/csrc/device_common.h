@@ -72,6 +72,7 @@ struct SearchArgs {
     const uint32_t *segend;  // per query: one past its last column
     uint32_t C[21];
     int32_t occ_packed;      // occ blocks are packed DNA (else one byte a character)
+    int32_t has_sep;         // the text holds record separators
 };
 
 // Query segments (batched search).  Single-query searches never read the arrays.

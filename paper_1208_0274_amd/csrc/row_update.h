@@ -49,21 +49,29 @@ __device__ inline bool dominated_tw(const SearchArgs &a, const int8_t *sub, cons
     const int64_t yl = y - (int64_t)seg_beg_of(a, (uint32_t)y);  // columns of y's query before y
     if (yl < reach) reach = yl;
     if (reach <= 0) return false;
+    if (a.has_sep) {  // an alignment never reaches across a record separator
+        for (int k = 1; k <= 32 && k <= reach; ++k) {
+            const int j = 32 - k;
+            if (((tw[j >> 2] >> (8 * (j & 3))) & 0xFFu) >= (uint32_t)a.sigma) {
+                reach = k - 1;
+                break;
+            }
+        }
+        if (reach <= 0) return false;
+    }
     uint32_t qw[8];
     load_window32(a.query, y, qw);
     int32_t sum = 0;
     bool dom = false;
-    bool sep = false;  // an alignment never reaches across a record separator
 #pragma unroll
     for (int k = 1; k <= 32; ++k) {
         const int j = 32 - k;
-        const uint32_t tc = (tw[j >> 2] >> (8 * (j & 3))) & 0xFFu;
+        uint32_t tc = (tw[j >> 2] >> (8 * (j & 3))) & 0xFFu;
         const uint32_t pc = (qw[j >> 2] >> (8 * (j & 3))) & 0xFFu;
-        sep |= tc >= (uint32_t)a.sigma;
-        const uint32_t tcs = sep ? 0u : tc;  // a separator is never scored
-        const int32_t d = a.matrix_mode ? (int32_t)sub[tcs * (uint32_t)a.sigma + pc]
-                                        : (tcs == pc ? a.s_match : a.s_mismatch);
-        if (k <= reach && !sep) {
+        if (a.matrix_mode && tc >= (uint32_t)a.sigma) tc = 0;  // past the reach; keeps the table index inside
+        const int32_t d = a.matrix_mode ? (int32_t)sub[tc * (uint32_t)a.sigma + pc]
+                                        : (tc == pc ? a.s_match : a.s_mismatch);
+        if (k <= reach) {
             sum += d;
             dom |= sum > 0;
         }
@@ -92,10 +100,12 @@ __device__ inline bool dominated_gapped(const SearchArgs &a, int64_t x, int64_t 
     int R = (int)(x < kGapWindow ? x : kGapWindow);
     const int C = (int)(yl < kGapWindow ? yl : kGapWindow);
     // the window's text rows stop at a record separator (no alignment crosses one)
-    for (int i = 1; i <= R; ++i) {
-        if (a.text[x - i] >= (uint32_t)a.sigma) {
-            R = i - 1;
-            break;
+    if (a.has_sep) {
+        for (int i = 1; i <= R; ++i) {
+            if (a.text[x - i] >= (uint32_t)a.sigma) {
+                R = i - 1;
+                break;
+            }
         }
     }
     if (R == 0 || C == 0) return false;

@@ -875,6 +875,7 @@ static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64
     // reuse replays forks along text the copies share; it is kept to texts without separators
     a.use_reuse = (opts && opts->use_reuse && !multi && idx->nsep == 0) ? 1 : 0;
     a.occ_packed = idx->occ_packed ? 1 : 0;
+    a.has_sep = idx->nsep > 0 ? 1 : 0;
     a.matrix_mode = sch.matrix_mode;
     a.s_match = sch.matrix_mode ? 0 : scoring->sa;
     a.s_mismatch = sch.matrix_mode ? 0 : scoring->sb;
@@ -1929,7 +1930,7 @@ static void add_stats(alae_stats &to, const alae_stats &x) {
     to.tail_depth = std::max(to.tail_depth, x.tail_depth);
 }
 
-constexpr uint64_t kBatchColumns = 1ull << 19;
+constexpr uint64_t kBatchColumns = 1ull << 18;
 
 }  // namespace alae
 
