@@ -514,23 +514,27 @@ __device__ inline void block_reserve(BlockReserveLds<NC, NW> &sh, unsigned long 
         for (int c = 0; c < NC; ++c) sh.tot[wave][c] = tot[c];
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned long long of = 0;
+    if (threadIdx.x < 64) {
+        // lane c of the first wave takes counter c, so the block's atomics are in flight
+        // together instead of one round trip after another
+        unsigned long long all = 0, b = 0;
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-            unsigned long long all = 0;
+            if ((int)threadIdx.x == c) {
 #pragma unroll
-            for (int w = 0; w < NW; ++w) all += sh.tot[w][c];
-            unsigned long long b = 0;
-            if (all && c < NRES) {
-                b = atomicAdd(ctr[c], all);
-                if (b + all > cap[c]) of |= ovbit[c];
-            } else if (all) {
-                __hip_atomic_fetch_add(ctr[c], all, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                for (int w = 0; w < NW; ++w) all += sh.tot[w][c];
+                if (all && c < NRES)
+                    b = atomicAdd(ctr[c], all);
+                else if (all)
+                    __hip_atomic_fetch_add(ctr[c], all, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
-            sh.base[c] = b;
         }
-        if (of) atomicOr(overflow, of);
+        uint32_t of = 0;
+#pragma unroll
+        for (int c = 0; c < NRES; ++c)
+            if ((int)threadIdx.x == c && all && b + all > cap[c]) of = ovbit[c];
+        if ((int)threadIdx.x < NC) sh.base[threadIdx.x] = b;
+        if (of) atomicOr(overflow, (unsigned long long)of);
     }
     __syncthreads();
 #pragma unroll
