@@ -110,6 +110,18 @@ def kernels_ms(stats_list):
             "sort_merge": f("merge_ms")}
 
 
+def wave_walkers(stats_list):
+    """The wave walkers' share: entries, rows stepped, the span of the pass that runs beside the
+    lane walker, and the longest single chain.  A chain's rows depend on each other, so its walk is
+    a serial chain of row steps; live_ms / max_rows bounds the time of one row step from above."""
+    st = stats_list[-1]
+    live = float(np.mean([s.live_ms for s in stats_list]))
+    return {"entries": int(st.wide_entries), "rows": int(st.wide_steps), "max_rows_one_chain": int(st.wide_max_steps),
+            "live_pass_ms": live, "entries_per_s": st.wide_entries / (live * 1e-3) if live > 0 else None,
+            "entries_per_row": st.wide_entries / max(1, st.wide_steps),
+            "us_per_row_step_bound": live * 1e3 / st.wide_max_steps if st.wide_max_steps else None}
+
+
 def batched_leg(alae, torch, args):
     """The headline: one batched search of 256 queries against the 1e9-base index."""
     from paper_1208_0274_amd import synth
@@ -219,7 +231,8 @@ def long_query_leg(alae, torch, args):
                        "(200-2,000, 15% subs, 2% indels); query 1e5; <1,-3,-5,-2>; H=30",
            "ms_per_search": ms, "cells_per_s": P.shape[0] * T.shape[0] / (ms * 1e-3), "hits": int(cnt),
            "dp_entries_per_s": float(np.mean([s.entries / t for s, t in zip(stats, times)])),
-           "kernels_ms": kernels_ms(stats), "roofline_trie_expansion": roofline(stats)}
+           "kernels_ms": kernels_ms(stats), "roofline_trie_expansion": roofline(stats),
+           "wave_walkers": wave_walkers(stats)}
     st_b = alae.Stats()
     (cb, tb) = timed(lambda: ws.search_device(dq, NO_OUTPUT_H, sc, stats=st_b, zero_floor_only=True), sync)
     out["filtering"] = {"entries_alae": int(stats[-1].entries), "entries_zero_floor_only": int(st_b.entries),
@@ -392,6 +405,7 @@ def main():
         "kernels_ms": kernels_ms(stats),
         "search_stats": {k: (float(v) if isinstance(v, float) else int(v)) for k, v in stats[-1].as_dict().items()},
         "roofline": roofline(stats),
+        "wave_walkers": wave_walkers(stats),
     }
     for k in ("single_query_loop", "filtering"):
         if k in b:

@@ -128,6 +128,10 @@ typedef struct {
     uint64_t level_lane_launches; /* levels that ran them                                  */
     uint64_t tail_chains;    /* chain items made from the frontier's tail (one per occurrence of a node) */
     uint64_t tail_depth;     /* depth at which the frontier's tail went to the chain walkers (0: never) */
+    /* the wave walkers (one wave, or the waves of one block, per chain) */
+    uint64_t wide_entries;   /* DP entries they computed (part of entries)                    */
+    uint64_t wide_max_steps; /* most rows walked for one chain item                            */
+    double live_ms;          /* span of the wave pass that runs beside the lane walker, first start to last end */
 } alae_stats;
 
 /*

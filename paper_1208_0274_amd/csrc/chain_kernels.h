@@ -420,7 +420,7 @@ __global__ void __launch_bounds__(kStartBlock, 4) k_chain_start(SearchArgs a, Su
                 const uint32_t ncol = col[s2] + 1;
                 const uint32_t pc = (uint32_t)(qw[s2] >> (8 * tpos)) & 0xFFu;
                 const int32_t v = M[s2] + score_of(a, sub, c, pc);
-                const bool ok = ((alive >> s2) & 1u) && ncol < send[s2] && keep_state(a, v, ncol, rowgain);
+                const bool ok = ((alive >> s2) & 1u) && ncol < send[s2] && keep_state_e(a, v, ncol, send[s2], rowgain);
                 nM[s2] = ok ? v : kNeg;
                 nalive |= ok ? (1u << s2) : 0u;
                 fgoe |= ok && v > -open;
@@ -885,6 +885,7 @@ __device__ inline void wide_stats_flush(Counters *cnt, const WideStats &w, bool 
     if (!uniform) return;
     atomicAdd(&cnt->st_wide_steps, w.steps);
     atomicAdd(&cnt->st_entries, w.entries);
+    atomicAdd(&cnt->st_wide_entries, w.entries);
     atomicAdd(&cnt->st_chain_bytes, w.bytes);
     if (w.reused) atomicAdd(&cnt->st_reused, w.reused);
     if (w.replay) atomicAdd(&cnt->st_replay, w.replay);
@@ -1025,7 +1026,7 @@ __global__ void __launch_bounds__(64 * kWideWaves) k_chain_wide_lds(SearchArgs a
         uint32_t e_end = nd.lo & ~kUniqueBit;
         int32_t depth = (int32_t)nd.hi;
         uint32_t len = nd.len;
-        const unsigned long long work0 = w.entries + w.steps;
+        const unsigned long long work0 = w.entries + w.steps, steps0 = w.steps;
         SoaRow cur{s_col[0], s_M[0], s_Ga[0]};
         SoaRow nxt{s_col[1], s_M[1], s_Ga[1]};
         bool done = true;
@@ -1069,6 +1070,7 @@ __global__ void __launch_bounds__(64 * kWideWaves) k_chain_wide_lds(SearchArgs a
             }
         }
         if (trace_work && lead) trace_work[item - first] = (float)(w.entries + w.steps - work0);
+        if (lead) atomicMax(&cnt->st_wide_max, w.steps - steps0);
         __syncthreads();
     }
     hit_release(hr, hkeys, hscores, caps.hits, cnt);
@@ -1238,10 +1240,12 @@ __global__ void __launch_bounds__(64) k_chain_wide_global(SearchArgs a, const No
         __syncthreads();
         AosRow cur{buf0}, nxt{buf1};
         Replay rp;
+        const unsigned long long steps0 = w.steps;
         if (!walk_wide(a, cur, nxt, len, e_end, depth, (uint32_t)caps.wrow, hkeys, hscores, caps, cnt, hr, w, rp,
                        s_delta)) {
             if (lane == 0) atomicOr(&cnt->overflow, kOvWideRow);
         }
+        if (lane == 0) atomicMax(&cnt->st_wide_max, w.steps - steps0);
         __syncthreads();
     }
     hit_release(hr, hkeys, hscores, caps.hits, cnt);

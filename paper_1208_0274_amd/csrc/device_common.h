@@ -70,21 +70,29 @@ struct SearchArgs {
     const uint32_t *qord;    // per column: ordinal of its query
     const uint32_t *segbeg;  // per query: first column
     const uint32_t *segend;  // per query: one past its last column
+    const uint32_t *colseg;  // per column: columns to the end of its query, kSegFirst on a query's first column
     uint32_t C[21];
     int32_t occ_packed;      // occ blocks are packed DNA (else one byte a character)
     int32_t has_sep;         // the text holds record separators
 };
 
 // Query segments (batched search).  Single-query searches never read the arrays.
+// The hot questions (where does col's query end, does it start at col) take
+// one load of colseg; the rest go through the query ordinal.
+constexpr uint32_t kSegFirst = 0x80000000u;
+__device__ inline uint32_t seg_info(const SearchArgs &a, uint32_t col) {
+    return a.multi ? a.colseg[col] : a.m - col;
+}
+__device__ inline uint32_t seg_dist(uint32_t info) { return info & ~kSegFirst; }
 __device__ inline uint32_t seg_end_of(const SearchArgs &a, uint32_t col) {
-    return a.multi ? a.segend[a.qord[col]] : a.m;
+    return a.multi ? col + seg_dist(a.colseg[col]) : a.m;
 }
 __device__ inline uint32_t seg_beg_of(const SearchArgs &a, uint32_t col) {
     return a.multi ? a.segbeg[a.qord[col]] : 0u;
 }
 // col is the first column of its query (nothing may enter it from the left)
 __device__ inline bool seg_first(const SearchArgs &a, uint32_t col) {
-    return a.multi && a.segbeg[a.qord[col]] == col;
+    return a.multi && (a.colseg[col] & kSegFirst) != 0;
 }
 // Offset that makes prefix-max keys of earlier queries useless in later ones:
 // within a query a key is M + |s_s|*col < 2^44, so the query ordinal shifted
@@ -218,6 +226,8 @@ struct Counters {
     kCounter t_gen0, t_gen1;  // first start / last end of lane-walker waves (100 MHz clock)
     kCounter t_live0, t_live1;  // same for the live wave pass
     kCounter t_push0;         // first item published to the live pass
+    kCounter st_wide_entries; // DP entries computed by the wave walkers
+    kCounter st_wide_max;     // most rows one wave walker stepped through for one item
     kCounter tasks;           // child tasks of the current level (node phase)
 };
 

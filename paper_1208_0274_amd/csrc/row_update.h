@@ -168,27 +168,12 @@ __device__ inline bool dominated_gapped(const SearchArgs &a, int64_t x, int64_t 
 // Zero floor (Theorem 2 (i)) and score filter (Theorem 2 (ii)) for a state of
 // value v at column col of a row at depth d1: the gain still available is at
 // most min(U(col), smax * (L_max - d1)) (query columns left, text rows left
-// under Theorem 1).  rowgain = smax * (L_max - d1).
-__device__ inline int32_t gain_after(const SearchArgs &a, uint32_t col) {
-    // match/mismatch scoring: every later column can add at most s_a
-    return a.u_closed ? a.smax * (int32_t)(seg_end_of(a, col) - 1 - col) : a.U[col];
-}
-
-__device__ inline bool keep_state(const SearchArgs &a, int32_t v, uint32_t col, int32_t rowgain) {
+// under Theorem 1).  rowgain = smax * (L_max - d1); send is the end of col's
+// query (one past its last column).
+__device__ inline bool keep_state_e(const SearchArgs &a, int32_t v, uint32_t col, uint32_t send, int32_t rowgain) {
     if (v <= 0) return false;
     if (!a.use_score_filter) return true;
-    int32_t g = gain_after(a, col);
-    if (rowgain < g) g = rowgain;
-    return v + g >= a.H;
-}
-
-// keep_state for a single query (SINGLE): no segment lookups.
-template <bool SINGLE>
-__device__ inline bool keep_state_q(const SearchArgs &a, int32_t v, uint32_t col, int32_t rowgain) {
-    if (!SINGLE) return keep_state(a, v, col, rowgain);
-    if (v <= 0) return false;
-    if (!a.use_score_filter) return true;
-    int32_t g = a.u_closed ? a.smax * (int32_t)(a.m - 1 - col) : a.U[col];
+    int32_t g = a.u_closed ? a.smax * (int32_t)(send - 1 - col) : a.U[col];
     if (rowgain < g) g = rowgain;
     return v + g >= a.H;
 }
@@ -289,27 +274,27 @@ __device__ void child_row(const SearchArgs &a, const Entry *prow, uint32_t plen,
     const int32_t ext = a.ss;
     const int32_t rowgain = a.smax * (a.lmax - d1);
     int64_t last = -1;     // last column already handled
+    uint32_t last_end = 0; // end of last's query (valid while gnext > 0)
     int32_t gnext = kNeg;  // G_b value for column last+1
     uint32_t gy = 0;       // its start column
 
     auto spread_to = [&](int64_t upto) {  // G_b-only columns last+1 .. upto
-        int64_t lim = upto;  // a query gap never runs into the next query
-        if (a.multi && last >= 0) {
-            const int64_t se = (int64_t)seg_end_of(a, (uint32_t)last) - 1;
-            if (se < lim) lim = se;
-        }
-        while (last < lim) {
-            if (gnext <= 0) break;
-            const uint32_t col = (uint32_t)(last + 1);
-            const int32_t v = gnext;
-            if (!keep_state(a, v, col, rowgain)) break;  // later columns only lose more
-            if (check_dom && dominated(a, sub, x, gy)) {
-                s.st_dom++;
-            } else {
-                emit_entry<WRITE>(a, s, col, v, kNeg, gy, 0, 1);
+        if (gnext > 0) {
+            // a query gap never runs into the next query
+            const int64_t lim = upto < (int64_t)last_end - 1 ? upto : (int64_t)last_end - 1;
+            while (last < lim) {
+                if (gnext <= 0) break;
+                const uint32_t col = (uint32_t)(last + 1);
+                const int32_t v = gnext;
+                if (!keep_state_e(a, v, col, last_end, rowgain)) break;  // later columns only lose more
+                if (check_dom && dominated(a, sub, x, gy)) {
+                    s.st_dom++;
+                } else {
+                    emit_entry<WRITE>(a, s, col, v, kNeg, gy, 0, 1);
+                }
+                last = col;
+                gnext = v + ext;
             }
-            last = col;
-            gnext = v + ext;
         }
         if (last < upto) {
             last = upto;
@@ -317,9 +302,10 @@ __device__ void child_row(const SearchArgs &a, const Entry *prow, uint32_t plen,
         }
     };
 
-    auto column = [&](uint32_t j, int32_t D, uint32_t yD, int32_t Gav, uint32_t yGav) {
+    // column j (first: j starts its query; send: end of j's query)
+    auto column = [&](uint32_t j, bool first, uint32_t send, int32_t D, uint32_t yD, int32_t Gav, uint32_t yGav) {
         spread_to((int64_t)j - 1);
-        const int32_t Gb = (last == (int64_t)j - 1 && !seg_first(a, j)) ? gnext : kNeg;
+        const int32_t Gb = (last == (int64_t)j - 1 && !first) ? gnext : kNeg;
         const uint32_t yGb = gy;
         int32_t M = D;
         uint32_t yM = yD;
@@ -331,8 +317,8 @@ __device__ void child_row(const SearchArgs &a, const Entry *prow, uint32_t plen,
             M = Gb;
             yM = yGb;
         }
-        const bool keepM = keep_state(a, M, j, rowgain);
-        const bool keepGa = keep_state(a, Gav, j, rowgain);
+        const bool keepM = keep_state_e(a, M, j, send, rowgain);
+        const bool keepGa = keep_state_e(a, Gav, j, send, rowgain);
         // G_b for column j+1 from this column's states that survive the filters
         int32_t gn = kNeg;
         uint32_t gny = 0;
@@ -345,6 +331,7 @@ __device__ void child_row(const SearchArgs &a, const Entry *prow, uint32_t plen,
             }
         }
         last = j;
+        last_end = send;
         gnext = gn;
         gy = gny;
         bool liveM = keepM, liveGa = keepGa;
@@ -368,30 +355,36 @@ __device__ void child_row(const SearchArgs &a, const Entry *prow, uint32_t plen,
     // parent entries k-1, k, k+1 move along in registers: one load per entry,
     // issued an entry ahead (the row's stores may alias it for the compiler)
     // with the score of the diagonal step after each (clamped into the row:
-    // used only where the column exists)
+    // used only where the column exists) and the column's query segment
     const uint32_t lastcol = a.m - 1;
     auto diag_score = [&](uint32_t col) -> int32_t { return pc[col < lastcol ? col + 1 : lastcol]; };
     Entry p{0, kNeg, kNeg, 0, 0};
     Entry nx{0, kNeg, kNeg, 0, 0};
     int32_t p_s = 0, nx_s = 0;
+    uint32_t nx_seg = 0;
     if (plen > 0) {
         nx = prow[0];
         nx_s = diag_score(nx.col);
+        nx_seg = seg_info(a, nx.col);
     }
     for (uint32_t k = 0; k < plen; ++k) {
         const Entry e = nx;
         const int32_t e_s = nx_s;
+        const uint32_t e_seg = nx_seg;
         const bool has_next = k + 1 < plen;
         if (has_next) {
             nx = prow[k + 1];
             nx_s = diag_score(nx.col);
+            nx_seg = seg_info(a, nx.col);
         }
         const uint32_t j = e.col;
+        const bool first = a.multi && (e_seg & kSegFirst) != 0;
+        const uint32_t send = j + seg_dist(e_seg);
         // diagonal from the previous parent entry, if it sits in column j-1
         int32_t D = kNeg;
         uint32_t yD = 0;
         if (k > 0) {
-            if (p.col + 1 == j && p.M > 0 && !seg_first(a, j)) {
+            if (p.col + 1 == j && p.M > 0 && !first) {
                 D = p.M + p_s;
                 yD = p.yM;
             }
@@ -407,10 +400,10 @@ __device__ void child_row(const SearchArgs &a, const Entry *prow, uint32_t plen,
             Gav = e.M + open;
             yGav = e.yM;
         }
-        column(j, D, yD, Gav, yGav);
+        column(j, first, send, D, yD, Gav, yGav);
         // diagonal into column j+1 when no parent entry sits there
-        if (e.M > 0 && j + 1 < seg_end_of(a, j) && !(has_next && nx.col == j + 1)) {
-            column(j + 1, e.M + e_s, e.yM, kNeg, 0);
+        if (e.M > 0 && j + 1 < send && !(has_next && nx.col == j + 1)) {
+            column(j + 1, false, send, e.M + e_s, e.yM, kNeg, 0);
         }
         p = e;
         p_s = e_s;
@@ -796,10 +789,13 @@ __device__ inline void wide_child_row(const SearchArgs &a, const Row cur, uint32
         uint32_t ncol = lane_down1(e.col);
         if (lane == 63) ncol = (k + 1 < len) ? cur.load(k + 1).col : kNone;
         if (k + 1 >= len) ncol = kNone;
+        // this entry's query: its end, and whether e.col starts it (one load in a batch)
+        const uint32_t sinfo = (FAST || !valid) ? 0u : seg_info(a, e.col);
+        const bool sfirst = !FAST && a.multi && (sinfo & kSegFirst) != 0;
         // column A = e.col: diagonal from the previous entry and G_a
         int32_t D = kNeg;
         uint32_t yD = 0;
-        if (valid && pcol != kNone && pcol + 1 == e.col && pM > 0 && (FAST || !seg_first(a, e.col))) {
+        if (valid && pcol != kNone && pcol + 1 == e.col && pM > 0 && !sfirst) {
             D = pM + pc[e.col];
             yD = pyM;
         }
@@ -822,7 +818,7 @@ __device__ inline void wide_child_row(const SearchArgs &a, const Row cur, uint32
             yM0A = yGaA;
         }
         // column B = e.col + 1: diagonal only, unless the next entry owns it
-        const uint32_t send = FAST ? a.m : (valid ? seg_end_of(a, e.col) : 0u);  // end of this entry's query
+        const uint32_t send = FAST ? a.m : (valid ? e.col + seg_dist(sinfo) : 0u);  // end of this entry's query
         const Key skey = FAST ? 0 : (valid ? (Key)seg_key(a, e.col) : 0);
         const bool hasB = valid && e.M > 0 && e.col + 1 < send && ncol != e.col + 1;
         const int32_t M0B = hasB ? e.M + pc[e.col + 1] : kNeg;
@@ -885,8 +881,8 @@ __device__ inline void wide_child_row(const SearchArgs &a, const Row cur, uint32
             MA = GbA;
             yMA = ext_tag;
         }
-        const bool keepMA = valid && keep_state_q<FAST>(a, MA, e.col, rowgain);
-        const bool keepGaA = valid && keep_state_q<FAST>(a, GaA, e.col, rowgain);
+        const bool keepMA = valid && keep_state_e(a, MA, e.col, send, rowgain);
+        const bool keepGaA = valid && keep_state_e(a, GaA, e.col, send, rowgain);
         // G_b and M at B
         Key kAB = exk;
         uint32_t tAB = ext_tag;
@@ -905,7 +901,7 @@ __device__ inline void wide_child_row(const SearchArgs &a, const Row cur, uint32
             MB = GbB;
             yMB = tAB;
         }
-        const bool keepMB = hasB && keep_state_q<FAST>(a, MB, e.col + 1, rowgain);
+        const bool keepMB = hasB && keep_state_e(a, MB, e.col + 1, send, rowgain);
         // G_b-only columns after this lane's last candidate, up to the next candidate
         Key kinc = kAB;
         uint32_t tinc = tAB;
@@ -919,7 +915,7 @@ __device__ inline void wide_child_row(const SearchArgs &a, const Row cur, uint32
         if (valid && kinc > kNoKey) {
             for (uint32_t col = lc + 1; col < stop; ++col) {
                 const Key v = kinc + a.sg - absss * (Key)col - skey;
-                if (v <= 0 || !keep_state_q<FAST>(a, (int32_t)v, col, rowgain)) break;
+                if (v <= 0 || !keep_state_e(a, (int32_t)v, col, send, rowgain)) break;
                 ++nspread;
                 nspread_hits += (v >= a.H);
             }

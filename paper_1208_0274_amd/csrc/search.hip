@@ -122,6 +122,15 @@ __global__ void k_gain_bound(const uint32_t *scan_rev, uint32_t m, const uint32_
     U[j] = (int32_t)u;
 }
 
+// Columns to the end of each column's query, with kSegFirst on first columns.
+__global__ void k_colseg(const uint32_t *qord, const uint32_t *segbeg, const uint32_t *segend, uint32_t m,
+                         uint32_t *colseg) {
+    uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= m) return;
+    const uint32_t q = qord[j];
+    colseg[j] = (segend[q] - j) | (segbeg[q] == j ? kSegFirst : 0u);
+}
+
 // Query ordinal of every column of a batch (segbeg is increasing).
 __global__ void k_qord(const uint32_t *segbeg, uint32_t nseg, uint32_t m, uint32_t *qord) {
     uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -492,6 +501,8 @@ struct alae_workspace {
     // batch segments
     uint32_t *qord = nullptr;
     uint64_t qord_cap = 0;
+    uint32_t *colseg = nullptr;  // per column: columns to its query's end | kSegFirst
+    uint64_t colseg_cap = 0;
     uint32_t *segbeg = nullptr;  // nseg first columns, then nseg ends
     uint64_t seg_cap = 0;
     uint64_t *d_off = nullptr;
@@ -587,6 +598,7 @@ static void ws_release_buffers(alae_workspace *ws) {
     hipFree(ws->left);
     hipFree(ws->tasks);
     hipFree(ws->qord);
+    hipFree(ws->colseg);
     hipFree(ws->segbeg);
     hipFree(ws->d_off);
     alae_workspace fresh;
@@ -884,12 +896,16 @@ static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64
     if (multi) {
         if ((st = grow(ws->qord, ws->qord_cap, m, false, 0, s)) != ALAE_OK) return st;
         if ((st = grow(ws->segbeg, ws->seg_cap, 2 * nseg, false, 0, s)) != ALAE_OK) return st;
+        if ((st = grow(ws->colseg, ws->colseg_cap, m, false, 0, s)) != ALAE_OK) return st;
         HIP_TRY(hipMemcpyAsync(ws->segbeg, ws->h_seg.data(), 2 * nseg * sizeof(uint32_t), hipMemcpyHostToDevice, s));
         k_qord<<<(uint32_t)((m + 255) / 256), 256, 0, s>>>(ws->segbeg, (uint32_t)nseg, (uint32_t)m, ws->qord);
+        k_colseg<<<(uint32_t)((m + 255) / 256), 256, 0, s>>>(ws->qord, ws->segbeg, ws->segbeg + nseg, (uint32_t)m,
+                                                              ws->colseg);
         a.multi = 1;
         a.qord = ws->qord;
         a.segbeg = ws->segbeg;
         a.segend = ws->segbeg + nseg;
+        a.colseg = ws->colseg;
     }
 
     SubTable sub;
@@ -1406,8 +1422,10 @@ static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64
         }
     }
     // items the live pass did not take: given-up claims, then the unclaimed tail
+    double live_ms = 0.0;
     {
         const Counters c0 = *ws->h_cnt;
+        if (c0.t_live0 != ~0ull && c0.t_live1 > c0.t_live0) live_ms = (double)(c0.t_live1 - c0.t_live0) * 1e-5;
         if (trace && (ng > 0 || nw1 > 0)) {
             const double t0 = (double)std::min(c0.t_gen0, c0.t_live0);
             fprintf(stderr,
@@ -1612,6 +1630,9 @@ static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64
         o->leftover = leftover;
         o->reused = c.st_reused;
         o->replay_chains = c.st_replay;
+        o->wide_entries = c.st_wide_entries;
+        o->wide_max_steps = c.st_wide_max;
+        o->live_ms = live_ms;
     }
     return ALAE_OK;
 }
@@ -1925,9 +1946,12 @@ static void add_stats(alae_stats &to, const alae_stats &x) {
     ALAE_ADD(level_lane_ms);
     ALAE_ADD(level_lane_launches);
     ALAE_ADD(tail_chains);
+    ALAE_ADD(wide_entries);
+    ALAE_ADD(live_ms);
 #undef ALAE_ADD
     to.max_depth = std::max(to.max_depth, x.max_depth);
     to.tail_depth = std::max(to.tail_depth, x.tail_depth);
+    to.wide_max_steps = std::max(to.wide_max_steps, x.wide_max_steps);
 }
 
 constexpr uint64_t kBatchColumns = 1ull << 18;
