@@ -112,14 +112,15 @@ def kernels_ms(stats_list):
 
 def wave_walkers(stats_list):
     """The wave walkers' share: entries, rows stepped, the span of the pass that runs beside the
-    lane walker, and the longest single chain.  A chain's rows depend on each other, so its walk is
-    a serial chain of row steps; live_ms / max_rows bounds the time of one row step from above."""
+    lane walker, and the chain item that took one block longest (its rows depend on each other, so
+    its walk is a serial chain of row steps: its time over its rows is the latency of one step)."""
     st = stats_list[-1]
     live = float(np.mean([s.live_ms for s in stats_list]))
     return {"entries": int(st.wide_entries), "rows": int(st.wide_steps), "max_rows_one_chain": int(st.wide_max_steps),
             "live_pass_ms": live, "entries_per_s": st.wide_entries / (live * 1e-3) if live > 0 else None,
             "entries_per_row": st.wide_entries / max(1, st.wide_steps),
-            "us_per_row_step_bound": live * 1e3 / st.wide_max_steps if st.wide_max_steps else None}
+            "slowest_chain_ms": float(st.wide_slowest_ms), "slowest_chain_rows": int(st.wide_slowest_rows),
+            "us_per_row_step": st.wide_slowest_ms * 1e3 / st.wide_slowest_rows if st.wide_slowest_rows else None}
 
 
 def batched_leg(alae, torch, args):

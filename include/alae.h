@@ -132,6 +132,8 @@ typedef struct {
     uint64_t wide_entries;   /* DP entries they computed (part of entries)                    */
     uint64_t wide_max_steps; /* most rows walked for one chain item                            */
     double live_ms;          /* span of the wave pass that runs beside the lane walker, first start to last end */
+    double wide_slowest_ms;  /* the chain item that took a wave-walker block longest: its time ... */
+    uint64_t wide_slowest_rows; /* ... and the rows it walked (a chain's rows depend on each other)  */
 } alae_stats;
 
 /*

@@ -218,13 +218,15 @@ constexpr int kStartBlock = 256;
 // Launched right behind the level kernels that make the chains, with a grid
 // for the most chains the level can make: the count is read here, and after
 // an overflow of the level (its outputs are incomplete and the host runs the
-// level and this kernel again) nothing is done.
+// level and this kernel again) nothing is done.  first_hits: write the hits
+// of an item's first row (off for items split off the frontier's tail, whose
+// rows' hits the level kernels wrote at every occurrence).
 // Four waves per SIMD (128 VGPRs, a few spilled): the random reads of the
 // suffix array and the text need the extra waves in flight more than the
 // spilled registers cost; a fifth wave spills too much.
 __global__ void __launch_bounds__(kStartBlock, 4) k_chain_start(SearchArgs a, SubTable subt, const Node *items,
                                                              const Entry *ient, ChainQueues q, Caps caps,
-                                                             Counters *cnt) {
+                                                             Counters *cnt, bool first_hits) {
     __shared__ int8_t sub[20 * 20];
     __shared__ BlockReserveLds<5, kStartBlock / 64> s_res5;
     __shared__ BlockReserveLds<11, kStartBlock / 64> s_res11;
@@ -280,7 +282,7 @@ __global__ void __launch_bounds__(kStartBlock, 4) k_chain_start(SearchArgs a, Su
                     ++n_dom;
                 }
             }
-            if (aM && e.M >= a.H) ++nh;
+            if (first_hits && aM && e.M >= a.H) ++nh;
             if (aM || aG) ++live;
             if (aG || (aM && e.M > -open)) ngr = false;
         }
@@ -1027,6 +1029,7 @@ __global__ void __launch_bounds__(64 * kWideWaves) k_chain_wide_lds(SearchArgs a
         int32_t depth = (int32_t)nd.hi;
         uint32_t len = nd.len;
         const unsigned long long work0 = w.entries + w.steps, steps0 = w.steps;
+        const unsigned long long tick0 = __builtin_amdgcn_s_memrealtime();
         SoaRow cur{s_col[0], s_M[0], s_Ga[0]};
         SoaRow nxt{s_col[1], s_M[1], s_Ga[1]};
         bool done = true;
@@ -1070,7 +1073,12 @@ __global__ void __launch_bounds__(64 * kWideWaves) k_chain_wide_lds(SearchArgs a
             }
         }
         if (trace_work && lead) trace_work[item - first] = (float)(w.entries + w.steps - work0);
-        if (lead) atomicMax(&cnt->st_wide_max, w.steps - steps0);
+        if (lead) {
+            const unsigned long long rows = w.steps - steps0;
+            atomicMax(&cnt->st_wide_max, rows);
+            const unsigned long long ticks = __builtin_amdgcn_s_memrealtime() - tick0;
+            atomicMax(&cnt->st_wide_slow, (ticks << 24) | (rows < (1ull << 24) ? rows : (1ull << 24) - 1));
+        }
         __syncthreads();
     }
     hit_release(hr, hkeys, hscores, caps.hits, cnt);

@@ -1150,8 +1150,9 @@ static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64
                     set_caps(cur);
                     const ChainQueues q{ws->gnodes, ws->gents, ws->wnodes, ws->wents, ws->hkeys, ws->hscores};
                     HIP_TRY(hipEventRecord(ws->evk0, s));
+                    // the level kernels wrote these rows' hits at every occurrence already
                     k_chain_start<<<(uint32_t)((items + kStartBlock - 1) / kStartBlock), kStartBlock, 0, s>>>(
-                        a, sub, ws->cnodes, ws->ents[cur], q, caps, ws->d_cnt);
+                        a, sub, ws->cnodes, ws->ents[cur], q, caps, ws->d_cnt, false);
                     double ums = 0.0;
                     if ((st = timed(ums)) != ALAE_OK) return st;
                     start_ms += ums;
@@ -1227,7 +1228,7 @@ static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64
                 if (most > 0) {
                     ChainQueues q{ws->gnodes, ws->gents, ws->wnodes, ws->wents, ws->hkeys, ws->hscores};
                     k_chain_start<<<(uint32_t)((most + kStartBlock - 1) / kStartBlock), kStartBlock, 0, s>>>(
-                        a, sub, ws->cnodes, ws->cents, q, caps, ws->d_cnt);
+                        a, sub, ws->cnodes, ws->cents, q, caps, ws->d_cnt, true);
                 }
             }
             double unit_ms = 0.0;
@@ -1632,6 +1633,8 @@ static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64
         o->replay_chains = c.st_replay;
         o->wide_entries = c.st_wide_entries;
         o->wide_max_steps = c.st_wide_max;
+        o->wide_slowest_ms = (double)(c.st_wide_slow >> 24) * 1e-5;
+        o->wide_slowest_rows = c.st_wide_slow & ((1ull << 24) - 1);
         o->live_ms = live_ms;
     }
     return ALAE_OK;
@@ -1952,6 +1955,10 @@ static void add_stats(alae_stats &to, const alae_stats &x) {
     to.max_depth = std::max(to.max_depth, x.max_depth);
     to.tail_depth = std::max(to.tail_depth, x.tail_depth);
     to.wide_max_steps = std::max(to.wide_max_steps, x.wide_max_steps);
+    if (x.wide_slowest_ms > to.wide_slowest_ms) {
+        to.wide_slowest_ms = x.wide_slowest_ms;
+        to.wide_slowest_rows = x.wide_slowest_rows;
+    }
 }
 
 constexpr uint64_t kBatchColumns = 1ull << 18;

@@ -267,7 +267,7 @@ def test_tail_split_identity(case):
     got_on = alae.search(idx, P, H, sc, stats=st_on)
     got_off = alae.search(idx, P, H, sc, stats=st_off, tail_split=False)
     print(f"{case}: tail chains {st_on.tail_chains} at depth {st_on.tail_depth}, levels {st_on.levels} "
-          f"against {st_off.levels}", flush=True)
+          f"against {st_off.levels}; hit records {st_on.emitted} against {st_off.emitted}", flush=True)
     exp = oracle.sw_hits(T, P, oracle.scoring_table(4, 1, -3), -5, -2, H, threads=8)
     assert_same(got_on, exp)
     assert_same(got_off, exp)
