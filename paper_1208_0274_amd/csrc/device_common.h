@@ -71,14 +71,15 @@ struct SearchArgs {
     const uint32_t *segbeg;  // per query: first column
     const uint32_t *segend;  // per query: one past its last column
     const uint32_t *colseg;  // per column: columns to the end of its query, kSegFirst on a query's first column
+    const uint32_t *colbeg;  // per column: columns of its query before it
     uint32_t C[21];
     int32_t occ_packed;      // occ blocks are packed DNA (else one byte a character)
     int32_t has_sep;         // the text holds record separators
 };
 
 // Query segments (batched search).  Single-query searches never read the arrays.
-// The hot questions (where does col's query end, does it start at col) take
-// one load of colseg; the rest go through the query ordinal.
+// The hot questions (where does col's query end or begin, does it start at
+// col) take one load; the prefix-max key offset goes through the query ordinal.
 constexpr uint32_t kSegFirst = 0x80000000u;
 __device__ inline uint32_t seg_info(const SearchArgs &a, uint32_t col) {
     return a.multi ? a.colseg[col] : a.m - col;
@@ -87,8 +88,9 @@ __device__ inline uint32_t seg_dist(uint32_t info) { return info & ~kSegFirst; }
 __device__ inline uint32_t seg_end_of(const SearchArgs &a, uint32_t col) {
     return a.multi ? col + seg_dist(a.colseg[col]) : a.m;
 }
-__device__ inline uint32_t seg_beg_of(const SearchArgs &a, uint32_t col) {
-    return a.multi ? a.segbeg[a.qord[col]] : 0u;
+// columns of col's query before col
+__device__ inline uint32_t seg_off(const SearchArgs &a, uint32_t col) {
+    return a.multi ? a.colbeg[col] : col;
 }
 // col is the first column of its query (nothing may enter it from the left)
 __device__ inline bool seg_first(const SearchArgs &a, uint32_t col) {

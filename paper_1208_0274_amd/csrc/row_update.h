@@ -46,7 +46,7 @@ __device__ inline bool dominated_tw(const SearchArgs &a, const int8_t *sub, cons
                                     int64_t y) {
     int64_t reach = a.dom_reach;
     if (x < reach) reach = x;
-    const int64_t yl = y - (int64_t)seg_beg_of(a, (uint32_t)y);  // columns of y's query before y
+    const int64_t yl = (int64_t)seg_off(a, (uint32_t)y);  // columns of y's query before y
     if (yl < reach) reach = yl;
     if (reach <= 0) return false;
     if (a.has_sep) {  // an alignment never reaches across a record separator
@@ -96,7 +96,7 @@ constexpr int kGapBand = 8;
 
 __device__ inline bool dominated_gapped(const SearchArgs &a, int64_t x, int64_t y) {
     constexpr int W = kGapBand, B = 2 * kGapBand + 1;
-    const int64_t yl = y - (int64_t)seg_beg_of(a, (uint32_t)y);
+    const int64_t yl = (int64_t)seg_off(a, (uint32_t)y);
     int R = (int)(x < kGapWindow ? x : kGapWindow);
     const int C = (int)(yl < kGapWindow ? yl : kGapWindow);
     // the window's text rows stop at a record separator (no alignment crosses one)

@@ -122,13 +122,15 @@ __global__ void k_gain_bound(const uint32_t *scan_rev, uint32_t m, const uint32_
     U[j] = (int32_t)u;
 }
 
-// Columns to the end of each column's query, with kSegFirst on first columns.
+// Columns to the end of each column's query, with kSegFirst on first columns,
+// and the columns of its query before it.
 __global__ void k_colseg(const uint32_t *qord, const uint32_t *segbeg, const uint32_t *segend, uint32_t m,
-                         uint32_t *colseg) {
+                         uint32_t *colseg, uint32_t *colbeg) {
     uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= m) return;
     const uint32_t q = qord[j];
     colseg[j] = (segend[q] - j) | (segbeg[q] == j ? kSegFirst : 0u);
+    colbeg[j] = j - segbeg[q];
 }
 
 // Query ordinal of every column of a batch (segbeg is increasing).
@@ -503,6 +505,8 @@ struct alae_workspace {
     uint64_t qord_cap = 0;
     uint32_t *colseg = nullptr;  // per column: columns to its query's end | kSegFirst
     uint64_t colseg_cap = 0;
+    uint32_t *colbeg = nullptr;  // per column: columns of its query before it
+    uint64_t colbeg_cap = 0;
     uint32_t *segbeg = nullptr;  // nseg first columns, then nseg ends
     uint64_t seg_cap = 0;
     uint64_t *d_off = nullptr;
@@ -599,6 +603,7 @@ static void ws_release_buffers(alae_workspace *ws) {
     hipFree(ws->tasks);
     hipFree(ws->qord);
     hipFree(ws->colseg);
+    hipFree(ws->colbeg);
     hipFree(ws->segbeg);
     hipFree(ws->d_off);
     alae_workspace fresh;
@@ -897,15 +902,17 @@ static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64
         if ((st = grow(ws->qord, ws->qord_cap, m, false, 0, s)) != ALAE_OK) return st;
         if ((st = grow(ws->segbeg, ws->seg_cap, 2 * nseg, false, 0, s)) != ALAE_OK) return st;
         if ((st = grow(ws->colseg, ws->colseg_cap, m, false, 0, s)) != ALAE_OK) return st;
+        if ((st = grow(ws->colbeg, ws->colbeg_cap, m, false, 0, s)) != ALAE_OK) return st;
         HIP_TRY(hipMemcpyAsync(ws->segbeg, ws->h_seg.data(), 2 * nseg * sizeof(uint32_t), hipMemcpyHostToDevice, s));
         k_qord<<<(uint32_t)((m + 255) / 256), 256, 0, s>>>(ws->segbeg, (uint32_t)nseg, (uint32_t)m, ws->qord);
         k_colseg<<<(uint32_t)((m + 255) / 256), 256, 0, s>>>(ws->qord, ws->segbeg, ws->segbeg + nseg, (uint32_t)m,
-                                                              ws->colseg);
+                                                              ws->colseg, ws->colbeg);
         a.multi = 1;
         a.qord = ws->qord;
         a.segbeg = ws->segbeg;
         a.segend = ws->segbeg + nseg;
         a.colseg = ws->colseg;
+        a.colbeg = ws->colbeg;
     }
 
     SubTable sub;
