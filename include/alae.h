@@ -134,6 +134,7 @@ typedef struct {
     double live_ms;          /* span of the wave pass that runs beside the lane walker, first start to last end */
     double wide_slowest_ms;  /* the chain item that took a wave-walker block longest: its time ... */
     uint64_t wide_slowest_rows; /* ... and the rows it walked (a chain's rows depend on each other)  */
+    uint64_t dominated_qgram;   /* seed states dropped by the q-gram domination table (Definition 1, Lemma 1) */
 } alae_stats;
 
 /*
@@ -173,7 +174,8 @@ typedef struct {
                                   score filter (Theorem 2), q-prefix seeding (Theorem 3, seeds at
                                   depth 1) or domination (Section 3.2).  Same hits, more work: the
                                   baseline of the filtering ratio (Equation 5).  Default 0.   */
-    int32_t use_domination;    /* Section 3.2 domination test (default 1)                  */
+    int32_t use_domination;    /* Section 3.2 domination: the q-gram table on the seeds    */
+                               /* (Definition 1, Lemma 1) and the tests on states (default 1) */
     int32_t use_score_filter;  /* Theorem 2 (default 1)                                     */
     int32_t use_qprefix;       /* Theorem 3 q-prefix seeding (default 1)                    */
     int32_t use_reuse;         /* Section 4 reuse of duplicate forks (default 0)             */

@@ -183,9 +183,13 @@ __global__ void k_batch_localize(uint64_t *keys, uint64_t count, const uint32_t 
 // significant), one per end column j >= q-1; other slots get the invalid key.
 // Matrix mode: slot c*m + j holds key c when s(c, P[j]) > 0.
 // In a batch a q-gram never spans two queries.
+// qdom (nullable): left characters of the text's q-grams (k_qgram_left); a
+// seed whose q-gram is preceded in the text by P[j - qeff] alone starts only
+// alignments that one more match to the left beats everywhere (Section 3.2.2,
+// Definition 1 and Lemma 1): its column is dropped.
 __global__ void k_seed_keys(const uint8_t *q, uint32_t m, int sigma, int qeff, int matrix_mode, SubTable sub,
                             const uint32_t *qord, const uint32_t *segbeg, uint64_t invalid, uint64_t *keys,
-                            uint32_t *vals) {
+                            uint32_t *vals, const uint32_t *qdom, Counters *cnt) {
     uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (!matrix_mode) {
         if (t >= m) return;
@@ -195,6 +199,13 @@ __global__ void k_seed_keys(const uint8_t *q, uint32_t m, int sigma, int qeff, i
         if ((int64_t)j - (int64_t)first >= qeff - 1) {
             key = 0;
             for (int k = qeff - 1; k >= 0; --k) key = key * sigma + q[j - k];
+            if (qdom && key < invalid && (int64_t)j - (int64_t)first >= qeff) {
+                const uint32_t left = q[j - qeff];
+                if (left < (uint32_t)sigma && qdom[key] == (1u << left)) {
+                    key = invalid;
+                    atomicAdd(&cnt->st_qdom, 1ull);
+                }
+            }
         }
         keys[t] = key;
         vals[t] = j;
@@ -205,6 +216,54 @@ __global__ void k_seed_keys(const uint8_t *q, uint32_t m, int sigma, int qeff, i
         keys[t] = sub.s[c * sigma + q[j]] > 0 ? c : invalid;
         vals[t] = j;
     }
+}
+
+// Left characters of the text's q-grams (Section 3.2.2, Definition 1):
+// mask[g] bit c is set when an occurrence of g is preceded by character c,
+// bit 31 when one starts the text or follows a record separator.  g is the
+// q-gram's code with its first character most significant (the seed keys'
+// order); q-grams holding a separator are skipped.  mask starts at zero.
+constexpr uint32_t kLeftNone = 1u << 31;
+constexpr int kQgramRun = 4096;      // text positions one thread rolls through
+constexpr uint32_t kQgramLds = 4096; // tables up to this size are gathered in LDS first
+constexpr uint64_t kQgramTableMax = 1ull << 24;  // larger tables (sigma^q) are not built
+__global__ void __launch_bounds__(256) k_qgram_left(const uint8_t *text, uint64_t n, int sigma, int q, uint32_t ng,
+                                                    uint32_t *mask) {
+    __shared__ uint32_t lmask[kQgramLds];
+    const bool local = ng <= kQgramLds;
+    if (local)
+        for (uint32_t g = threadIdx.x; g < ng; g += blockDim.x) lmask[g] = 0;
+    __syncthreads();
+    const uint64_t x0 = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) * (uint64_t)kQgramRun;
+    if (x0 + (uint64_t)q <= n) {
+        // windows starting at x0 .. x1-1; characters x0 .. x1+q-2 (all < n)
+        const uint64_t x1 = x0 + kQgramRun < n - q + 1 ? x0 + kQgramRun : n - q + 1;
+        uint32_t g = 0;
+        int64_t lastbad = -1;  // last position read that holds no letter
+        for (uint64_t p = x0; p + 1 < x1 + (uint64_t)q; ++p) {
+            const uint32_t c = text[p];
+            if (c >= (uint32_t)sigma) {
+                lastbad = (int64_t)p;
+                g = 0;
+            } else {
+                g = (uint32_t)(((uint64_t)g * (uint64_t)sigma + c) % ng);
+            }
+            if (p + 1 < x0 + (uint64_t)q) continue;  // the first window is not full yet
+            const uint64_t x = p + 1 - (uint64_t)q;
+            if (lastbad >= (int64_t)x) continue;
+            const uint32_t left = x == 0 ? 0xFFu : (uint32_t)text[x - 1];
+            const uint32_t bit = left < (uint32_t)sigma ? (1u << left) : kLeftNone;
+            if (local) {
+                if ((lmask[g] & bit) == 0) atomicOr(&lmask[g], bit);
+            } else {
+                if ((mask[g] & bit) == 0) atomicOr(&mask[g], bit);
+            }
+        }
+    }
+    if (!local) return;
+    __syncthreads();
+    for (uint32_t g = threadIdx.x; g < ng; g += blockDim.x)
+        if (lmask[g]) atomicOr(&mask[g], lmask[g]);
 }
 
 __device__ inline void backward_step(const SearchArgs &a, int c, int64_t &l, int64_t &r) {
@@ -507,6 +566,9 @@ struct alae_workspace {
     uint64_t colseg_cap = 0;
     uint32_t *colbeg = nullptr;  // per column: columns of its query before it
     uint64_t colbeg_cap = 0;
+    uint32_t *qdom = nullptr;    // left characters of the text's q-grams (k_qgram_left)
+    uint64_t qdom_cap = 0;
+    int qdom_q = 0;              // q of the table in qdom (0: none)
     uint32_t *segbeg = nullptr;  // nseg first columns, then nseg ends
     uint64_t seg_cap = 0;
     uint64_t *d_off = nullptr;
@@ -604,6 +666,7 @@ static void ws_release_buffers(alae_workspace *ws) {
     hipFree(ws->qord);
     hipFree(ws->colseg);
     hipFree(ws->colbeg);
+    hipFree(ws->qdom);
     hipFree(ws->segbeg);
     hipFree(ws->d_off);
     alae_workspace fresh;
@@ -943,10 +1006,26 @@ static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64
     for (int k = 0; k < (matrix_seeds ? 1 : qeff); ++k) space *= (uint64_t)sigma;
     const uint64_t invalid = space;  // keys >= invalid are not seeds
     const int seed_depth = matrix_seeds ? 1 : qeff;
+    // left characters of the text's q-grams, once per workspace and q (not in a fixed region)
+    const uint32_t *qdom = nullptr;
+    if (use_dom && !matrix_seeds && !t_region && space <= kQgramTableMax) {
+        if (ws->qdom_q != qeff) {
+            ws->qdom_q = 0;
+            if ((st = grow(ws->qdom, ws->qdom_cap, space, false, 0, s)) != ALAE_OK) return st;
+            k_fill_u32<<<(uint32_t)((space + 255) / 256), 256, 0, s>>>(ws->qdom, 0u, space);
+            const uint64_t threads = (idx->n - (uint64_t)qeff + 1 + kQgramRun - 1) / kQgramRun;
+            if (idx->n >= (uint64_t)qeff)
+                k_qgram_left<<<(uint32_t)((threads + 255) / 256), 256, 0, s>>>(idx->d_text, idx->n, sigma, qeff,
+                                                                               (uint32_t)space, ws->qdom);
+            HIP_TRY(hipGetLastError());
+            ws->qdom_q = qeff;
+        }
+        qdom = ws->qdom;
+    }
     k_seed_keys<<<(uint32_t)((nseed + tb - 1) / tb), tb, 0, s>>>(d_query, (uint32_t)m, sigma, seed_depth,
                                                                   matrix_seeds ? 1 : 0, sub,
                                                                   multi ? a.qord : nullptr, a.segbeg, invalid,
-                                                                  ws->seed_keys, ws->seed_vals);
+                                                                  ws->seed_keys, ws->seed_vals, qdom, ws->d_cnt);
     bool alt = false;
     HIP_TRY(radix_sort_pairs(ws->seed_keys, ws->seed_vals, ws->seed_keys_alt, ws->seed_vals_alt, nseed,
                              bit_length(invalid), ws->scratch, &alt, s));
@@ -1609,6 +1688,7 @@ static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64
         o->entries_gap2 = c.st_gap2;
         o->entries_gap3 = c.st_gap3;
         o->dominated = c.st_dominated;
+        o->dominated_qgram = c.st_qdom;
         o->emitted = emitted - padding;
         o->hits = unique;
         o->levels = levels;
@@ -1957,6 +2037,7 @@ static void add_stats(alae_stats &to, const alae_stats &x) {
     ALAE_ADD(level_lane_launches);
     ALAE_ADD(tail_chains);
     ALAE_ADD(wide_entries);
+    ALAE_ADD(dominated_qgram);
     ALAE_ADD(live_ms);
 #undef ALAE_ADD
     to.max_depth = std::max(to.max_depth, x.max_depth);
