@@ -63,18 +63,25 @@ __device__ inline bool dominated_tw(const SearchArgs &a, const int8_t *sub, cons
     load_window32(a.query, y, qw);
     int32_t sum = 0;
     bool dom = false;
+    // eight characters at a time; a lane stops once its sum can no longer turn
+    // positive within the reach (each character adds at most s_max)
 #pragma unroll
-    for (int k = 1; k <= 32; ++k) {
-        const int j = 32 - k;
-        uint32_t tc = (tw[j >> 2] >> (8 * (j & 3))) & 0xFFu;
-        const uint32_t pc = (qw[j >> 2] >> (8 * (j & 3))) & 0xFFu;
-        if (a.matrix_mode && tc >= (uint32_t)a.sigma) tc = 0;  // past the reach; keeps the table index inside
-        const int32_t d = a.matrix_mode ? (int32_t)sub[tc * (uint32_t)a.sigma + pc]
-                                        : (tc == pc ? a.s_match : a.s_mismatch);
-        if (k <= reach) {
-            sum += d;
-            dom |= sum > 0;
+    for (int k0 = 1; k0 <= 32; k0 += 8) {
+#pragma unroll
+        for (int k = k0; k < k0 + 8; ++k) {
+            const int j = 32 - k;
+            uint32_t tc = (tw[j >> 2] >> (8 * (j & 3))) & 0xFFu;
+            const uint32_t pc = (qw[j >> 2] >> (8 * (j & 3))) & 0xFFu;
+            if (a.matrix_mode && tc >= (uint32_t)a.sigma) tc = 0;  // past the reach; keeps the table index inside
+            const int32_t d = a.matrix_mode ? (int32_t)sub[tc * (uint32_t)a.sigma + pc]
+                                            : (tc == pc ? a.s_match : a.s_mismatch);
+            if (k <= reach) {
+                sum += d;
+                dom |= sum > 0;
+            }
         }
+        const int64_t left = reach - (k0 + 7);
+        if (dom || left <= 0 || sum + (int64_t)a.smax * left <= 0) break;
     }
     return dom;
 }

@@ -593,6 +593,7 @@ static void ws_release_buffers(alae_workspace *ws);
 
 static void ws_release(alae_workspace *ws) {
     ws_release_buffers(ws);
+    hipFree(ws->qdom);  // kept by ws_release_buffers when small
     hipFree(ws->d_cnt);
     if (ws->h_cnt) hipHostFree(ws->h_cnt);
     if (ws->s2) hipStreamDestroy(ws->s2);
@@ -666,7 +667,8 @@ static void ws_release_buffers(alae_workspace *ws) {
     hipFree(ws->qord);
     hipFree(ws->colseg);
     hipFree(ws->colbeg);
-    hipFree(ws->qdom);
+    const bool keep_qdom = ws->qdom_cap <= (1ull << 18);  // a small q-gram table outlives a trim
+    if (!keep_qdom) hipFree(ws->qdom);
     hipFree(ws->segbeg);
     hipFree(ws->d_off);
     alae_workspace fresh;
@@ -684,6 +686,11 @@ static void ws_release_buffers(alae_workspace *ws) {
     fresh.ev_join = ws->ev_join;
     fresh.s2 = ws->s2;
     fresh.region = ws->region;
+    if (keep_qdom) {
+        fresh.qdom = ws->qdom;
+        fresh.qdom_cap = ws->qdom_cap;
+        fresh.qdom_q = ws->qdom_q;
+    }
     *ws = fresh;
 }
 
