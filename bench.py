@@ -35,7 +35,8 @@ sys.path.insert(0, ROOT)
 METRIC = "effective m*n cell-updates/s + DP entries/s at exact hits; p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
 LEVEL_KERNEL = "k_level_tasks+k_expand_children"  # the trie-expansion step of one level (node phase, child phase)
-TRAFFIC_PROFILE = "trie_expansion_traffic_batched_dna.md"
+TRAFFIC_PROFILE = {"batched": "trie_expansion_traffic_batched_dna.md",
+                   "long_query": "trie_expansion_traffic_dna_long_query.md"}
 # Under BWT-SW's zero-floor rule the rows kept do not depend on H (no score or length filter
 # reads it), so its entry count is taken with a threshold no score reaches: without the
 # domination test every start inside a planted homolog re-emits that homolog's hit cells, and
@@ -66,14 +67,14 @@ def timed(fn, sync):
     return out, time.perf_counter() - t0
 
 
-def measured_traffic():
-    """HBM bytes per level of the trie-expansion kernels on the batched workload from the
-    committed rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE scaled by a device-copy
+def measured_traffic(workload):
+    """HBM bytes per level of the trie-expansion kernels on a workload from its committed
+    rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE scaled by a device-copy
     calibration), or None when the kernel sources or the host loop changed since."""
     import hashlib
     import re
 
-    path = os.path.join(ROOT, "profiles", TRAFFIC_PROFILE)
+    path = os.path.join(ROOT, "profiles", TRAFFIC_PROFILE[workload])
     if not os.path.exists(path):
         return None
     text = open(path).read()
@@ -89,13 +90,13 @@ def measured_traffic():
     return int(m_b.group(1))
 
 
-def roofline(stats_list):
+def roofline(stats_list, workload):
     level_ms = float(np.mean([s.level_lane_ms for s in stats_list]))
     st = stats_list[-1]
     launches = max(1, st.level_lane_launches)
     alg = st.level_alg_bytes()
     achieved = alg / (level_ms * 1e-3) / 1e9 if level_ms > 0 else 0.0
-    traffic = measured_traffic()
+    traffic = measured_traffic(workload)
     return {"kernel": LEVEL_KERNEL, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
             "traffic_GBps": (traffic / (level_ms / launches * 1e-3) / 1e9) if traffic else None,
@@ -232,8 +233,13 @@ def long_query_leg(alae, torch, args):
                        "(200-2,000, 15% subs, 2% indels); query 1e5; <1,-3,-5,-2>; H=30",
            "ms_per_search": ms, "cells_per_s": P.shape[0] * T.shape[0] / (ms * 1e-3), "hits": int(cnt),
            "dp_entries_per_s": float(np.mean([s.entries / t for s, t in zip(stats, times)])),
-           "kernels_ms": kernels_ms(stats), "roofline_trie_expansion": roofline(stats),
+           "kernels_ms": kernels_ms(stats), "roofline_trie_expansion": roofline(stats, "long_query"),
            "wave_walkers": wave_walkers(stats)}
+    if args.long_query_only:
+        log(f"long query: {ms:.1f} ms")
+        ws.free()
+        idx.free()
+        return out
     st_b = alae.Stats()
     (cb, tb) = timed(lambda: ws.search_device(dq, NO_OUTPUT_H, sc, stats=st_b, zero_floor_only=True), sync)
     out["filtering"] = {"entries_alae": int(stats[-1].entries), "entries_zero_floor_only": int(st_b.entries),
@@ -367,6 +373,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="only the headline and its to-host timing")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--long-query-only", action="store_true",
+                    help="only the DNA long-query leg's searches, without its filtering, tuning and scheduling "
+                         "extras (to profile it alone)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU; the search would shard by text range, one index part per GPU",
@@ -377,6 +386,10 @@ def main():
 
     from paper_1208_0274_amd import alae
 
+    if args.long_query_only:
+        args.no_extras = True
+        print(json.dumps({"dna_long_query": long_query_leg(alae, torch, args)}), flush=True)
+        return
     b = batched_leg(alae, torch, args)
     stats, times = b["stats"], b["times"]
     ms = b["ms"]
@@ -405,7 +418,7 @@ def main():
         "index_build_s": b["index_build_s"],
         "kernels_ms": kernels_ms(stats),
         "search_stats": {k: (float(v) if isinstance(v, float) else int(v)) for k, v in stats[-1].as_dict().items()},
-        "roofline": roofline(stats),
+        "roofline": roofline(stats, "batched"),
         "wave_walkers": wave_walkers(stats),
     }
     for k in ("single_query_loop", "filtering"):
