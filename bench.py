@@ -324,8 +324,7 @@ def serving(alae, idx, T, rates=(10.0, 30.0, 100.0, 300.0, 1000.0), count=200):
         t0 = time.perf_counter()
         th.start()
         th.join()
-        for i in ids:
-            srv.poll(i)
+        results = [srv.poll(i) for i in ids]
         wall = time.perf_counter() - t0
         st = srv.stats()
         out.append({"rate_qps": rate, "requests": count, "throughput_qps": count / wall, "p50_ms": st["p50_ms"],
@@ -333,6 +332,14 @@ def serving(alae, idx, T, rates=(10.0, 30.0, 100.0, 300.0, 1000.0), count=200):
                     "mean_m": float(np.mean([q.shape[0] for q in qs]))})
         log(f"serving at {rate} q/s: {out[-1]}")
     srv.close()
+    # the last rate's results against the same queries searched alone (a sample of eight)
+    same = 0
+    sample = list(range(0, count, max(1, count // 8)))[:8]
+    for k in sample:
+        alone = alae.search(idx, qs[k], 30, sc)
+        same += int(all(np.array_equal(x, y) for x, y in zip(alone, results[k])))
+    out.append({"identical_to_alone": f"{same} of {len(sample)} sampled requests of the last rate"})
+    log(f"serving: {out[-1]}")
     return out
 
 

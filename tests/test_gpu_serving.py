@@ -102,3 +102,47 @@ def test_admission_and_errors(planted):
     with pytest.raises(alae.AlaeError):
         srv.poll(rid)  # already collected
     srv.close()
+
+
+@pytest.mark.slow
+@pytest.mark.timeout(600)
+def test_serving_on_1e9_index():
+    """Serving at full size: the 1e9-base index of the batched workload stays resident;
+    40 requests shaped like the serving workload (log-uniform 100-100,000, half carrying a
+    mutated text segment) arrive at once.  Every result equals the same query searched
+    alone; for the shorter requests with hits, the oracle on a text window around all of
+    their hits (2,000 text ends on either side, plus L_max of context) gives exactly the
+    served hits."""
+    w = synth.batched_dna()
+    T = w["text"]
+    qs = synth.serving_queries(T, 40)
+    idx = alae.Index.build(T, "dna")
+    sc = alae.make_scoring(1, -3, -5, -2)
+    H = 30
+    print(f"serving on n={T.shape[0]}: {len(qs)} requests, sum m={sum(q.shape[0] for q in qs)}", flush=True)
+    srv = alae.Server(idx, max_batch=16)
+    ids = [srv.submit(q, H, sc) for q in qs]
+    mix = [srv.poll(i) for i in ids]
+    st = srv.stats()
+    srv.close()
+    print(st, flush=True)
+    assert st["completed"] == len(qs)
+    ws = alae.Workspace(idx)
+    for k, q in enumerate(qs):
+        _same(mix[k], alae.search(idx, q, H, sc), f"request {k} alone")
+    ws.free()
+    sub = oracle.scoring_table(4, 1, -3)
+    checked = 0
+    for k, q in enumerate(qs):
+        j, t, s = mix[k]
+        if t.shape[0] == 0 or q.shape[0] > 4000:
+            continue
+        a = max(0, int(t.min()) - 2000)
+        b = min(T.shape[0], int(t.max()) + 2001)
+        lo = max(0, a - oracle.lmax(q.shape[0], 1, -5, -2, H))
+        oj, ot, os_ = oracle.sw_hits(T[lo:b], q, sub, -5, -2, H, t_lo=a - lo, t_hi=b - lo, threads=8)
+        _same(mix[k], (oj, ot + lo, os_), f"request {k} oracle window [{a}, {b})")
+        checked += 1
+    print(f"{checked} requests checked against oracle windows", flush=True)
+    assert checked >= 3
+    idx.free()
