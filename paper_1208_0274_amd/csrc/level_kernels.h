@@ -21,7 +21,12 @@
 
 namespace alae {
 
-constexpr uint32_t kLaneRow = 32;
+// Rows up to this length are expanded one lane per child; longer ones by a
+// wave per node.  Where the frontier widens, most rows hold a few dozen
+// entries: a wave per such node costs its own allocation atomics per child,
+// and same-address atomics are served one at a time, while the lane kernel
+// reserves once per block.
+constexpr uint32_t kLaneRow = 128;
 
 struct LevelOut {
     Node *onodes;   // next level, rows of at most kLaneRow entries

@@ -1113,7 +1113,9 @@ static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64
     const uint64_t wrow = m + 2;  // a row never holds more than m entries
     // staging rows of the level-wide kernel start short and grow to the longest child row met
     uint64_t srow = std::min<uint64_t>(wrow, 4096);
-    const uint64_t stage_budget = ((2ull << 30) >> (2 * sh)) / sizeof(Entry);
+    // (8 GiB: at the first levels of a wide batch every node's rows are long, and the
+    // stage per block is what limits how many nodes expand at once)
+    const uint64_t stage_budget = (t_region ? ((2ull << 30) >> (2 * sh)) : (8ull << 30)) / sizeof(Entry);
     // queues that live through the whole search
     for (int i = 0; i < 2; ++i)
         if ((st = grow(ws->lwide[i], ws->lwide_cap[i], 1ull << 12, false, 0, s)) != ALAE_OK) return st;
@@ -1308,8 +1310,10 @@ static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64
             }
             HIP_TRY(hipEventRecord(ws->evkm, s));
             if (nlw > 0) {
-                const uint32_t blocks =
-                    (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>({nlw, 2048, stage_budget / srow}));
+                // one wave per node; as many as the CUs hold (rows just over a lane's limit are
+                // common at the levels where the frontier widens, and each costs a few round trips)
+                const uint32_t blocks = (uint32_t)std::max<uint64_t>(
+                    1, std::min<uint64_t>({nlw, (uint64_t)cus * 16, stage_budget / srow}));
                 if ((st = grow(ws->stage, ws->stage_cap, (uint64_t)blocks * srow, false, 0, s)) != ALAE_OK) return st;
                 k_expand_level_wide<<<blocks, 64, 0, s>>>(a, ws->lwide[cur], (uint32_t)nlw, ws->ents[cur], d1, o,
                                                           caps, ws->d_cnt, ws->stage);
