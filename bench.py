@@ -121,6 +121,7 @@ def wave_walkers(stats_list):
             "live_pass_ms": live, "entries_per_s": st.wide_entries / (live * 1e-3) if live > 0 else None,
             "entries_per_row": st.wide_entries / max(1, st.wide_steps),
             "slowest_chain_ms": float(st.wide_slowest_ms), "slowest_chain_rows": int(st.wide_slowest_rows),
+            "slowest_chain_start_ms": float(st.wide_slowest_start_ms),
             "us_per_row_step": st.wide_slowest_ms * 1e3 / st.wide_slowest_rows if st.wide_slowest_rows else None}
 
 

@@ -135,6 +135,7 @@ typedef struct {
     double wide_slowest_ms;  /* the chain item that took a wave-walker block longest: its time ... */
     uint64_t wide_slowest_rows; /* ... and the rows it walked (a chain's rows depend on each other)  */
     uint64_t dominated_qgram;   /* seed states dropped by the q-gram domination table (Definition 1, Lemma 1) */
+    double wide_slowest_start_ms; /* when the slowest wave-walker item began, after its pass began */
 } alae_stats;
 
 /*

@@ -69,7 +69,7 @@ class Stats(ctypes.Structure):
                 ("tail_chains", ctypes.c_uint64), ("tail_depth", ctypes.c_uint64),
                 ("wide_entries", ctypes.c_uint64), ("wide_max_steps", ctypes.c_uint64), ("live_ms", ctypes.c_double),
                 ("wide_slowest_ms", ctypes.c_double), ("wide_slowest_rows", ctypes.c_uint64),
-                ("dominated_qgram", ctypes.c_uint64)]
+                ("dominated_qgram", ctypes.c_uint64), ("wide_slowest_start_ms", ctypes.c_double)]
 
     def reusing_ratio(self) -> float:
         """Equation 6: reused entries over accessed (reused + computed) entries."""

@@ -1076,8 +1076,17 @@ __global__ void __launch_bounds__(64 * kWideWaves) k_chain_wide_lds(SearchArgs a
         if (lead) {
             const unsigned long long rows = w.steps - steps0;
             atomicMax(&cnt->st_wide_max, rows);
-            const unsigned long long ticks = __builtin_amdgcn_s_memrealtime() - tick0;
-            atomicMax(&cnt->st_wide_slow, (ticks << 24) | (rows < (1ull << 24) ? rows : (1ull << 24) - 1));
+            // duration (10 ns ticks, 26 bits), start after the pass began (µs, 20 bits), rows (18 bits)
+            const unsigned long long now = __builtin_amdgcn_s_memrealtime();
+            const unsigned long long ticks = now - tick0;
+            const unsigned long long p0 = live.ready ? __hip_atomic_load(&cnt->t_live0, __ATOMIC_RELAXED,
+                                                                          __HIP_MEMORY_SCOPE_AGENT)
+                                                     : tick0;
+            const unsigned long long start_us = tick0 > p0 ? (tick0 - p0) / 100 : 0;
+            const unsigned long long key = (ticks < (1ull << 26) ? ticks : (1ull << 26) - 1) << 38 |
+                                           (start_us < (1ull << 20) ? start_us : (1ull << 20) - 1) << 18 |
+                                           (rows < (1ull << 18) ? rows : (1ull << 18) - 1);
+            atomicMax(&cnt->st_wide_slow, key);
         }
         __syncthreads();
     }

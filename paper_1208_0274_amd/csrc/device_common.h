@@ -230,7 +230,7 @@ struct Counters {
     kCounter t_push0;         // first item published to the live pass
     kCounter st_wide_entries; // DP entries computed by the wave walkers
     kCounter st_wide_max;     // most rows one wave walker stepped through for one item
-    kCounter st_wide_slow;    // slowest wave-walker item: 100 MHz ticks << 24 | its rows
+    kCounter st_wide_slow;    // slowest wave-walker item: ticks << 38 | start (µs into the pass) << 18 | rows
     kCounter st_qdom;         // seed states dropped by the q-gram domination table
     kCounter tasks;           // child tasks of the current level (node phase)
 };

@@ -1731,8 +1731,9 @@ static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64
         o->replay_chains = c.st_replay;
         o->wide_entries = c.st_wide_entries;
         o->wide_max_steps = c.st_wide_max;
-        o->wide_slowest_ms = (double)(c.st_wide_slow >> 24) * 1e-5;
-        o->wide_slowest_rows = c.st_wide_slow & ((1ull << 24) - 1);
+        o->wide_slowest_ms = (double)(c.st_wide_slow >> 38) * 1e-5;
+        o->wide_slowest_start_ms = (double)((c.st_wide_slow >> 18) & ((1ull << 20) - 1)) * 1e-3;
+        o->wide_slowest_rows = c.st_wide_slow & ((1ull << 18) - 1);
         o->live_ms = live_ms;
     }
     return ALAE_OK;
@@ -2057,6 +2058,7 @@ static void add_stats(alae_stats &to, const alae_stats &x) {
     if (x.wide_slowest_ms > to.wide_slowest_ms) {
         to.wide_slowest_ms = x.wide_slowest_ms;
         to.wide_slowest_rows = x.wide_slowest_rows;
+        to.wide_slowest_start_ms = x.wide_slowest_start_ms;
     }
 }
 
