@@ -417,7 +417,7 @@ def main():
         "config": {"workload": "batched DNA: 256 queries (log-uniform 500-50,000), 20 planted mutated segments of "
                                "each (200-2,000, 15% subs, 2% indels) in a 1e9 i.i.d. ACGT text; <1,-3,-5,-2>; "
                                "H=30", "n": b["n"], "queries": 256, "sum_m": b["sum_m"], "H": b["H"],
-                   "batch_columns": 1 << 18},
+                   "batch_columns": 1 << 19},
         "dp_entries_per_s": float(np.mean([s.entries / t for s, t in zip(stats, times)])),
         "p50_ms": float(np.percentile(times, 50) * 1e3),
         "p99_ms": float(np.percentile(times, 99) * 1e3),

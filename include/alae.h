@@ -198,7 +198,7 @@ typedef struct {
        the text (the hit set is the same either way) */
     int32_t no_tail_split;
     /* batched searches: queries are taken in order in groups of at most this many columns
-       (a longer query alone), one trie traversal per group; 0 = 2^18 */
+       (a longer query alone), one trie traversal per group; 0 = 2^19 */
     uint64_t batch_columns;
 } alae_search_opts;
 

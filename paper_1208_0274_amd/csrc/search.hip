@@ -2062,7 +2062,7 @@ static void add_stats(alae_stats &to, const alae_stats &x) {
     }
 }
 
-constexpr uint64_t kBatchColumns = 1ull << 18;
+constexpr uint64_t kBatchColumns = 1ull << 19;
 
 }  // namespace alae
 
