@@ -369,8 +369,24 @@ __device__ void child_row(const SearchArgs &a, const Entry *prow, uint32_t plen,
     Entry nx{0, kNeg, kNeg, 0, 0};
     int32_t p_s = 0, nx_s = 0;
     uint32_t nx_seg = 0;
+    // parent entries are read four at a time (80 contiguous bytes a lane), so that a
+    // lane's row is fetched while its lines are in the cache
+    Entry q0 = nx, q1 = nx, q2 = nx, q3 = nx;
+    uint32_t qb = 0xFFFFFFFFu;
+    auto parent = [&](uint32_t k) -> Entry {
+        const uint32_t b = k & ~3u;
+        if (b != qb) {
+            qb = b;
+            q0 = prow[b];
+            if (b + 1 < plen) q1 = prow[b + 1];
+            if (b + 2 < plen) q2 = prow[b + 2];
+            if (b + 3 < plen) q3 = prow[b + 3];
+        }
+        const uint32_t r = k & 3u;
+        return r == 0 ? q0 : r == 1 ? q1 : r == 2 ? q2 : q3;
+    };
     if (plen > 0) {
-        nx = prow[0];
+        nx = parent(0);
         nx_s = diag_score(nx.col);
         nx_seg = seg_info(a, nx.col);
     }
@@ -380,7 +396,7 @@ __device__ void child_row(const SearchArgs &a, const Entry *prow, uint32_t plen,
         const uint32_t e_seg = nx_seg;
         const bool has_next = k + 1 < plen;
         if (has_next) {
-            nx = prow[k + 1];
+            nx = parent(k + 1);
             nx_s = diag_score(nx.col);
             nx_seg = seg_info(a, nx.col);
         }
