@@ -224,8 +224,8 @@ __global__ void k_seed_keys(const uint8_t *q, uint32_t m, int sigma, int qeff, i
 // q-gram's code with its first character most significant (the seed keys'
 // order); q-grams holding a separator are skipped.  mask starts at zero.
 constexpr uint32_t kLeftNone = 1u << 31;
-constexpr int kQgramRun = 4096;      // text positions one thread rolls through
-constexpr uint32_t kQgramLds = 4096; // tables up to this size are gathered in LDS first
+constexpr int kQgramPerThread = 256;  // windows a thread takes, 256 apart (a block: 65,536 consecutive)
+constexpr uint32_t kQgramLds = 4096;  // tables up to this size are gathered in LDS first
 constexpr uint64_t kQgramTableMax = 1ull << 24;  // larger tables (sigma^q) are not built
 __global__ void __launch_bounds__(256) k_qgram_left(const uint8_t *text, uint64_t n, int sigma, int q, uint32_t ng,
                                                     uint32_t *mask) {
@@ -234,30 +234,26 @@ __global__ void __launch_bounds__(256) k_qgram_left(const uint8_t *text, uint64_
     if (local)
         for (uint32_t g = threadIdx.x; g < ng; g += blockDim.x) lmask[g] = 0;
     __syncthreads();
-    const uint64_t x0 = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) * (uint64_t)kQgramRun;
-    if (x0 + (uint64_t)q <= n) {
-        // windows starting at x0 .. x1-1; characters x0 .. x1+q-2 (all < n)
-        const uint64_t x1 = x0 + kQgramRun < n - q + 1 ? x0 + kQgramRun : n - q + 1;
+    const uint64_t windows = n - (uint64_t)q + 1;  // the launch has n >= q
+    const uint64_t base = (uint64_t)blockIdx.x * blockDim.x * kQgramPerThread;
+    for (int i = 0; i < kQgramPerThread; ++i) {
+        // neighbouring lanes take neighbouring windows: every load below is one contiguous span
+        const uint64_t x = base + (uint64_t)i * blockDim.x + threadIdx.x;
+        if (x >= windows) break;
         uint32_t g = 0;
-        int64_t lastbad = -1;  // last position read that holds no letter
-        for (uint64_t p = x0; p + 1 < x1 + (uint64_t)q; ++p) {
-            const uint32_t c = text[p];
-            if (c >= (uint32_t)sigma) {
-                lastbad = (int64_t)p;
-                g = 0;
-            } else {
-                g = (uint32_t)(((uint64_t)g * (uint64_t)sigma + c) % ng);
-            }
-            if (p + 1 < x0 + (uint64_t)q) continue;  // the first window is not full yet
-            const uint64_t x = p + 1 - (uint64_t)q;
-            if (lastbad >= (int64_t)x) continue;
-            const uint32_t left = x == 0 ? 0xFFu : (uint32_t)text[x - 1];
-            const uint32_t bit = left < (uint32_t)sigma ? (1u << left) : kLeftNone;
-            if (local) {
-                if ((lmask[g] & bit) == 0) atomicOr(&lmask[g], bit);
-            } else {
-                if ((mask[g] & bit) == 0) atomicOr(&mask[g], bit);
-            }
+        bool letters = true;
+        for (int k = 0; k < q; ++k) {
+            const uint32_t c = text[x + (uint64_t)k];
+            letters = letters && c < (uint32_t)sigma;
+            g = g * (uint32_t)sigma + (c < (uint32_t)sigma ? c : 0u);
+        }
+        if (!letters) continue;
+        const uint32_t left = x == 0 ? 0xFFu : (uint32_t)text[x - 1];
+        const uint32_t bit = left < (uint32_t)sigma ? (1u << left) : kLeftNone;
+        if (local) {
+            if ((lmask[g] & bit) == 0) atomicOr(&lmask[g], bit);
+        } else {
+            if ((mask[g] & bit) == 0) atomicOr(&mask[g], bit);
         }
     }
     if (!local) return;
@@ -1020,10 +1016,10 @@ static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64
             ws->qdom_q = 0;
             if ((st = grow(ws->qdom, ws->qdom_cap, space, false, 0, s)) != ALAE_OK) return st;
             k_fill_u32<<<(uint32_t)((space + 255) / 256), 256, 0, s>>>(ws->qdom, 0u, space);
-            const uint64_t threads = (idx->n - (uint64_t)qeff + 1 + kQgramRun - 1) / kQgramRun;
+            const uint64_t per_block = 256ull * kQgramPerThread;
             if (idx->n >= (uint64_t)qeff)
-                k_qgram_left<<<(uint32_t)((threads + 255) / 256), 256, 0, s>>>(idx->d_text, idx->n, sigma, qeff,
-                                                                               (uint32_t)space, ws->qdom);
+                k_qgram_left<<<(uint32_t)((idx->n - (uint64_t)qeff + 1 + per_block - 1) / per_block), 256, 0, s>>>(
+                    idx->d_text, idx->n, sigma, qeff, (uint32_t)space, ws->qdom);
             HIP_TRY(hipGetLastError());
             ws->qdom_q = qeff;
         }
