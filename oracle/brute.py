@@ -127,3 +127,49 @@ def basic_A(T, P, sub, sg: int, ss: int):
                 if M[k][j] > A[i][j]:
                     A[i][j] = M[k][j]
     return A
+
+
+def brute_A_prefixes(T, P, sub, sg: int, ss: int):
+    """The same A as :func:`brute_A`, enumerating each alignment once as a prefix.
+
+    Every alignment of T[x..i] against P[y..j] is a prefix of the transcripts
+    that start at (x, y); a depth-first walk over all transcripts from each
+    start keeps the running score of the prefix walked so far (a substitution
+    score per pair; sg + ss for the first character of a gap run, ss for each
+    further one: the Section 2.1 cost of the run cut where the prefix ends) and
+    records it at the prefix's end cell.  No dynamic programming: the number of
+    prefixes walked is the number of alignments, which makes 8 x 8 feasible.
+    """
+    n, m = len(T), len(P)
+    A = [[0] * (m + 1) for _ in range(n + 1)]
+    for x in range(n):
+        for y in range(m):
+            # (i, j, score, last op): i, j characters of T and P consumed from (x, y)
+            stack = [(x, y, 0, "")]
+            while stack:
+                i, j, v, last = stack.pop()
+                if i < n and j < m:
+                    w = v + sub[T[i]][P[j]]
+                    if w > A[i + 1][j + 1]:
+                        A[i + 1][j + 1] = w
+                    stack.append((i + 1, j + 1, w, "M"))
+                if i < n:
+                    w = v + ss + (sg if last != "D" else 0)
+                    if w > A[i + 1][j]:
+                        A[i + 1][j] = w
+                    stack.append((i + 1, j, w, "D"))
+                if j < m:
+                    w = v + ss + (sg if last != "I" else 0)
+                    if w > A[i][j + 1]:
+                        A[i][j + 1] = w
+                    stack.append((i, j + 1, w, "I"))
+    # an alignment ends where its last pair or gap character ends; A is at least 0 and
+    # row/column 0 hold no local alignment of a non-empty text and query prefix
+    for i in range(n + 1):
+        A[i][0] = 0
+    for j in range(m + 1):
+        A[0][j] = 0
+    for i in range(1, n + 1):
+        for j in range(1, m + 1):
+            A[i][j] = max(0, A[i][j])
+    return A

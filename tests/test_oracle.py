@@ -119,17 +119,51 @@ def test_exhaustive_small(seed):
 
 
 def test_exhaustive_eight_chars():
-    """Exhaustive search at the size limit: 8 x 8 with a gap-friendly scheme."""
+    """Exhaustive search at the size limit: 8 x 8 with a gap-friendly scheme (the
+    corner cell by per-substring enumeration, the full matrix by prefix enumeration)."""
     T = oracle.encode("GATTACAG")
     P = oracle.encode("GATACCAG")
     sub = table(4, 2, -1)
     A_or = oracle.sw_matrix(T, P, sub, -1, -1)
-    # only the corner cell at full size (the full matrix at 8x8 takes minutes)
     best = 0
     for x in range(1, 9):
         for y in range(1, 9):
             best = max(best, brute.sim(T[x - 1:], P[y - 1:], sub.tolist(), -1, -1))
     assert A_or[8, 8] == best
+    np.testing.assert_array_equal(A_or, np.array(brute.brute_A_prefixes(T, P, sub.tolist(), -1, -1)))
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_prefix_enumeration_equals_substring_enumeration(seed):
+    """The prefix enumeration visits every alignment once; on small strings its A equals
+    the per-substring enumeration's cell for cell."""
+    rng = np.random.default_rng(2000 + seed)
+    sigma = [4, 3, 2, 20][seed]
+    T = rng.integers(0, sigma, size=int(rng.integers(1, 6))).astype(np.uint8)
+    P = rng.integers(0, sigma, size=int(rng.integers(1, 6))).astype(np.uint8)
+    sa, sb, sg, ss = PAPER_SCHEMES[seed % 4]
+    sub = table(sigma, sa, sb).tolist()
+    assert brute.brute_A_prefixes(T, P, sub, sg, ss) == brute.brute_A(T, P, sub, sg, ss)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_exhaustive_full_matrix_up_to_eight(seed):
+    """Every alignment of every substring pair enumerated, strings of 7 and 8 characters,
+    the full A matrix against the oracle, under the paper's schemes and a random matrix."""
+    rng = np.random.default_rng(3000 + seed)
+    sigma = [4, 4, 2, 3, 4, 20][seed]
+    n = int(rng.integers(7, 9))
+    m = int(rng.integers(7, 9))
+    T = rng.integers(0, sigma, size=n).astype(np.uint8)
+    P = rng.integers(0, sigma, size=m).astype(np.uint8)
+    if seed == 4:
+        sub = sym_random_matrix(rng, sigma)
+        sg, ss = -2, -1
+    else:
+        sa, sb, sg, ss = PAPER_SCHEMES[seed % 4]
+        sub = table(sigma, sa, sb)
+    np.testing.assert_array_equal(oracle.sw_matrix(T, P, sub, sg, ss),
+                                  np.array(brute.brute_A_prefixes(T, P, sub.tolist(), sg, ss)))
 
 
 @pytest.mark.parametrize("seed", range(8))
