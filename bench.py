@@ -125,6 +125,35 @@ def wave_walkers(stats_list):
             "us_per_row_step": st.wide_slowest_ms * 1e3 / st.wide_slowest_rows if st.wide_slowest_rows else None}
 
 
+def level_graph_leg(alae, torch, ws, H, sc):
+    """Short single queries on the resident 1e9-base index, with the level loop host-driven
+    (level_graph 0) and device-driven from captured graphs (level_graph 8): median search time
+    of 7 after two warm-ups, and the hit counts of both, which must agree."""
+    rng = np.random.default_rng(12)
+    sync = torch.cuda.synchronize
+    out = {"note": "random DNA queries (no homolog in the text); graphs are captured in the warm-ups "
+                   "and replayed in the timed searches"}
+    for m in (100, 1000, 10000):
+        dq = torch.from_numpy(rng.integers(0, 4, size=m).astype(np.uint8)).to("cuda")
+        row = {}
+        for K in (0, 8):
+            for _ in range(2):
+                ws.search_device(dq, H, sc, level_graph=K)
+            st = alae.Stats()
+            runs = [timed(lambda: ws.search_device(dq, H, sc, stats=st, level_graph=K), sync) for _ in range(7)]
+            row[f"ms_level_graph_{K}"] = float(np.median([dt for _, dt in runs]) * 1e3)
+            row[f"hits_level_graph_{K}"] = int(runs[-1][0])
+            if K:
+                row["device_levels"] = int(st.device_levels)
+                row["levels"] = int(st.levels)
+                row["graph_captures_last_search"] = int(st.graph_captures)
+        if row["hits_level_graph_0"] != row["hits_level_graph_8"]:
+            raise SystemExit(f"level_graph changed the hit count at m={m}: {row}")
+        out[f"m={m}"] = row
+    log(f"level graph: {out}")
+    return out
+
+
 def batched_leg(alae, torch, args):
     """The headline: one batched search of 256 queries against the 1e9-base index."""
     from paper_1208_0274_amd import synth
@@ -202,6 +231,7 @@ def batched_leg(alae, torch, args):
                             "ms_alae": ta * 1e3, "ms_zero_floor_only_no_output": tb * 1e3, "speedup_at_least": tb / ta,
                             "note": ZERO_FLOOR_NOTE}
         log(f"filtering (batched sample): {res['filtering']}")
+        res["level_graph"] = level_graph_leg(alae, torch, ws, H, sc)
         del dqs
     ws.free()
     res["idx"] = idx

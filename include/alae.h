@@ -136,6 +136,8 @@ typedef struct {
     uint64_t wide_slowest_rows; /* ... and the rows it walked (a chain's rows depend on each other)  */
     uint64_t dominated_qgram;   /* seed states dropped by the q-gram domination table (Definition 1, Lemma 1) */
     double wide_slowest_start_ms; /* when the slowest wave-walker item began, after its pass began */
+    uint64_t device_levels;  /* levels run device-driven (alae_search_opts.level_graph), part of levels */
+    uint64_t graph_captures; /* batches of level slots captured as a graph (the others were replayed) */
 } alae_stats;
 
 /*
@@ -200,6 +202,15 @@ typedef struct {
     /* batched searches: queries are taken in order in groups of at most this many columns
        (a longer query alone), one trie traversal per group; 0 = 2^19 */
     uint64_t batch_columns;
+    /* device-driven levels: K in 1..64 runs the level loop in batches of K level slots with no
+       host round trip between levels, each batch a HIP graph captured once per buffer layout
+       and start parity (kept in the workspace) and replayed; -K enqueues the same batches
+       kernel by kernel (no graph).  Grids are sized for the buffers' capacities and the
+       kernels read the level's sizes and depth from device memory; a level that overflows a
+       buffer and the hand-over of the frontier's tail go back to the host.  0 (default): one
+       host round trip a level.  The hit set is the same either way.  Not in the entry point
+       that allocates nothing (there it is ignored). */
+    int32_t level_graph;
 } alae_search_opts;
 
 /* Index options; pass NULL for the defaults. */

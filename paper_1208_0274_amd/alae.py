@@ -69,7 +69,8 @@ class Stats(ctypes.Structure):
                 ("tail_chains", ctypes.c_uint64), ("tail_depth", ctypes.c_uint64),
                 ("wide_entries", ctypes.c_uint64), ("wide_max_steps", ctypes.c_uint64), ("live_ms", ctypes.c_double),
                 ("wide_slowest_ms", ctypes.c_double), ("wide_slowest_rows", ctypes.c_uint64),
-                ("dominated_qgram", ctypes.c_uint64), ("wide_slowest_start_ms", ctypes.c_double)]
+                ("dominated_qgram", ctypes.c_uint64), ("wide_slowest_start_ms", ctypes.c_double),
+                ("device_levels", ctypes.c_uint64), ("graph_captures", ctypes.c_uint64)]
 
     def reusing_ratio(self) -> float:
         """Equation 6: reused entries over accessed (reused + computed) entries."""
@@ -104,7 +105,7 @@ class SearchOpts(ctypes.Structure):
                 ("trace", ctypes.POINTER(TraceStruct)), ("partition_threshold", ctypes.c_float),
                 ("level_stage", ctypes.c_int32), ("wide_blocks_per_cu", ctypes.c_int32),
                 ("lane_waves_per_cu", ctypes.c_int32), ("no_tail_split", ctypes.c_int32),
-                ("batch_columns", ctypes.c_uint64)]
+                ("batch_columns", ctypes.c_uint64), ("level_graph", ctypes.c_int32)]
 
 
 class TuneTrial(ctypes.Structure):
@@ -262,9 +263,10 @@ def make_scoring(sa=1, sb=-3, sg=-5, ss=-2, matrix=None):
 def make_opts(stats: Stats | None = None, use_domination=True, use_score_filter=True, use_qprefix=True,
               entry_capacity=0, hit_capacity=0, zero_floor_only=False, use_reuse=False, order_model=None, trace=None,
               order_queues=0, partition_threshold=0.0, level_stage=0, wide_blocks_per_cu=0, lane_waves_per_cu=0,
-              tail_split=True, batch_columns=0):
+              tail_split=True, batch_columns=0, level_graph=0):
     o = SearchOpts()
     o.batch_columns = int(batch_columns)
+    o.level_graph = int(level_graph)
     o.no_tail_split = 0 if tail_split else 1
     o.level_stage = int(level_stage)
     o.wide_blocks_per_cu = int(wide_blocks_per_cu)

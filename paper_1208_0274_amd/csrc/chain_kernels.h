@@ -224,19 +224,11 @@ constexpr int kStartBlock = 256;
 // Four waves per SIMD (128 VGPRs, a few spilled): the random reads of the
 // suffix array and the text need the extra waves in flight more than the
 // spilled registers cost; a fifth wave spills too much.
-__global__ void __launch_bounds__(kStartBlock, 4) k_chain_start(SearchArgs a, SubTable subt, const Node *items,
-                                                             const Entry *ient, ChainQueues q, Caps caps,
-                                                             Counters *cnt, bool first_hits) {
-    __shared__ int8_t sub[20 * 20];
-    __shared__ BlockReserveLds<5, kStartBlock / 64> s_res5;
-    __shared__ BlockReserveLds<11, kStartBlock / 64> s_res11;
-    if (cnt->overflow) return;  // the whole grid: the level is run again
-    const uint64_t made = cnt->cnodes;
-    const uint32_t nitems = (uint32_t)(made < caps.cnodes ? made : caps.cnodes);
-    if ((uint64_t)blockIdx.x * kStartBlock >= nitems) return;  // the whole block
-    for (int i = threadIdx.x; i < a.sigma * a.sigma; i += blockDim.x) sub[i] = subt.s[i];
-    __syncthreads();
-    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void chain_start_tile(const SearchArgs &a, const int8_t *sub, const Node *items,
+                                                 const Entry *ient, const ChainQueues &q, const Caps &caps,
+                                                 Counters *cnt, bool first_hits, uint32_t t, uint32_t nitems,
+                                                 BlockReserveLds<5, kStartBlock / 64> &s_res5,
+                                                 BlockReserveLds<11, kStartBlock / 64> &s_res11) {
     const int32_t open = a.sg + a.ss;
     unsigned long long n_dom = 0, n_steps = 0, n_entries = 0, n_hits = 0, n_wide = 0;
     // phase 1: locate, test the states (ungapped domination), classify
@@ -496,6 +488,33 @@ __global__ void __launch_bounds__(kStartBlock, 4) k_chain_start(SearchArgs a, Su
             nd.len = cntlive;
             q.gnodes[slot] = nd;
         }
+    }
+}
+
+// The kernel: one tile per block (STRIDE false), or, for device-driven levels
+// (STRIDE true, ctl), a grid of a few blocks per CU striding over the chains.
+template <bool STRIDE>
+__global__ void __launch_bounds__(kStartBlock, 4) k_chain_start(SearchArgs a, SubTable subt, const Node *items,
+                                                             const Entry *ient, ChainQueues q, Caps caps,
+                                                             Counters *cnt, bool first_hits,
+                                                             const LevelCtl *ctl) {
+    __shared__ int8_t sub[20 * 20];
+    __shared__ BlockReserveLds<5, kStartBlock / 64> s_res5;
+    __shared__ BlockReserveLds<11, kStartBlock / 64> s_res11;
+    if (cnt->overflow) return;  // the whole grid: the level is run again
+    if (STRIDE && ctl->stop) return;  // device-driven levels: no level was begun in this slot
+    const uint64_t made = cnt->cnodes;
+    const uint32_t nitems = (uint32_t)(made < caps.cnodes ? made : caps.cnodes);
+    if ((uint64_t)blockIdx.x * kStartBlock >= nitems) return;  // the whole block
+    for (int i = threadIdx.x; i < a.sigma * a.sigma; i += blockDim.x) sub[i] = subt.s[i];
+    __syncthreads();
+    if (STRIDE) {
+        for (uint64_t b0 = (uint64_t)blockIdx.x * kStartBlock; b0 < nitems; b0 += (uint64_t)gridDim.x * kStartBlock)
+            chain_start_tile(a, sub, items, ient, q, caps, cnt, first_hits, (uint32_t)b0 + threadIdx.x, nitems,
+                             s_res5, s_res11);
+    } else {
+        chain_start_tile(a, sub, items, ient, q, caps, cnt, first_hits, blockIdx.x * kStartBlock + threadIdx.x,
+                         nitems, s_res5, s_res11);
     }
 }
 

@@ -235,6 +235,30 @@ struct Counters {
     kCounter tasks;           // child tasks of the current level (node phase)
 };
 
+// State of a device-driven run of levels (the level loop on the device, a
+// batch of level slots replayed from one captured graph).  k_level_step,
+// between the slots, commits the level before (its frontier sizes and depth)
+// and begins the next, or stops the batch; the level kernels read the sizes
+// and the depth here and do nothing once `stop` is set.
+enum : uint32_t { kStopNone = 0, kStopDone = 1, kStopSplit = 2, kStopOverflow = 3, kStopLarge = 4 };
+// Device-driven levels take frontiers of at most this many nodes (their grids
+// are sized for it; a larger level goes back to the host-driven loop, whose
+// per-level round trip is small beside its kernels).
+constexpr unsigned long long kDeviceFrontier = 1ull << 16;
+struct LevelCtl {
+    unsigned long long nn, nlw;   // nodes (lane rows, long rows) of the level being expanded
+    unsigned long long peak;      // largest frontier seen (nodes of a level)
+    unsigned long long split_below;  // the frontier's tail goes to the chain walkers at this size
+    unsigned long long max_depth; // deepest level that made nodes or chains
+    int32_t depth;                // depth of the frontier being expanded
+    int32_t d1;                   // depth of its children
+    int32_t lmax;
+    uint32_t stop;                // kStop*: the batch's remaining slots do nothing
+    uint32_t pending;             // a level was begun and not yet committed
+    uint32_t ran;                 // levels committed by this batch
+    Counters snap;                // the counters as the pending level found them (for a rerun)
+};
+
 // Key of an unused hit slot: sorts after every real (column, text end) key.
 constexpr uint64_t kPadKey = ~0ull;
 

@@ -64,10 +64,10 @@ static_assert(sizeof(ChildTask) == 16, "child task is 16 bytes");
 
 constexpr int kTaskBlock = 1024;
 
-__global__ void __launch_bounds__(kTaskBlock) k_level_tasks(SearchArgs a, const Node *nodes, uint32_t nn,
-                                                            ChildTask *tasks, Caps caps, Counters *cnt) {
-    __shared__ BlockReserveLds<4, kTaskBlock / 64> s_res;
-    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+// The child tasks of nodes t - threadIdx.x .. of one block (t = this lane's node).
+__device__ inline void level_tasks_tile(const SearchArgs &a, const Node *nodes, uint32_t nn, uint32_t t,
+                                        ChildTask *tasks, const Caps &caps, Counters *cnt,
+                                        BlockReserveLds<4, kTaskBlock / 64> &s_res) {
     const bool active = t < nn;
     uint32_t mask = 0, nocc = 0, nin = 0;
     Node nd{0, 0, 0, 0};
@@ -118,6 +118,26 @@ __global__ void __launch_bounds__(kTaskBlock) k_level_tasks(SearchArgs a, const 
             if (base < caps.tasks) tasks[base] = ChildTask{lo, hi, nd.off, nd.len | ((uint32_t)c << 24)};
             ++base;
         }
+    }
+}
+
+// One lane per node.  The host-driven loop launches a block per 1024 nodes
+// (STRIDE false); for device-driven levels (STRIDE true, ctl) the node count
+// is read from ctl and a grid of a few blocks per CU strides over the nodes.
+// (Two instantiations: the loop costs the one-shot form registers.)
+template <bool STRIDE>
+__global__ void __launch_bounds__(kTaskBlock) k_level_tasks(SearchArgs a, const Node *nodes, uint32_t nn,
+                                                            ChildTask *tasks, Caps caps, Counters *cnt,
+                                                            const LevelCtl *ctl) {
+    __shared__ BlockReserveLds<4, kTaskBlock / 64> s_res;
+    if (STRIDE) {
+        if (ctl->stop) return;  // the whole grid
+        nn = (uint32_t)ctl->nn;
+        for (uint64_t b0 = (uint64_t)blockIdx.x * kTaskBlock; b0 < nn; b0 += (uint64_t)gridDim.x * kTaskBlock)
+            level_tasks_tile(a, nodes, nn, (uint32_t)b0 + threadIdx.x, tasks, caps, cnt, s_res);
+    } else {
+        if ((uint64_t)blockIdx.x * kTaskBlock >= nn) return;  // the whole block
+        level_tasks_tile(a, nodes, nn, blockIdx.x * kTaskBlock + threadIdx.x, tasks, caps, cnt, s_res);
     }
 }
 
@@ -229,17 +249,32 @@ __device__ inline void expand_child_tile(const SearchArgs &a, const Entry *ent, 
 
 // One child row per lane, staged in LDS (STAGE entries a lane).  The grid is
 // sized for the most tasks a level can have (the host does not wait for the
-// node phase's count); blocks past the tasks it made leave at once.
-template <int STAGE>
+// node phase's count); blocks past the tasks it made leave at once.  STRIDE
+// (device-driven levels, ctl): a grid of a few blocks per CU strides over the
+// tasks.
+template <int STAGE, bool STRIDE>
 __global__ void __launch_bounds__(kLevelBlock) k_expand_children(SearchArgs a, const Entry *ent,
                                                                  const ChildTask *tasks, int32_t d1, LevelOut o,
-                                                                 Caps caps, Counters *cnt) {
+                                                                 Caps caps, Counters *cnt, const LevelCtl *ctl) {
     __shared__ uint32_t s_stage[kLevelBlock * stage_words(STAGE)];
     __shared__ BlockReserveLds<12, kLevelBlock / 64> s_res;
-    const uint64_t ntasks = cnt->tasks;  // written by the node phase before this launch
-    const uint64_t base = (uint64_t)blockIdx.x * kLevelBlock;
-    if (base >= ntasks) return;  // the whole block
-    expand_child_tile<STAGE>(a, ent, tasks, d1, o, caps, cnt, base + threadIdx.x, ntasks, s_stage, s_res);
+    if (STRIDE) {  // device-driven levels: the depth is read there
+        if (ctl->stop) return;
+        d1 = ctl->d1;
+    }
+    // written by the node phase before this launch (beyond caps.tasks it overflowed and
+    // wrote no more: the level is run again)
+    const uint64_t made = cnt->tasks;
+    const uint64_t ntasks = made < caps.tasks ? made : caps.tasks;
+    if (STRIDE) {
+        for (uint64_t base = (uint64_t)blockIdx.x * kLevelBlock; base < ntasks;
+             base += (uint64_t)gridDim.x * kLevelBlock)
+            expand_child_tile<STAGE>(a, ent, tasks, d1, o, caps, cnt, base + threadIdx.x, ntasks, s_stage, s_res);
+    } else {
+        const uint64_t base = (uint64_t)blockIdx.x * kLevelBlock;
+        if (base >= ntasks) return;  // the whole block
+        expand_child_tile<STAGE>(a, ent, tasks, d1, o, caps, cnt, base + threadIdx.x, ntasks, s_stage, s_res);
+    }
 }
 
 // Hits of a staged row for every occurrence [lo, hi] (wave-parallel).
@@ -273,7 +308,13 @@ __device__ inline void emit_row_hits_multi(const SearchArgs &a, const Entry *row
 // a longer child row raises kOvStageRow with its length in stage_need.
 __global__ void __launch_bounds__(64) k_expand_level_wide(SearchArgs a, const Node *wnodes, uint32_t nw,
                                                           const Entry *ent, int32_t d1, LevelOut o, Caps caps,
-                                                          Counters *cnt, Entry *stage) {
+                                                          Counters *cnt, Entry *stage, const LevelCtl *ctl) {
+    if (ctl) {  // device-driven levels: the node count and the depth are read there
+        if (ctl->stop) return;
+        nw = (uint32_t)ctl->nlw;
+        d1 = ctl->d1;
+    }
+    if (blockIdx.x >= nw) return;  // a block with no node (its statistics are all zero)
     const int lane = threadIdx.x & 63;
     Entry *buf = stage + (uint64_t)blockIdx.x * caps.srow;
     HitRes hr = {0, 0, 0};

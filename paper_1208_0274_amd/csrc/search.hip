@@ -19,6 +19,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstddef>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -371,6 +372,67 @@ __global__ void __launch_bounds__(256) k_split_nodes(const Node *nodes, uint32_t
     for (uint32_t i = 0; i < r; ++i) items[first + i] = Node{nd.lo + i, depth, nd.off, nd.len};
 }
 
+// The frontier's tail goes to the chain walkers once a level has at most
+// kSplitNodes nodes and a kSplitShrink-th of the largest level (so that the
+// levels have done the shared work), and makes at most kSplitChains chains.
+constexpr uint64_t kSplitNodes = 1ull << 15, kSplitChains = 1ull << 17, kSplitShrink = 64;
+
+// Between two slots of a device-driven batch of levels (one block): commit
+// the level the previous slot ran (or stop the batch on its overflow), then,
+// when `begin`, test the loop's end and the tail split as the host loop does
+// and begin the next level: keep the counters for a rerun and clear the
+// per-level ones.
+__global__ void __launch_bounds__(64) k_level_step(LevelCtl *ctl, Counters *cnt, bool begin) {
+    __shared__ uint32_t s_go;
+    if (threadIdx.x == 0) {
+        uint32_t go = 0;
+        if (ctl->stop == kStopNone) {
+            if (ctl->pending) {
+                if (cnt->overflow) {
+                    ctl->stop = kStopOverflow;  // the host grows what overflowed and runs the level again
+                } else {
+                    const unsigned long long nn = cnt->nodes, nlw = cnt->lwnodes;
+                    if (nn || nlw || cnt->cnodes) ctl->max_depth = (unsigned long long)ctl->d1;
+                    ctl->depth = ctl->d1;
+                    ctl->nn = nn;
+                    ctl->nlw = nlw;
+                    ctl->pending = 0;
+                    ctl->ran += 1;
+                }
+            }
+            if (begin && ctl->stop == kStopNone) {
+                const unsigned long long f = ctl->nn + ctl->nlw;
+                if (f == 0 || ctl->depth >= ctl->lmax) {
+                    ctl->stop = kStopDone;
+                } else if (f > kDeviceFrontier) {
+                    ctl->stop = kStopLarge;  // the host-driven loop takes the large levels
+                } else {
+                    if (f > ctl->peak) ctl->peak = f;
+                    if (f <= ctl->split_below && f * kSplitShrink <= ctl->peak)
+                        ctl->stop = kStopSplit;  // the host hands the tail to the chain walkers
+                    else
+                        go = 1;
+                }
+            }
+        }
+        s_go = go;
+    }
+    __syncthreads();
+    if (!s_go) return;
+    const unsigned long long *src = reinterpret_cast<const unsigned long long *>(cnt);
+    unsigned long long *dst = reinterpret_cast<unsigned long long *>(&ctl->snap);
+    for (uint32_t i = threadIdx.x; i < sizeof(Counters) / sizeof(unsigned long long); i += blockDim.x) dst[i] = src[i];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        cnt->nodes = cnt->entries = cnt->lwnodes = cnt->cnodes = cnt->centries = 0;
+        cnt->overflow = 0;
+        cnt->stage_need = 0;
+        cnt->tasks = 0;
+        ctl->d1 = ctl->depth + 1;
+        ctl->pending = 1;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Host driver
 // ---------------------------------------------------------------------------
@@ -581,6 +643,12 @@ struct alae_workspace {
     hipEvent_t evks = nullptr;                  // after all level kernels, before the chain start
     // fixed device region every buffer is cut from (callers that cannot allocate)
     FixedRegion region{nullptr, 0, 0};
+    // device-driven levels: their state, and one captured batch of level slots per
+    // start parity with the launch parameters it was captured with
+    LevelCtl *d_ctl = nullptr;
+    LevelCtl *h_ctl = nullptr;
+    hipGraphExec_t lg_exec[2] = {nullptr, nullptr};
+    std::vector<uint8_t> lg_sig[2];
 };
 
 namespace alae {
@@ -590,6 +658,10 @@ static void ws_release_buffers(alae_workspace *ws);
 static void ws_release(alae_workspace *ws) {
     ws_release_buffers(ws);
     hipFree(ws->qdom);  // kept by ws_release_buffers when small
+    for (int i = 0; i < 2; ++i)
+        if (ws->lg_exec[i]) hipGraphExecDestroy(ws->lg_exec[i]);
+    hipFree(ws->d_ctl);
+    if (ws->h_ctl) hipHostFree(ws->h_ctl);
     hipFree(ws->d_cnt);
     if (ws->h_cnt) hipHostFree(ws->h_cnt);
     if (ws->s2) hipStreamDestroy(ws->s2);
@@ -682,6 +754,11 @@ static void ws_release_buffers(alae_workspace *ws) {
     fresh.ev_join = ws->ev_join;
     fresh.s2 = ws->s2;
     fresh.region = ws->region;
+    // the captured level batches name the freed buffers: the next search captures them again
+    for (int i = 0; i < 2; ++i)
+        if (ws->lg_exec[i]) hipGraphExecDestroy(ws->lg_exec[i]);
+    fresh.d_ctl = ws->d_ctl;
+    fresh.h_ctl = ws->h_ctl;
     if (keep_qdom) {
         fresh.qdom = ws->qdom;
         fresh.qdom_cap = ws->qdom_cap;
@@ -1103,6 +1180,9 @@ static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64
     hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ws->device);
     // launch shapes (alae_search_opts; validated by the entry points)
     const int level_stage = (opts && opts->level_stage) ? opts->level_stage : kStageDefault;
+    // device-driven levels (not in a fixed region, whose buffers cannot be sized for them)
+    const int32_t level_batch = (opts && !t_region) ? opts->level_graph : 0;
+    uint64_t device_levels = 0, graph_captures = 0;
     const uint32_t wide_bpc = (opts && opts->wide_blocks_per_cu) ? (uint32_t)opts->wide_blocks_per_cu : 3u;
     const uint32_t lane_wpc = (opts && opts->lane_waves_per_cu) ? (uint32_t)opts->lane_waves_per_cu : 8u;
     const uint32_t max_waves = (uint32_t)cus * lane_wpc;
@@ -1208,11 +1288,173 @@ static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64
     static const bool trace = getenv("ALAE_TRACE") != nullptr;
     uint64_t nlw = nlw0;  // nodes of the current level with long rows (in ws->lwide[cur])
     // The frontier's tail goes to the chain walkers (k_split_nodes) once it is
-    // small (at most kSplitNodes nodes, and a 64th of its largest level, so
-    // that the levels have done the shared work) and has few occurrences.
-    constexpr uint64_t kSplitNodes = 1ull << 15, kSplitChains = 1ull << 17, kSplitShrink = 64;
+    // small and has few occurrences (kSplitNodes, kSplitShrink, kSplitChains).
     uint64_t peak_nodes = nn + nlw, split_below = (opts && opts->no_tail_split) ? 0 : kSplitNodes;
     uint64_t tail_chains = 0, tail_depth = 0;
+    // One device-driven batch (level_batch != 0) from the current frontier.  On
+    // return the host state (frontier, depth, parity, counters) is that after the
+    // levels the batch committed; `rerun`: the next level overflowed, its buffers
+    // are grown and the host copy of the counters is the one it started from.
+    auto run_level_batch = [&](bool &rerun) -> alae_status {
+        rerun = false;
+        const uint32_t K = (uint32_t)(level_batch < 0 ? -level_batch : level_batch);
+        if (!ws->d_ctl) {
+            HIP_TRY(hipMalloc(&ws->d_ctl, sizeof(LevelCtl)));
+            HIP_TRY(hipHostMalloc(&ws->h_ctl, sizeof(LevelCtl), hipHostMallocDefault));
+        }
+        // child tasks of the largest frontier a slot expands
+        if ((st = grow(ws->tasks, ws->task_cap, (uint64_t)sigma * kDeviceFrontier, false, 0, s)) != ALAE_OK)
+            return st;
+        uint32_t wblocks[2];
+        for (int p = 0; p < 2; ++p)
+            wblocks[p] = (uint32_t)std::max<uint64_t>(
+                1, std::min<uint64_t>({ws->lwide_cap[p], kDeviceFrontier, (uint64_t)cus * 16, stage_budget / srow}));
+        if ((st = grow(ws->stage, ws->stage_cap, (uint64_t)std::max(wblocks[0], wblocks[1]) * srow, false, 0, s)) !=
+            ALAE_OK)
+            return st;
+        Caps cp[2];  // the caps of a slot whose output parity is p
+        set_caps(0);
+        cp[0] = caps;
+        set_caps(1);
+        cp[1] = caps;
+        // grids for a frontier of kDeviceFrontier nodes (sigma children each), fewer when the
+        // buffers hold less; the kernels stride over anything beyond
+        const uint64_t most_nodes = std::min<uint64_t>(kDeviceFrontier, std::max(ws->node_cap[0], ws->node_cap[1]));
+        auto sgrid = [&](uint64_t cap, uint64_t want, uint64_t per_block) {
+            return (uint32_t)std::max<uint64_t>(1, (std::min(cap, want) + per_block - 1) / per_block);
+        };
+        const uint32_t g_tasks = sgrid(ws->task_cap, (uint64_t)sigma * most_nodes, kLevelBlock);
+        const uint32_t g_chains = sgrid(ws->cnode_cap, (uint64_t)sigma * most_nodes, kStartBlock);
+        const ChainQueues cq{ws->gnodes, ws->gents, ws->wnodes, ws->wents, ws->hkeys, ws->hscores};
+        auto enqueue = [&](int p0, hipStream_t es) {
+            for (uint32_t j = 0; j < K; ++j) {
+                const int p = p0 ^ (int)(j & 1u), q = p ^ 1;
+                LevelOut o;
+                o.onodes = ws->nodes[q];
+                o.owide = ws->lwide[q];
+                o.oent = ws->ents[q];
+                o.chains = ws->cnodes;
+                o.cent = ws->cents;
+                o.hkeys = ws->hkeys;
+                o.hscores = ws->hscores;
+                o.node_base = o.wide_base = o.ent_base = o.chain_base = o.cent_base = o.hit_base = 0;
+                const uint32_t g_nodes = sgrid(ws->node_cap[p], most_nodes, kTaskBlock);
+                k_level_step<<<1, 64, 0, es>>>(ws->d_ctl, ws->d_cnt, true);
+                k_level_tasks<true><<<g_nodes, kTaskBlock, 0, es>>>(a, ws->nodes[p], 0u, ws->tasks, cp[q], ws->d_cnt,
+                                                             ws->d_ctl);
+                if (level_stage == 2)
+                    k_expand_children<2, true><<<g_tasks, kLevelBlock, 0, es>>>(a, ws->ents[p], ws->tasks, 0, o, cp[q],
+                                                                         ws->d_cnt, ws->d_ctl);
+                else if (level_stage == 8)
+                    k_expand_children<8, true><<<g_tasks, kLevelBlock, 0, es>>>(a, ws->ents[p], ws->tasks, 0, o, cp[q],
+                                                                         ws->d_cnt, ws->d_ctl);
+                else
+                    k_expand_children<4, true><<<g_tasks, kLevelBlock, 0, es>>>(a, ws->ents[p], ws->tasks, 0, o, cp[q],
+                                                                         ws->d_cnt, ws->d_ctl);
+                k_expand_level_wide<<<wblocks[p], 64, 0, es>>>(a, ws->lwide[p], 0u, ws->ents[p], 0, o, cp[q],
+                                                              ws->d_cnt, ws->stage, ws->d_ctl);
+                k_chain_start<true><<<g_chains, kStartBlock, 0, es>>>(a, sub, ws->cnodes, ws->cents, cq, cp[q], ws->d_cnt,
+                                                               true, ws->d_ctl);
+            }
+            k_level_step<<<1, 64, 0, es>>>(ws->d_ctl, ws->d_cnt, false);  // commits the last slot's level
+        };
+        LevelCtl &h = *ws->h_ctl;
+        h.nn = nn;
+        h.nlw = nlw;
+        h.peak = peak_nodes;
+        h.split_below = split_below;
+        h.max_depth = max_depth;
+        h.depth = depth;
+        h.d1 = depth + 1;
+        h.lmax = (int32_t)lmax;
+        h.stop = kStopNone;
+        h.pending = 0;
+        h.ran = 0;
+        HIP_TRY(hipMemcpyAsync(ws->d_ctl, ws->h_ctl, offsetof(LevelCtl, snap), hipMemcpyHostToDevice, s));
+        HIP_TRY(hipEventRecord(ws->evk0, s));
+        if (level_batch > 0) {
+            // the launch parameters of the batch: a captured graph is replayed while they hold
+            std::vector<uint8_t> sig;
+            auto put = [&](const void *v, size_t n) {
+                const uint8_t *b = static_cast<const uint8_t *>(v);
+                sig.insert(sig.end(), b, b + n);
+            };
+            put(&K, sizeof K);
+            put(&level_stage, sizeof level_stage);
+            put(&a, sizeof a);
+            put(&sub, sizeof sub);
+            put(cp, sizeof cp);
+            put(wblocks, sizeof wblocks);
+            put(&g_tasks, sizeof g_tasks);
+            put(&g_chains, sizeof g_chains);
+            const void *ptrs[] = {ws->nodes[0], ws->nodes[1], ws->ents[0],   ws->ents[1],  ws->lwide[0],
+                                  ws->lwide[1], ws->tasks,    ws->cnodes,    ws->cents,    ws->gnodes,
+                                  ws->gents,    ws->wnodes,   ws->wents,     ws->hkeys,    ws->hscores,
+                                  ws->stage,    ws->d_ctl,    ws->d_cnt};
+            put(ptrs, sizeof ptrs);
+            const uint64_t ncap[2] = {ws->node_cap[0], ws->node_cap[1]};
+            put(ncap, sizeof ncap);
+            hipGraphExec_t &ex = ws->lg_exec[cur];
+            if (!ex || ws->lg_sig[cur] != sig) {
+                if (ex) {
+                    HIP_TRY(hipGraphExecDestroy(ex));
+                    ex = nullptr;
+                }
+                // captured on the second stream (idle during the levels; the caller's stream
+                // may be the null stream, which cannot be captured), replayed on s
+                hipGraph_t g = nullptr;
+                HIP_TRY(hipStreamBeginCapture(ws->s2, hipStreamCaptureModeRelaxed));
+                enqueue(cur, ws->s2);
+                const hipError_t ce = hipStreamEndCapture(ws->s2, &g);
+                if (ce != hipSuccess) {
+                    if (g) hipGraphDestroy(g);
+                    set_error("capturing the level batch failed: %s", hipGetErrorString(ce));
+                    return ALAE_E_DEVICE;
+                }
+                const hipError_t ie = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+                hipGraphDestroy(g);
+                if (ie != hipSuccess) {
+                    ex = nullptr;
+                    set_error("instantiating the level batch failed: %s", hipGetErrorString(ie));
+                    return ALAE_E_DEVICE;
+                }
+                ws->lg_sig[cur] = std::move(sig);
+                ++graph_captures;
+            }
+            HIP_TRY(hipGraphLaunch(ex, s));
+        } else {
+            enqueue(cur, s);
+        }
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipEventRecord(ws->evk1, s));
+        HIP_TRY(hipMemcpyAsync(ws->h_ctl, ws->d_ctl, sizeof(LevelCtl), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(ws->h_cnt, ws->d_cnt, sizeof(Counters), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        float kms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&kms, ws->evk0, ws->evk1));
+        expand_ms += kms;
+        ++launches;
+        const LevelCtl &r = *ws->h_ctl;
+        levels += r.ran;
+        level_launches += r.ran;
+        device_levels += r.ran;
+        if (r.ran & 1u) cur ^= 1;
+        nn = r.nn;
+        nlw = r.nlw;
+        depth = r.depth;
+        peak_nodes = r.peak;
+        max_depth = r.max_depth;
+        if (trace)
+            fprintf(stderr, "[alae] device levels to depth %d: %u levels, %llu+%llu nodes, stop %u; %.3f ms\n",
+                    depth, r.ran, (unsigned long long)nn, (unsigned long long)nlw, r.stop, kms);
+        if (r.stop == kStopOverflow) {
+            ++retries;
+            if ((st = grow_overflowed(*ws->h_cnt, r.snap, cur ^ 1)) != ALAE_OK) return st;
+            *ws->h_cnt = r.snap;  // the counters the level found
+            rerun = true;
+        }
+        return ALAE_OK;
+    };
     while ((nn > 0 || nlw > 0) && depth < lmax) {
         peak_nodes = std::max<uint64_t>(peak_nodes, nn + nlw);
         if (nn + nlw <= split_below && (nn + nlw) * kSplitShrink <= peak_nodes) {
@@ -1242,8 +1484,8 @@ static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64
                     const ChainQueues q{ws->gnodes, ws->gents, ws->wnodes, ws->wents, ws->hkeys, ws->hscores};
                     HIP_TRY(hipEventRecord(ws->evk0, s));
                     // the level kernels wrote these rows' hits at every occurrence already
-                    k_chain_start<<<(uint32_t)((items + kStartBlock - 1) / kStartBlock), kStartBlock, 0, s>>>(
-                        a, sub, ws->cnodes, ws->ents[cur], q, caps, ws->d_cnt, false);
+                    k_chain_start<false><<<(uint32_t)((items + kStartBlock - 1) / kStartBlock), kStartBlock, 0, s>>>(
+                        a, sub, ws->cnodes, ws->ents[cur], q, caps, ws->d_cnt, false, nullptr);
                     double ums = 0.0;
                     if ((st = timed(ums)) != ALAE_OK) return st;
                     start_ms += ums;
@@ -1260,6 +1502,16 @@ static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64
                 nn = nlw = 0;
                 break;
             }
+        }
+        if (level_batch != 0 && nn + nlw <= kDeviceFrontier) {
+            // Device-driven levels: a batch of K level slots, each k_level_step and the
+            // level's kernels with grids sized for a frontier of kDeviceFrontier nodes, then
+            // one host round trip.  A level that overflowed is run again below by the host
+            // path (its buffers grown); the tail split is taken at the top of the loop, and
+            // a larger frontier by the host-driven loop.
+            bool rerun = false;
+            if ((st = run_level_batch(rerun)) != ALAE_OK) return st;
+            if (!rerun) continue;
         }
         const int32_t d1 = depth + 1;
         const int nxt = cur ^ 1;
@@ -1290,19 +1542,19 @@ static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64
             HIP_TRY(hipEventRecord(ws->evk0, s));
             if (nn > 0) {
                 // node phase (child tasks), then one child row per lane
-                k_level_tasks<<<(uint32_t)((nn + kTaskBlock - 1) / kTaskBlock), kTaskBlock, 0, s>>>(a, ws->nodes[cur], (uint32_t)nn,
-                                                                          ws->tasks, caps, ws->d_cnt);
+                k_level_tasks<false><<<(uint32_t)((nn + kTaskBlock - 1) / kTaskBlock), kTaskBlock, 0, s>>>(a, ws->nodes[cur], (uint32_t)nn,
+                                                                          ws->tasks, caps, ws->d_cnt, nullptr);
                 const uint64_t maxtasks = (uint64_t)sigma * nn;
                 const uint32_t cblocks = (uint32_t)((maxtasks + kLevelBlock - 1) / kLevelBlock);
                 if (level_stage == 2)
-                    k_expand_children<2><<<cblocks, kLevelBlock, 0, s>>>(a, ws->ents[cur], ws->tasks, d1, o, caps,
-                                                                         ws->d_cnt);
+                    k_expand_children<2, false><<<cblocks, kLevelBlock, 0, s>>>(a, ws->ents[cur], ws->tasks, d1, o, caps,
+                                                                         ws->d_cnt, nullptr);
                 else if (level_stage == 8)
-                    k_expand_children<8><<<cblocks, kLevelBlock, 0, s>>>(a, ws->ents[cur], ws->tasks, d1, o, caps,
-                                                                         ws->d_cnt);
+                    k_expand_children<8, false><<<cblocks, kLevelBlock, 0, s>>>(a, ws->ents[cur], ws->tasks, d1, o, caps,
+                                                                         ws->d_cnt, nullptr);
                 else
-                    k_expand_children<4><<<cblocks, kLevelBlock, 0, s>>>(a, ws->ents[cur], ws->tasks, d1, o, caps,
-                                                                         ws->d_cnt);
+                    k_expand_children<4, false><<<cblocks, kLevelBlock, 0, s>>>(a, ws->ents[cur], ws->tasks, d1, o, caps,
+                                                                         ws->d_cnt, nullptr);
             }
             HIP_TRY(hipEventRecord(ws->evkm, s));
             if (nlw > 0) {
@@ -1312,7 +1564,7 @@ static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64
                     1, std::min<uint64_t>({nlw, (uint64_t)cus * 16, stage_budget / srow}));
                 if ((st = grow(ws->stage, ws->stage_cap, (uint64_t)blocks * srow, false, 0, s)) != ALAE_OK) return st;
                 k_expand_level_wide<<<blocks, 64, 0, s>>>(a, ws->lwide[cur], (uint32_t)nlw, ws->ents[cur], d1, o,
-                                                          caps, ws->d_cnt, ws->stage);
+                                                          caps, ws->d_cnt, ws->stage, nullptr);
             }
             // the chains this level makes, right behind it (one host round trip a level)
             HIP_TRY(hipEventRecord(ws->evks, s));
@@ -1320,8 +1572,8 @@ static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64
                 const uint64_t most = std::min<uint64_t>((uint64_t)sigma * (nn + nlw), caps.cnodes);
                 if (most > 0) {
                     ChainQueues q{ws->gnodes, ws->gents, ws->wnodes, ws->wents, ws->hkeys, ws->hscores};
-                    k_chain_start<<<(uint32_t)((most + kStartBlock - 1) / kStartBlock), kStartBlock, 0, s>>>(
-                        a, sub, ws->cnodes, ws->cents, q, caps, ws->d_cnt, true);
+                    k_chain_start<false><<<(uint32_t)((most + kStartBlock - 1) / kStartBlock), kStartBlock, 0, s>>>(
+                        a, sub, ws->cnodes, ws->cents, q, caps, ws->d_cnt, true, nullptr);
                 }
             }
             double unit_ms = 0.0;
@@ -1731,6 +1983,8 @@ static alae_status run_search(alae_workspace *ws, const uint8_t *d_query, uint64
         o->wide_slowest_start_ms = (double)((c.st_wide_slow >> 18) & ((1ull << 20) - 1)) * 1e-3;
         o->wide_slowest_rows = c.st_wide_slow & ((1ull << 18) - 1);
         o->live_ms = live_ms;
+        o->device_levels = device_levels;
+        o->graph_captures = graph_captures;
     }
     return ALAE_OK;
 }
@@ -1742,8 +1996,11 @@ static bool launch_shapes_ok(const alae_search_opts *o, const char *where) {
     if (!o) return true;
     const bool ok = (o->level_stage == 0 || o->level_stage == 2 || o->level_stage == 4 || o->level_stage == 8) &&
                     o->wide_blocks_per_cu >= 0 && o->wide_blocks_per_cu <= 8 && o->lane_waves_per_cu >= 0 &&
-                    o->lane_waves_per_cu <= 16;
-    if (!ok) set_error("%s: level_stage must be 0, 2, 4 or 8, wide_blocks_per_cu 0..8, lane_waves_per_cu 0..16", where);
+                    o->lane_waves_per_cu <= 16 && o->level_graph >= -64 && o->level_graph <= 64;
+    if (!ok)
+        set_error("%s: level_stage must be 0, 2, 4 or 8, wide_blocks_per_cu 0..8, lane_waves_per_cu 0..16, "
+                  "level_graph -64..64",
+                  where);
     return ok;
 }
 
@@ -2047,6 +2304,8 @@ static void add_stats(alae_stats &to, const alae_stats &x) {
     ALAE_ADD(wide_entries);
     ALAE_ADD(dominated_qgram);
     ALAE_ADD(live_ms);
+    ALAE_ADD(device_levels);
+    ALAE_ADD(graph_captures);
 #undef ALAE_ADD
     to.max_depth = std::max(to.max_depth, x.max_depth);
     to.tail_depth = std::max(to.tail_depth, x.tail_depth);
