@@ -459,7 +459,7 @@ def main():
         "roofline": roofline(stats, "batched"),
         "wave_walkers": wave_walkers(stats),
     }
-    for k in ("single_query_loop", "filtering"):
+    for k in ("single_query_loop", "filtering", "level_graph"):
         if k in b:
             out[k] = b[k]
     if not args.no_extras:
