@@ -250,10 +250,12 @@ __device__ inline void expand_child_tile(const SearchArgs &a, const Entry *ent, 
 // One child row per lane, staged in LDS (STAGE entries a lane).  The grid is
 // sized for the most tasks a level can have (the host does not wait for the
 // node phase's count); blocks past the tasks it made leave at once.  STRIDE
-// (device-driven levels, ctl): a grid of a few blocks per CU strides over the
-// tasks.
+// (device-driven levels, ctl): a grid sized for a small frontier strides over
+// the tasks.  Seven blocks per CU: the four-entry stage leaves LDS for seven,
+// and the row update fits the 72 registers that allows without spilling (the
+// waves wait on dependent reads most of the time; the seventh hides more).
 template <int STAGE, bool STRIDE>
-__global__ void __launch_bounds__(kLevelBlock) k_expand_children(SearchArgs a, const Entry *ent,
+__global__ void __launch_bounds__(kLevelBlock, 7) k_expand_children(SearchArgs a, const Entry *ent,
                                                                  const ChildTask *tasks, int32_t d1, LevelOut o,
                                                                  Caps caps, Counters *cnt, const LevelCtl *ctl) {
     __shared__ uint32_t s_stage[kLevelBlock * stage_words(STAGE)];
