@@ -366,8 +366,8 @@ alae_status alae_search_device(alae_workspace *ws, const uint8_t *d_query_codes,
  * Launch-shape autotuner.  Times searches of one device-resident query (as in
  * alae_search_device) with the launch shapes of alae_search_opts changed one
  * at a time (coordinate descent: wave-walker blocks per CU in {2,3,4,6},
- * lane-walker waves per CU in {4,8,12}, child-phase LDS stage in {2,4,8}; a
- * change is kept when it is at least 1% faster), each timing the mean device
+ * lane-walker waves per CU in {4,8,12}, child-phase LDS stage in {2,4,8},
+ * level_graph in {0,8}; a change is kept when it is at least 1% faster), each timing the mean device
  * time of `reps` searches after one warm-up search.  opts is in/out: its other
  * fields are used as given (trace is ignored) and the chosen shapes are
  * written back.  Every trial must return the same hit count, otherwise
@@ -376,6 +376,7 @@ alae_status alae_search_device(alae_workspace *ws, const uint8_t *d_query_codes,
 typedef struct {
     int32_t level_stage, wide_blocks_per_cu, lane_waves_per_cu;
     double ms;  /* mean device time of a search with these shapes */
+    int32_t level_graph;
 } alae_tune_trial;
 typedef struct {
     double default_ms;         /* with the shapes passed in (0 = defaults)  */

@@ -110,7 +110,7 @@ class SearchOpts(ctypes.Structure):
 
 class TuneTrial(ctypes.Structure):
     _fields_ = [("level_stage", ctypes.c_int32), ("wide_blocks_per_cu", ctypes.c_int32),
-                ("lane_waves_per_cu", ctypes.c_int32), ("ms", ctypes.c_double)]
+                ("lane_waves_per_cu", ctypes.c_int32), ("ms", ctypes.c_double), ("level_graph", ctypes.c_int32)]
 
 
 class TuneReport(ctypes.Structure):
@@ -575,7 +575,7 @@ class Workspace:
 
     def autotune(self, d_query, H: int, scoring: Scoring | None = None, reps: int = 2, stream=None, **opt):
         """Pick the launch shapes for this query (alae_autotune).  Returns (shapes, report): shapes is a
-        dict of the three chosen options, to pass to search_device; report has the timings."""
+        dict of the four chosen options, to pass to search_device; report has the timings."""
         sc = scoring if scoring is not None else make_scoring()
         opts = make_opts(**opt)
         rep = TuneReport()
@@ -583,9 +583,10 @@ class Workspace:
         _check(_lib.alae_autotune(self._h, _vp(d_query.data_ptr()), int(d_query.numel()), ctypes.byref(sc), int(H),
                                   ctypes.byref(opts), int(reps), sptr, ctypes.byref(rep)), "alae_autotune")
         shapes = {"level_stage": opts.level_stage, "wide_blocks_per_cu": opts.wide_blocks_per_cu,
-                  "lane_waves_per_cu": opts.lane_waves_per_cu}
+                  "lane_waves_per_cu": opts.lane_waves_per_cu, "level_graph": opts.level_graph}
         trials = [{"level_stage": r.level_stage, "wide_blocks_per_cu": r.wide_blocks_per_cu,
-                   "lane_waves_per_cu": r.lane_waves_per_cu, "ms": r.ms} for r in rep.trial[:rep.trials]]
+                   "lane_waves_per_cu": r.lane_waves_per_cu, "level_graph": r.level_graph, "ms": r.ms}
+                  for r in rep.trial[:rep.trials]]
         return shapes, {"default_ms": rep.default_ms, "best_ms": rep.best_ms, "trials": trials}
 
     def search_device_batch(self, d_queries, lens, H: int, scoring: Scoring | None = None,

@@ -2224,6 +2224,7 @@ alae_status alae_autotune(alae_workspace *ws, const uint8_t *d_query_codes, size
             tr.level_stage = c.level_stage;
             tr.wide_blocks_per_cu = c.wide_blocks_per_cu;
             tr.lane_waves_per_cu = c.lane_waves_per_cu;
+            tr.level_graph = c.level_graph;
             tr.ms = *ms;
         }
         return ALAE_OK;
@@ -2235,16 +2236,22 @@ alae_status alae_autotune(alae_workspace *ws, const uint8_t *d_query_codes, size
     double best_ms = 0.0;
     if ((st = timed(o, &best_ms)) != ALAE_OK) return st;
     report->default_ms = best_ms;
-    // coordinate descent over the three shapes; a change must win by 1%
-    const int32_t wide_c[] = {2, 3, 4, 6}, lane_c[] = {4, 8, 12}, stage_c[] = {2, 4, 8};
-    for (int pass = 0; pass < 3; ++pass) {
-        const int32_t *cand = pass == 0 ? wide_c : pass == 1 ? lane_c : stage_c;
-        const int nc = pass == 0 ? 4 : 3;
-        const int32_t start = pass == 0 ? o.wide_blocks_per_cu : pass == 1 ? o.lane_waves_per_cu : o.level_stage;
+    // coordinate descent over the four shapes; a change must win by 1%
+    const int32_t wide_c[] = {2, 3, 4, 6}, lane_c[] = {4, 8, 12}, stage_c[] = {2, 4, 8}, graph_c[] = {0, 8};
+    for (int pass = 0; pass < 4; ++pass) {
+        const int32_t *cand = pass == 0 ? wide_c : pass == 1 ? lane_c : pass == 2 ? stage_c : graph_c;
+        const int nc = pass == 0 ? 4 : pass == 3 ? 2 : 3;
+        const int32_t start = pass == 0   ? o.wide_blocks_per_cu
+                              : pass == 1 ? o.lane_waves_per_cu
+                              : pass == 2 ? o.level_stage
+                                          : o.level_graph;
         for (int i = 0; i < nc; ++i) {
             if (cand[i] == start) continue;  // timed already
             alae_search_opts c = o;
-            int32_t &field = pass == 0 ? c.wide_blocks_per_cu : pass == 1 ? c.lane_waves_per_cu : c.level_stage;
+            int32_t &field = pass == 0   ? c.wide_blocks_per_cu
+                             : pass == 1 ? c.lane_waves_per_cu
+                             : pass == 2 ? c.level_stage
+                                         : c.level_graph;
             field = cand[i];
             double ms = 0.0;
             if ((st = timed(c, &ms)) != ALAE_OK) return st;
@@ -2258,6 +2265,7 @@ alae_status alae_autotune(alae_workspace *ws, const uint8_t *d_query_codes, size
     opts->level_stage = o.level_stage;
     opts->wide_blocks_per_cu = o.wide_blocks_per_cu;
     opts->lane_waves_per_cu = o.lane_waves_per_cu;
+    opts->level_graph = o.level_graph;
     return ALAE_OK;
 }
 
