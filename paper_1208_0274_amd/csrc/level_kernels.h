@@ -254,8 +254,9 @@ __device__ inline void expand_child_tile(const SearchArgs &a, const Entry *ent, 
 // the tasks.  Seven blocks per CU: the four-entry stage leaves LDS for seven,
 // and the row update fits the 72 registers that allows without spilling (the
 // waves wait on dependent reads most of the time; the seventh hides more).
+// The eight-entry stage leaves LDS for three.
 template <int STAGE, bool STRIDE>
-__global__ void __launch_bounds__(kLevelBlock, 7) k_expand_children(SearchArgs a, const Entry *ent,
+__global__ void __launch_bounds__(kLevelBlock, STAGE == 8 ? 3 : 7) k_expand_children(SearchArgs a, const Entry *ent,
                                                                  const ChildTask *tasks, int32_t d1, LevelOut o,
                                                                  Caps caps, Counters *cnt, const LevelCtl *ctl) {
     __shared__ uint32_t s_stage[kLevelBlock * stage_words(STAGE)];
