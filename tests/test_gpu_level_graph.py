@@ -126,3 +126,50 @@ def test_level_graph_option_range():
     idx = alae.Index.build(T, "dna")
     with pytest.raises(alae.AlaeError):
         alae.search(idx, P, 14, alae.make_scoring(*SCHEME), level_graph=65)
+
+
+def test_level_graph_protein_matrix_mode():
+    """20 letters, a substitution matrix (seeds at depth 1): device-driven levels
+    against the oracle."""
+    rng = np.random.default_rng(14)
+    a = rng.integers(-4, 3, size=(20, 20))
+    a = np.triu(a) + np.triu(a, 1).T
+    np.fill_diagonal(a, rng.integers(4, 12, size=20))
+    T = rng.integers(0, 20, size=40_000).astype(np.uint8)
+    P = rng.integers(0, 20, size=250).astype(np.uint8)
+    synth.plant_segments(rng, T, [P[20:140], P[100:220]], 20, 0.3, 0.03)
+    idx = alae.Index.build(T, "protein")
+    sc = alae.make_scoring(0, 0, -11, -1, a)
+    exp = oracle.sw_hits(T, P, np.asarray(a, dtype=np.int32), -11, -1, 40, threads=8)
+    st = alae.Stats()
+    got = alae.search(idx, P, 40, sc, stats=st, level_graph=4)
+    print(f"hits {exp[0].shape[0]} levels {st.levels} device-driven {st.device_levels} "
+          f"captures {st.graph_captures}", flush=True)
+    assert exp[0].shape[0] > 0
+    assert st.device_levels > 0
+    assert_same(got, exp)
+
+
+def test_level_graph_ignored_without_allocation():
+    """The entry point that allocates nothing runs the host-driven loop whatever
+    level_graph says (its buffers are cut from a fixed array): same hits."""
+    import torch
+
+    T, P = planted(15, 30_000, 200, n_plants=3)
+    idx = alae.Index.build(T, "dna")
+    idx.upload()
+    sc = alae.make_scoring(*SCHEME)
+    exp = oracle_hits(T, P, SCHEME, 14)
+    dq = torch.from_numpy(P).cuda()
+    cap = exp[0].shape[0] + 4096
+    keys = torch.full((cap,), -1, dtype=torch.int64, device="cuda")
+    scores = torch.full((cap,), -1, dtype=torch.int32, device="cuda")
+    st = alae.Stats()
+    n = alae.search_device_noalloc(idx, dq, 14, keys, scores, sc, stats=st, level_graph=8)
+    torch.cuda.synchronize()
+    k = keys[:n].cpu().numpy().view(np.uint64)
+    got = ((k >> np.uint64(32)).astype(np.int64), (k & np.uint64(0xFFFFFFFF)).astype(np.int64),
+           scores[:n].cpu().numpy().astype(np.int64))
+    print(f"noalloc with level_graph=8: {n} hits, device-driven levels {st.device_levels}", flush=True)
+    assert st.device_levels == 0
+    assert_same(got, exp)
