@@ -173,3 +173,30 @@ def test_level_graph_ignored_without_allocation():
     print(f"noalloc with level_graph=8: {n} hits, device-driven levels {st.device_levels}", flush=True)
     assert st.device_levels == 0
     assert_same(got, exp)
+
+
+def test_level_graph_modes_alternate_on_one_workspace():
+    """One workspace, queries of two lengths and the three modes in turn (graph,
+    host-driven, enqueued, graph again): graphs captured for one query are not
+    replayed for another, and every result equals the oracle's."""
+    import torch
+
+    T, P = planted(16, 100_000, 600)
+    idx = alae.Index.build(T, "dna")
+    sc = alae.make_scoring(*SCHEME)
+    ws = alae.Workspace(idx)
+    cases = [(P, 8), (P[:350], 8), (P, 0), (P[:350], -4), (P, 8), (P[:350], 8)]
+    want = {}
+    for q, K in cases:
+        m = q.shape[0]
+        if m not in want:
+            e = oracle_hits(T, q, SCHEME, 15)
+            want[m] = ((e[0].astype(np.int64) << 32) | e[1].astype(np.int64), e[2].astype(np.int64))
+        st = alae.Stats()
+        n = ws.search_device(torch.from_numpy(np.ascontiguousarray(q)).cuda(), 15, sc, stats=st, tail_split=False,
+                             level_graph=K)
+        k, s = ws.result_torch()
+        torch.cuda.synchronize()
+        print(f"m={m} K={K}: {n} hits, device-driven {st.device_levels}, captures {st.graph_captures}", flush=True)
+        assert (st.device_levels > 0) == (K != 0)
+        assert_same((k.cpu().numpy().astype(np.int64), s.cpu().numpy().astype(np.int64)), want[m], f"m={m} K={K}")
