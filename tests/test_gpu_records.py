@@ -89,7 +89,8 @@ def test_dna_records_match_per_record_oracle(seed, scheme, H):
     st = alae.Stats()
     got = alae.search(idx, P, H, alae.make_scoring(*scheme), stats=st)
     assert_same(got, exp, f"seed {seed}")
-    for opt in (dict(use_domination=False), dict(tail_split=False)):
+    for opt in (dict(use_domination=False), dict(tail_split=False), dict(level_graph=8),
+                dict(level_graph=3, tail_split=False)):
         assert_same(alae.search(idx, P, H, alae.make_scoring(*scheme), **opt), exp, str(opt))
     # every hit maps inside one record
     for t in got[1][:: max(1, got[1].shape[0] // 50)]:
