@@ -411,6 +411,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="only the headline and its to-host timing")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--level-graph-only", action="store_true",
+                    help="only the short-query leg with host- and device-driven levels, on the 1e9-base index "
+                         "(to profile it alone)")
     ap.add_argument("--long-query-only", action="store_true",
                     help="only the DNA long-query leg's searches, without its filtering, tuning and scheduling "
                          "extras (to profile it alone)")
@@ -424,6 +427,17 @@ def main():
 
     from paper_1208_0274_amd import alae
 
+    if args.level_graph_only:
+        from paper_1208_0274_amd import synth
+
+        w = synth.batched_dna()
+        idx = alae.Index.build(w["text"], "dna")
+        ws = alae.Workspace(idx)
+        out = level_graph_leg(alae, torch, ws, int(w["H"]), alae.make_scoring(w["sa"], w["sb"], w["sg"], w["ss"]))
+        ws.free()
+        idx.free()
+        print(json.dumps({"level_graph": out}), flush=True)
+        return
     if args.long_query_only:
         args.no_extras = True
         print(json.dumps({"dna_long_query": long_query_leg(alae, torch, args)}), flush=True)
