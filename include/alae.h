@@ -203,13 +203,14 @@ typedef struct {
        (a longer query alone), one trie traversal per group; 0 = 2^19 */
     uint64_t batch_columns;
     /* device-driven levels: K in 1..64 runs the level loop in batches of K level slots with no
-       host round trip between levels, each batch a HIP graph captured once per buffer layout
-       and start parity (kept in the workspace) and replayed; -K enqueues the same batches
-       kernel by kernel (no graph).  Grids are sized for the buffers' capacities and the
-       kernels read the level's sizes and depth from device memory; a level that overflows a
-       buffer and the hand-over of the frontier's tail go back to the host.  0 (default): one
-       host round trip a level.  The hit set is the same either way.  Not in the entry point
-       that allocates nothing (there it is ignored). */
+       host round trip between levels while the frontier holds at most 2^18 nodes, each batch
+       a HIP graph captured once per buffer layout and start parity (kept in the workspace)
+       and replayed; -K enqueues the same batches kernel by kernel (no graph).  Grids are
+       sized for such a frontier and the kernels read the level's sizes and depth from device
+       memory; a level that overflows a buffer, a larger frontier and the hand-over of the
+       frontier's tail go back to the host.  0 (default): one host round trip a level.  The
+       hit set is the same either way.  Not in the entry point that allocates nothing (there
+       it is ignored). */
     int32_t level_graph;
 } alae_search_opts;
 

@@ -244,7 +244,7 @@ enum : uint32_t { kStopNone = 0, kStopDone = 1, kStopSplit = 2, kStopOverflow = 
 // Device-driven levels take frontiers of at most this many nodes (their grids
 // are sized for it; a larger level goes back to the host-driven loop, whose
 // per-level round trip is small beside its kernels).
-constexpr unsigned long long kDeviceFrontier = 1ull << 16;
+constexpr unsigned long long kDeviceFrontier = 1ull << 18;
 struct LevelCtl {
     unsigned long long nn, nlw;   // nodes (lane rows, long rows) of the level being expanded
     unsigned long long peak;      // largest frontier seen (nodes of a level)
